@@ -1,0 +1,163 @@
+"""Oracle: non-nested Galerkin multigrid V-cycle and MG-preconditioned CG.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Setup (Sec. 2, Sec. 4.4, Sec. 5): for each level l (0 = finest) the DOF map of
+its mesh, the cell quality and local-correction patches of its mesh, the
+operator (assembled on level 0, A_(l+1) = P_l^T A_l P_l below), D_l = diag(A_l),
+the Chebyshev interval from the (adjusted) largest eigenvalue, and on the
+coarsest level a Cholesky factorisation (direct solver).
+
+V-cycle (Algorithm "alg:mg", correction scheme): pre-smooth nu times, restrict
+the residual b_c = P^T (b - A u), solve the coarse problem for a correction
+starting from zero, add P u_c, post-smooth nu times.  The printed algorithm
+initialises the coarse unknown with P^T u; since the coarse right-hand side is a
+residual, the coarse unknown is a correction, and the reading used is u_c = 0.
+One "smoother application" is one combined S_c -> S_g -> S_c sandwich; S_g is a
+Chebyshev polynomial of degree cheb_degree.
+
+PCG (Sec. 6.2: one V-cycle per CG iteration) with x_0 = 0 and the stopping rule
+||b - A x||_2 <= rtol ||b||_2 on the recursively updated residual (Sec. 6 intro);
+the iteration count is the number of products with A.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .fem import DofMap, assemble
+from .patches import MERGE, colour, patches
+from .quality import radius_ratio
+from .smoothers import LocalCorrection, lanczos_lmax, sandwich
+from .transfer import galerkin, prolongation
+
+
+@dataclass
+class Options:
+    degree: int = 1
+    nu: int = 2
+    cheb_degree: int = 2
+    cheb_lo_frac: float = 0.1
+    local_correction: bool = True
+    adjusted_eig: bool = True
+    patch_policy: int = MERGE
+    eig_tol: float = 1e-8
+    eig_maxit: int = 200
+
+
+@dataclass
+class Level:
+    dofmap: DofMap
+    A: sp.csr_matrix
+    dinv: np.ndarray
+    gamma: np.ndarray
+    patch_cells: list
+    patch_dofs: list
+    colours: np.ndarray
+    lam: float = 0.0
+    lam_adj: float = 0.0
+    lo: float = 0.0
+    hi: float = 0.0
+    local: LocalCorrection | None = None
+    P: sp.csr_matrix | None = None            # to the next coarser level
+    locate_cell: np.ndarray | None = None     # coarse cell of each free DOF node
+    chol: tuple | None = None                 # coarsest only
+    Mf: sp.csr_matrix | None = None           # level 0 only: b = Mf f_hat
+    extra: dict = field(default_factory=dict)
+
+
+class Hierarchy:
+    def __init__(self, meshes: list, tau: float = 0.1, layers: int = 1,
+                 opts: Options | None = None):
+        self.opts = opts = opts or Options()
+        self.levels: list[Level] = []
+        nlev = len(meshes)
+        dms = [DofMap(m, opts.degree) for m in meshes]
+        A = None
+        for l, (mesh, dm) in enumerate(zip(meshes, dms)):
+            Mf = None
+            if l == 0:
+                _, A, Mf = assemble(mesh, opts.degree)
+            gamma = radius_ratio(mesh["coords"], mesh["cells"])
+            pc, pd = patches(dm.cells, dm.coords.shape[0], gamma, tau, layers,
+                             opts.patch_policy, dm.cell_dofs, dm.free_index)
+            cols = colour(pd)
+            lev = Level(dofmap=dm, A=A, dinv=1.0 / A.diagonal(), gamma=gamma,
+                        patch_cells=pc, patch_dofs=pd, colours=cols, Mf=Mf)
+            if l < nlev - 1:
+                lev.P, lev.locate_cell = prolongation(dm, dms[l + 1])
+                A = galerkin(A, lev.P)
+            self.levels.append(lev)
+        for l, lev in enumerate(self.levels):
+            if l == nlev - 1:
+                lev.chol = sla.cho_factor(lev.A.toarray(), lower=True)
+                continue
+            lev.lam, _ = lanczos_lmax(lev.A, None, opts.eig_tol, opts.eig_maxit)
+            use_local = opts.local_correction and len(lev.patch_dofs) > 0
+            if use_local:
+                g = np.ones(lev.A.shape[0], dtype=bool)
+                for B in lev.patch_dofs:
+                    g[B] = False
+                lev.lam_adj, _ = lanczos_lmax(lev.A, g, opts.eig_tol, opts.eig_maxit)
+                lev.local = LocalCorrection(lev.A, lev.patch_dofs, lev.colours)
+            else:
+                lev.lam_adj = lev.lam
+            lev.hi = lev.lam_adj if (use_local and opts.adjusted_eig) else lev.lam
+            lev.lo = opts.cheb_lo_frac * lev.hi
+
+    # -- the method --------------------------------------------------------
+    def smooth(self, l: int, b: np.ndarray, u: np.ndarray, nu: int) -> np.ndarray:
+        lev = self.levels[l]
+        for _ in range(nu):
+            u = sandwich(lev.A, lev.dinv, b, u, lev.local, self.opts.cheb_degree,
+                         lev.lo, lev.hi)
+        return u
+
+    def vcycle(self, b: np.ndarray, u: np.ndarray | None = None, l: int = 0) -> np.ndarray:
+        lev = self.levels[l]
+        if u is None:
+            u = np.zeros_like(b)
+        if l == len(self.levels) - 1:
+            return u + sla.cho_solve(lev.chol, b - lev.A @ u)
+        u = self.smooth(l, b, u, self.opts.nu)
+        bc = lev.P.T @ (b - lev.A @ u)
+        uc = self.vcycle(bc, None, l + 1)
+        u = u + lev.P @ uc
+        return self.smooth(l, b, u, self.opts.nu)
+
+    def pcg(self, b: np.ndarray, rtol: float, maxit: int, x0: np.ndarray | None = None):
+        """Returns (x, iterations, converged, history of ||r||/||b||)."""
+        A = self.levels[0].A
+        x = np.zeros_like(b) if x0 is None else x0.copy()
+        r = b - A @ x
+        bnorm = float(np.linalg.norm(b))
+        hist = [float(np.linalg.norm(r)) / bnorm if bnorm > 0 else 0.0]
+        if bnorm == 0.0:
+            return np.zeros_like(b), 0, True, hist
+        if hist[0] <= rtol:
+            return x, 0, True, hist
+        z = self.vcycle(r)
+        p = z.copy()
+        rho = float(r @ z)
+        it = 0
+        while it < maxit:
+            q = A @ p
+            it += 1
+            alpha = rho / float(p @ q)
+            x = x + alpha * p
+            r = r - alpha * q
+            rel = float(np.linalg.norm(r)) / bnorm
+            hist.append(rel)
+            if rel <= rtol:
+                return x, it, True, hist
+            z = self.vcycle(r)
+            rho_new = float(r @ z)
+            p = z + (rho_new / rho) * p
+            rho = rho_new
+        return x, it, False, hist
+
+    def rhs_from_nodal(self, f_nodal: np.ndarray) -> np.ndarray:
+        return self.levels[0].Mf @ f_nodal

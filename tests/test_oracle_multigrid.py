@@ -1,0 +1,125 @@
+"""Pins of the oracle's V-cycle (Algorithm alg:mg) and MG-preconditioned CG
+(Sec. 6.2): brute-force dense multigrid operators on tiny meshes, exact
+coarse solves, and the paper's qualitative claims on iteration counts."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import meshgen
+import oracle
+from oracle.multigrid import Hierarchy, Options
+
+
+def _tiny_hierarchy(degree=1, sides=(8, 4), nu=2, k=2, local=True, seed=0, n_single=2):
+    meshes = [meshgen.square_mesh(sides[0], seed, n_single=n_single, single_depth=1e-3)]
+    meshes += [meshgen.square_mesh(s, seed + 10 + i) for i, s in enumerate(sides[1:])]
+    return Hierarchy(meshes, tau=0.1, layers=1,
+                     opts=Options(degree=degree, nu=nu, cheb_degree=k, local_correction=local))
+
+
+def _dense_smoother(H, l):
+    lev = H.levels[l]
+    n = lev.A.shape[0]
+    return np.stack([H.smooth(l, e, np.zeros(n), 1) for e in np.eye(n)], axis=1)
+
+
+def _dense_B(H, l):
+    """Brute-force V-cycle operator B_l (u = B_l b from u = 0):
+    E_l = (I - S A)^nu (I - P B_(l+1) P^T A) (I - S A)^nu,  B_l = (I - E_l) A^-1."""
+    lev = H.levels[l]
+    Ad = lev.A.toarray()
+    if l == len(H.levels) - 1:
+        return np.linalg.inv(Ad)
+    n = Ad.shape[0]
+    S = _dense_smoother(H, l)
+    I = np.eye(n)
+    P = lev.P.toarray()
+    Esm = np.linalg.matrix_power(I - S @ Ad, H.opts.nu)
+    E = Esm @ (I - P @ _dense_B(H, l + 1) @ P.T @ Ad) @ Esm
+    return (I - E) @ np.linalg.inv(Ad)
+
+
+@pytest.mark.parametrize("sides,degree", [((8, 4), 1), ((6, 3), 2), ((10, 5, 3), 1)])
+def test_vcycle_equals_brute_force_operator(sides, degree):
+    H = _tiny_hierarchy(degree=degree, sides=sides)
+    n = H.levels[0].A.shape[0]
+    V = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+    B = _dense_B(H, 0)
+    assert np.allclose(V, B, atol=1e-9 * np.abs(B).max())
+    # symmetric positive definite preconditioner
+    assert np.allclose(V, V.T, atol=1e-9 * np.abs(V).max())
+    assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+
+
+def test_vcycle_with_nonzero_initial_guess_is_affine():
+    H = _tiny_hierarchy(sides=(8, 4))
+    n = H.levels[0].A.shape[0]
+    rng = np.random.default_rng(2)
+    b, u = rng.normal(size=n), rng.normal(size=n)
+    B = _dense_B(H, 0)
+    A = H.levels[0].A
+    assert np.allclose(H.vcycle(b, u), u + B @ (b - A @ u), atol=1e-10)
+
+
+def test_galerkin_coarse_operator_in_hierarchy():
+    H = _tiny_hierarchy(sides=(8, 4))
+    l0, l1 = H.levels
+    want = (l0.P.T @ l0.A @ l0.P).toarray()
+    assert np.allclose(l1.A.toarray(), want, atol=1e-14)
+
+
+def test_single_level_pcg_converges_in_one_iteration():
+    mesh = meshgen.square_mesh(6, 0)
+    H = Hierarchy([mesh], opts=Options(degree=2))
+    b = meshgen.random_rhs(H.levels[0].A.shape[0], 0)
+    x, it, conv, _ = H.pcg(b, 1e-12, 10)
+    assert conv and it == 1
+    assert np.allclose(x, spla.spsolve(H.levels[0].A.tocsc(), b), rtol=1e-10)
+
+
+def test_pcg_solution_matches_direct_solve():
+    H = _tiny_hierarchy(degree=2, sides=(10, 5))
+    A = H.levels[0].A
+    b = meshgen.random_rhs(A.shape[0], 3)
+    x, it, conv, hist = H.pcg(b, 1e-12, 100)
+    assert conv
+    assert np.linalg.norm(b - A @ x) <= 1.01e-12 * np.linalg.norm(b)
+    assert np.allclose(x, spla.spsolve(A.tocsc(), b), rtol=1e-8, atol=1e-12)
+    assert all(h2 < 10 * h1 for h1, h2 in zip(hist, hist[1:]))
+
+
+def test_pcg_zero_rhs():
+    H = _tiny_hierarchy(sides=(6, 3))
+    n = H.levels[0].A.shape[0]
+    x, it, conv, _ = H.pcg(np.zeros(n), 1e-10, 10)
+    assert conv and it == 0 and np.all(x == 0)
+
+
+def test_rhs_from_nodal_is_mass_times_nodal_values():
+    mesh = meshgen.square_mesh(6, 0, dirichlet=("y0", "y1"))
+    H = Hierarchy([mesh], opts=Options(degree=2))
+    dm = H.levels[0].dofmap
+    f = np.ones(dm.n_dofs)
+    b = H.rhs_from_nodal(f)
+    # sum over free rows of int phi_i = area minus the Dirichlet share
+    _, _, M = oracle.assemble_full(mesh, 2)
+    assert np.allclose(b, (M @ f)[dm.free])
+
+
+def test_global_local_recovers_reference_iterations():
+    """Table number_struct / Sec. 6: with the local correction and adjusted
+    eigenvalue, CG iterations return to the high-quality reference count
+    (within one), while the plain smoother needs many more."""
+    low = meshgen.hierarchy("square_p1_4k", seed=0)
+    ref = meshgen.hierarchy("square_p1_4k", seed=0, case="ref")
+    its = {}
+    for name, meshes, local in (("gl", low, True), ("plain", low, False), ("ref", ref, True)):
+        H = Hierarchy(meshes, tau=0.1, layers=2,
+                      opts=Options(degree=1, local_correction=local, adjusted_eig=local))
+        b = meshgen.random_rhs(H.levels[0].A.shape[0], 1)
+        _, it, conv, _ = H.pcg(b, 1e-10, 200)
+        assert conv
+        its[name] = it
+    assert abs(its["gl"] - its["ref"]) <= 1
+    assert its["plain"] >= its["gl"] + 4
