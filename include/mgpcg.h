@@ -1,0 +1,209 @@
+/*
+ * mgpcg.h - C ABI of the MI355X (gfx950) global-local multigrid library.
+ *
+ * The library solves the reduced finite-element Poisson system A u = b of
+ * continuous Lagrange P1/P2 (2D, 3D) or P3 (2D) elements on a simplicial mesh
+ * (Chen & Wells, arXiv 2402.12947, Sec. 2, eq. system_finest; Sec. 6.1) with
+ * conjugate gradients preconditioned by one non-nested geometric Galerkin
+ * multigrid V-cycle per iteration (Algorithm alg:mg; Sec. 6.2).  The smoother
+ * is the global-local combined smoother of Sec. 4.2: a local residual
+ * correction S_c (exact dense solves on patches around cells whose normalised
+ * radius ratio is below a threshold, Sec. 4.1, Sec. 4.4), a Jacobi-
+ * preconditioned Chebyshev sweep S_g over the whole level with the adjusted
+ * largest eigenvalue of Sec. 5, then S_c again.
+ *
+ * Conventions shared by every entry point
+ *  - Meshes are host arrays owned by the caller; mg_setup copies what it
+ *    needs and keeps no caller pointer.  Cells must be positively oriented.
+ *  - Homogeneous Dirichlet conditions (u = 0) are imposed on the DOFs of
+ *    boundary facets whose vertices are all flagged in dirichlet_vertex; the
+ *    rest of the boundary carries the natural (zero-flux) condition.
+ *  - DOF numbering: vertex DOFs first (id = vertex id), then edge DOFs in the
+ *    order of the sorted (low vertex, high vertex) pairs (P3: two per edge,
+ *    the node nearer the low vertex first), then P3 cell interiors in cell
+ *    order.  Solver vectors (b, u, f) hold the FREE (non-Dirichlet) DOFs of
+ *    level 0 in that order; their length is mg_level_info.n_free.
+ *  - Vectors passed to mg_smooth / mg_vcycle / mg_pcg_solve / mg_rhs_from_nodal
+ *    are DEVICE pointers to FP64 arrays, accessed on the context's stream.
+ *  - Errors: a negative status; mg_last_error(ctx) (or mg_global_error() when
+ *    mg_setup failed and returned no context) holds a message.  A positive
+ *    status is a warning with valid outputs.  Outputs are undefined after an
+ *    error.  A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef MGPCG_H
+#define MGPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_API_VERSION 1
+#define MG_MAX_HISTORY 1024
+
+typedef struct mg_ctx mg_ctx;
+
+typedef enum {
+  MG_OK = 0,
+  MG_NOT_CONVERGED = 1,   /* maxit reached; u holds the last iterate          */
+  MG_ERR_ARG = -1,        /* bad argument (NULL, size, aliasing, option)        */
+  MG_ERR_MESH = -2,       /* index out of range or non-positive cell volume     */
+  MG_ERR_LOCATE = -3,     /* a fine DOF node lies outside the next coarser mesh */
+  MG_ERR_NOT_SPD = -4,    /* non-positive pivot / diagonal: system not SPD      */
+  MG_ERR_BREAKDOWN = -5,  /* CG breakdown: p.Ap <= 0 or a non-finite value      */
+  MG_ERR_HIP = -6,        /* a HIP runtime call failed                          */
+  MG_ERR_OOM = -7,        /* device allocation failed                           */
+  MG_ERR_LIMIT = -8       /* a documented size limit was exceeded               */
+} mg_status;
+
+enum { MG_FP64 = 0, MG_MIXED = 1 };
+enum { MG_PATCH_MERGE = 0, MG_PATCH_OVERLAP = 1 };
+
+/* One level of the hierarchy: an independent simplicial mesh of the domain. */
+typedef struct {
+  int32_t dim;                      /* 2 or 3                                  */
+  int64_t n_vertices;
+  const double *coords;             /* host [n_vertices * dim]                 */
+  int64_t n_cells;
+  const int32_t *cells;             /* host [n_cells * (dim + 1)], vertex ids  */
+  const uint8_t *dirichlet_vertex;  /* host [n_vertices], 1 = on Gamma_D       */
+} mg_mesh;
+
+/* Solver options; mg_default_options fills the paper's values. */
+typedef struct {
+  int32_t degree;           /* Lagrange degree 1, 2 or 3 (3: dim 2 only)       */
+  int32_t precision;        /* MG_FP64, or MG_MIXED: FP32 V-cycle (smoothers,
+                               transfers, patch solves) inside FP64 CG; the
+                               coarsest solve stays FP64                       */
+  int32_t nu;               /* smoother applications pre and post (Sec. 6: 2)  */
+  int32_t cheb_degree;      /* Chebyshev polynomial degree per S_g (2)         */
+  double cheb_lo_frac;      /* lower bound = frac * upper (Sec. 3.2: 0.1)      */
+  int32_t local_correction; /* 1: S_c -> S_g -> S_c; 0: S_g only               */
+  int32_t adjusted_eig;     /* 1: Chebyshev upper bound = adjusted lambda_max
+                               (Sec. 5); 0: lambda_max of D^-1 A               */
+  int32_t patch_policy;     /* MG_PATCH_MERGE (disjoint subdomains, one colour)
+                               or MG_PATCH_OVERLAP (coloured, sequential)     */
+  double eig_tol;           /* Lanczos Ritz-residual tolerance (1e-8)          */
+  int32_t eig_maxit;        /* Lanczos step limit (200)                        */
+  int32_t use_graph;        /* 1: replay the V-cycle from a captured hipGraph  */
+  int32_t sell_sigma;       /* SELL row-sorting window: 0 = autotune, 1 = off,
+                               else a multiple of 64                          */
+  void *stream;             /* hipStream_t to run on; NULL = library-owned     */
+} mg_options;
+
+typedef struct {
+  int32_t iterations;       /* number of products with A (Sec. 6 stopping)     */
+  int32_t converged;
+  double rel_residual;      /* ||r||/||b|| of the recursively updated residual */
+  double true_rel_residual; /* ||b - A u||/||b|| recomputed at exit, FP64      */
+  double solve_ms;          /* wall time of the solve on the stream            */
+  int32_t n_history;
+  double history[MG_MAX_HISTORY]; /* rel. residual after each iteration, [0]=1 */
+} mg_solve_stats;
+
+typedef struct {
+  int64_t n_vertices, n_cells;
+  int64_t n_dofs;           /* all DOFs of the level's mesh                    */
+  int64_t n_free;           /* unknowns of the level's operator                */
+  int64_t nnz;              /* nonzeros of A_l (CSR)                           */
+  int64_t n_flagged;        /* cells with gamma < threshold                    */
+  int32_t n_patches, n_colours, max_patch;
+  int64_t sum_patch_dofs;
+  double gamma_min;
+  double lambda_max;        /* lambda_max(D^-1 A_l) (Lanczos)                  */
+  double lambda_adj;        /* adjusted lambda_max (Sec. 5)                    */
+  double cheb_lo, cheb_hi;  /* Chebyshev interval used                         */
+  int32_t lanczos_steps, lanczos_steps_adj;
+  int32_t sell_sigma;       /* SELL sorting window chosen                      */
+  int64_t sell_stored;      /* stored SELL entries incl. padding               */
+  int32_t is_coarsest;
+  double setup_ms;          /* setup time spent on this level                  */
+} mg_level_info;
+
+/* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
+enum {
+  MG_ARR_QUALITY = 1,      /* double  [n_cells]  normalised radius ratio        */
+  MG_ARR_FLAGS = 2,        /* uint8   [n_cells]  gamma < threshold              */
+  MG_ARR_PATCH_PTR = 3,    /* int32   [n_patches + 1]                           */
+  MG_ARR_PATCH_DOFS = 4,   /* int32   [sum_patch_dofs] free DOF ids, ascending  */
+  MG_ARR_PATCH_COLOUR = 5, /* int32   [n_patches]                               */
+  MG_ARR_LOCATE = 6,       /* int32   [n_free] coarse cell of each free DOF node
+                              (levels above the coarsest)                     */
+  MG_ARR_FREE_DOFS = 7,    /* int32   [n_free] canonical DOF id of each unknown */
+  MG_ARR_DOF_NODES = 8,    /* double  [n_dofs * dim] node coordinates          */
+  MG_ARR_A_ROWPTR = 9,     /* int64   [n_free + 1]                              */
+  MG_ARR_A_COLS = 10,      /* int32   [nnz]                                     */
+  MG_ARR_A_VALS = 11,      /* double  [nnz]                                     */
+  MG_ARR_P_COLS = 12,      /* int32   [n_free * width] (row-major, -1 = none)   */
+  MG_ARR_P_VALS = 13,      /* double  [n_free * width]                          */
+  MG_ARR_CELL_DOFS = 14,   /* int32   [n_cells * n_local] canonical DOF ids     */
+  MG_ARR_P_WIDTH = 15      /* int32   [1] coarse DOFs per cell (ELL width)      */
+};
+
+/* Fills *opt with: degree 1, MG_FP64, nu 2, cheb_degree 2, cheb_lo_frac 0.1,
+ * local_correction 1, adjusted_eig 1, MG_PATCH_MERGE, eig_tol 1e-8,
+ * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL. */
+void mg_default_options(mg_options *opt);
+
+/* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,
+ * cell quality gamma (Sec. 3 eq. radius_ratio, read as d R_I / R_C), the
+ * local-correction patches (cells with gamma < quality_threshold grown by
+ * patch_layers vertex layers), the fine-level assembly, the interpolation
+ * prolongation by point location and the Galerkin operators
+ * A_(l+1) = P_l^T A_l P_l, the patch factorisations, the (adjusted) largest
+ * eigenvalues and, on the coarsest level, a dense Cholesky factorisation.
+ * levels[0] is the finest mesh.  On success *out owns all device memory it
+ * allocated until mg_destroy.  On failure *out = NULL and nothing leaks.
+ * Errors: MG_ERR_ARG, MG_ERR_MESH, MG_ERR_LOCATE, MG_ERR_NOT_SPD, MG_ERR_HIP,
+ * MG_ERR_OOM, MG_ERR_LIMIT. */
+mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_threshold,
+                   int32_t patch_layers, const mg_options *opt, mg_ctx **out);
+
+/* u <- S^nu(A_l, b, u) (Sec. 2 smoother notation): nu applications of the
+ * combined smoother S_c -> S_g -> S_c (Sec. 4.2) on level `level`, in the
+ * context's precision.  b, u: device FP64 vectors of the level's n_free;
+ * b must not alias u.  Not available on the coarsest level. */
+mg_status mg_smooth(mg_ctx *c, int32_t level, const double *b, double *u, int32_t nu);
+
+/* u <- Vcycle(A_0, b, u) (Algorithm alg:mg) on level 0 from the given u. */
+mg_status mg_vcycle(mg_ctx *c, const double *b, double *u);
+
+/* CG on A_0 u = b preconditioned by one V-cycle per iteration (Sec. 6.2),
+ * from u = 0, stopping when ||b - A u||_2 <= rtol ||b||_2 (Sec. 6) on the
+ * recursively updated residual.  st may be NULL.  Returns MG_NOT_CONVERGED if
+ * maxit iterations were not enough (u holds the last iterate), or
+ * MG_ERR_BREAKDOWN. */
+mg_status mg_pcg_solve(mg_ctx *c, const double *b, double *u, double rtol, int32_t maxit,
+                       mg_solve_stats *st);
+
+/* b = M f_hat restricted to the free DOFs: the consistent-mass load of nodal
+ * data f_hat given at ALL n_dofs DOFs of level 0 (device FP64). */
+mg_status mg_rhs_from_nodal(mg_ctx *c, const double *f_nodal, double *b);
+
+mg_status mg_get_level_info(const mg_ctx *c, int32_t level, mg_level_info *out);
+
+/* Copies array `what` (MG_ARR_*) of `level` to the host buffer `out`, which
+ * must be large enough (sizes above, from mg_get_level_info). */
+mg_status mg_get_array(const mg_ctx *c, int32_t level, int32_t what, void *out);
+
+/* Device-event timing of the level-0 Chebyshev step kernel: when enabled,
+ * every launch of that kernel on the context's stream is bracketed by HIP
+ * events; mg_kernel_time returns the number of launches since enabling and
+ * their summed duration in milliseconds (synchronises the stream). */
+mg_status mg_enable_kernel_timing(mg_ctx *c, int32_t enable);
+mg_status mg_kernel_time(mg_ctx *c, int64_t *launches, double *total_ms);
+
+/* Bytes one launch of the level-0 Chebyshev step kernel must move at least:
+ * matrix values and column indices once, and the level vectors it reads and
+ * writes (12 nnz + 48 n in FP64, 8 nnz + 24 n in FP32 mixed mode). */
+mg_status mg_cheb_algorithmic_bytes(const mg_ctx *c, double *bytes);
+
+const char *mg_last_error(const mg_ctx *c);
+const char *mg_global_error(void);
+void mg_destroy(mg_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGPCG_H */

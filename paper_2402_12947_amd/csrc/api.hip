@@ -1,0 +1,616 @@
+// C entry points: setup of the hierarchy, the combined smoother, the V-cycle
+// and multigrid-preconditioned CG (paper Sec. 2 Algorithm alg:mg, Sec. 4.2,
+// Sec. 6.2).  Host code here only orchestrates: every numerical step of the
+// solve phase is one of the HIP kernels of solve.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "mg_internal.h"
+
+namespace mg {
+
+void fail(mg_status code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Error{code, std::string(buf)};
+}
+
+Ctx::~Ctx() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  for (auto &e : events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (h_scal) (void)hipHostFree(h_scal);
+  lv.clear();
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+enum { W_B = 0, W_U = 1, W_ALT = 2, W_D = 3, W_R = 4, W_T = 5 };
+
+template <class T>
+struct LV;
+template <>
+struct LV<double> {
+  static double *w(Level &L, int k) { return L.w64[k].p; }
+  static double *res(Level &L) { return L.res64.p; }
+  static const double *dinv(Level &L) { return L.dinv64.p; }
+};
+template <>
+struct LV<float> {
+  static float *w(Level &L, int k) { return L.w32[k].p; }
+  static float *res(Level &L) { return L.res32.p; }
+  static const float *dinv(Level &L) { return L.dinv32.p; }
+};
+
+void ensure_work(Ctx &c, Level &L) {
+  bool mixed = c.opt.precision == MG_MIXED;
+  for (int k = 0; k < 6; ++k) {
+    if (mixed) L.w32[k].alloc(L.nfree); else L.w64[k].alloc(L.nfree);
+  }
+  if (L.patch.total > 0) {
+    if (mixed) L.res32.alloc(L.patch.total); else L.res64.alloc(L.patch.total);
+  }
+  if (L.coarsest) L.cpart.alloc(dense_part_size(L.nfree));
+}
+
+// ---------------------------------------------------------------------------
+// smoother and V-cycle
+// ---------------------------------------------------------------------------
+static void time_begin(Ctx &c, int l) {
+  if (!c.timing || l != 0) return;
+  if (c.events_used == c.events.size()) {
+    hipEvent_t a, b;
+    MG_HIP(hipEventCreate(&a));
+    MG_HIP(hipEventCreate(&b));
+    c.events.push_back({a, b});
+  }
+  MG_HIP(hipEventRecord(c.events[c.events_used].first, c.stream));
+}
+static void time_end(Ctx &c, int l) {
+  if (!c.timing || l != 0) return;
+  MG_HIP(hipEventRecord(c.events[c.events_used].second, c.stream));
+  ++c.events_used;
+}
+
+template <class T>
+static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending) {
+  for (int k = 0; k < L.patch.ncolour; ++k) {
+    int col = descending ? L.patch.ncolour - 1 - k : k;
+    patch_residual<T>(c.stream, L.S, L.patch, col, b, u, LV<T>::res(L));
+    patch_apply<T>(c.stream, L.patch, col, LV<T>::res(L), u);
+  }
+}
+
+// k Chebyshev-Jacobi steps (paper Sec. 3.2; see the recurrence in solve.hip)
+template <class T>
+static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt) {
+  Level &L = c.lv[l];
+  const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  T *d = LV<T>::w(L, W_D);
+  time_begin(c, l);
+  cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, 1, 0.0, 1.0 / theta);
+  time_end(c, l);
+  std::swap(u, alt);
+  for (int j = 1; j < c.opt.cheb_degree; ++j) {
+    double rho_new = 1.0 / (2.0 * sigma - rho);
+    time_begin(c, l);
+    cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, 0, rho_new * rho, 2.0 * rho_new / delta);
+    time_end(c, l);
+    std::swap(u, alt);
+    rho = rho_new;
+  }
+}
+
+// u <- S^nu (b, u): nu applications of S_c -> S_g -> S_c (paper Sec. 4.2)
+template <class T>
+static void smooth(Ctx &c, int l, const T *b, T *u, int nu) {
+  Level &L = c.lv[l];
+  bool local = c.opt.local_correction && L.patch.n > 0;
+  T *cur = u, *alt = LV<T>::w(L, W_ALT);
+  if (u == alt) alt = LV<T>::w(L, W_T);
+  for (int s = 0; s < nu; ++s) {
+    if (local) local_correction<T>(c, L, b, cur, false);
+    chebyshev<T>(c, l, b, cur, alt);
+    if (local) local_correction<T>(c, L, b, cur, true);
+  }
+  if (cur != u) convert<T, T>(c.stream, cur, u, L.nfree);
+}
+
+// u = V_l(b) from a zero initial guess (Algorithm alg:mg, correction scheme)
+template <class T>
+static void vcycle_zero(Ctx &c, int l, const T *b, T *u) {
+  Level &L = c.lv[l];
+  if (L.coarsest) {
+    dense_symv<T>(c.stream, L.nfree, L.cinv, b, u, L.cpart);
+    return;
+  }
+  fill<T>(c.stream, u, L.nfree, T(0));
+  smooth<T>(c, l, b, u, c.opt.nu);
+  T *r = LV<T>::w(L, W_R);
+  sell_spmv<T>(c.stream, L.S, u, r, SPMV_RESID, b);
+  Level &C = c.lv[l + 1];
+  sell_spmv<T>(c.stream, L.R, r, LV<T>::w(C, W_B), SPMV_SET, nullptr);
+  vcycle_zero<T>(c, l + 1, LV<T>::w(C, W_B), LV<T>::w(C, W_U));
+  sell_spmv<T>(c.stream, L.P, LV<T>::w(C, W_U), u, SPMV_ADD, nullptr);
+  smooth<T>(c, l, b, u, c.opt.nu);
+}
+
+// z = B r (FP64 in and out); mixed precision runs the cycle in FP32
+static void precondition_eager(Ctx &c, const double *r, double *z) {
+  Level &L0 = c.lv[0];
+  if (c.opt.precision == MG_MIXED) {
+    convert<double, float>(c.stream, r, L0.w32[W_B], L0.nfree);
+    vcycle_zero<float>(c, 0, L0.w32[W_B], L0.w32[W_U]);
+    convert<float, double>(c.stream, L0.w32[W_U], z, L0.nfree);
+  } else {
+    vcycle_zero<double>(c, 0, r, z);
+  }
+}
+
+// the graph replays the cycle on the context's fixed buffers c.r -> c.z
+static void precondition(Ctx &c) {
+  if (c.opt.use_graph && !c.timing) {
+    if (!c.graph_exec) {
+      MG_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+      try {
+        precondition_eager(c, c.r, c.z);
+      } catch (...) {
+        hipGraph_t g;
+        (void)hipStreamEndCapture(c.stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      MG_HIP(hipStreamEndCapture(c.stream, &c.graph));
+      MG_HIP(hipGraphInstantiate(&c.graph_exec, c.graph, nullptr, nullptr, 0));
+    }
+    MG_HIP(hipGraphLaunch(c.graph_exec, c.stream));
+  } else {
+    precondition_eager(c, c.r, c.z);
+  }
+}
+
+static double read_scalar(Ctx &c, const double *d) {
+  double h = 0;
+  MG_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  MG_HIP(hipStreamSynchronize(c.stream));
+  return h;
+}
+
+static void dot_to(Ctx &c, const double *x, const double *y, int64_t n, double *out) {
+  int nb = dot_blocks(n);
+  dot_partials(c.stream, x, y, n, c.partial, nb);
+  finish_sum(c.stream, c.partial, nb, out);
+}
+
+}  // namespace mg
+
+using namespace mg;
+
+static thread_local std::string g_error;
+
+#define MG_API_BEGIN try {
+#define MG_API_END(ctxp)                                        \
+  }                                                             \
+  catch (const Error &e) {                                      \
+    if (ctxp) (ctxp)->err = e.msg; else g_error = e.msg;        \
+    return e.code;                                              \
+  }                                                             \
+  catch (const std::exception &e) {                             \
+    if (ctxp) (ctxp)->err = e.what(); else g_error = e.what();  \
+    return MG_ERR_HIP;                                          \
+  }
+
+struct mg_ctx {
+  Ctx impl;
+};
+
+template <class T>
+static void copy_out(hipStream_t s, const T *d, size_t n, void *out) {
+  if (n == 0) return;
+  if (!d) fail(MG_ERR_ARG, "array not available on this level");
+  MG_HIP(hipMemcpyAsync(out, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+
+extern "C" {
+
+void mg_default_options(mg_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->degree = 1;
+  o->precision = MG_FP64;
+  o->nu = 2;
+  o->cheb_degree = 2;
+  o->cheb_lo_frac = 0.1;
+  o->local_correction = 1;
+  o->adjusted_eig = 1;
+  o->patch_policy = MG_PATCH_MERGE;
+  o->eig_tol = 1e-8;
+  o->eig_maxit = 200;
+  o->use_graph = 0;
+  o->sell_sigma = 0;
+  o->stream = nullptr;
+}
+
+const char *mg_global_error(void) { return g_error.c_str(); }
+
+const char *mg_last_error(const mg_ctx *c) { return c ? c->impl.err.c_str() : g_error.c_str(); }
+
+void mg_destroy(mg_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->impl.stream);
+  delete c;
+}
+
+static void validate_mesh(const mg_mesh &m, int dim, int l) {
+  if (m.dim != dim) fail(MG_ERR_ARG, "level %d: dimension %d differs from level 0 (%d)", l, m.dim, dim);
+  if (!m.coords || !m.cells || !m.dirichlet_vertex) fail(MG_ERR_ARG, "level %d: NULL mesh array", l);
+  if (m.n_vertices < dim + 1 || m.n_cells < 1) fail(MG_ERR_ARG, "level %d: empty mesh", l);
+  if (m.n_vertices > 2000000000LL || m.n_cells > 200000000LL) fail(MG_ERR_LIMIT, "level %d: mesh too large", l);
+  int64_t nidx = m.n_cells * (dim + 1);
+  for (int64_t i = 0; i < nidx; ++i)
+    if (m.cells[i] < 0 || m.cells[i] >= m.n_vertices)
+      fail(MG_ERR_MESH, "level %d: cell %lld has vertex index %d out of range", l, (long long)(i / (dim + 1)),
+           m.cells[i]);
+  for (int64_t i = 0; i < m.n_vertices * dim; ++i)
+    if (!std::isfinite(m.coords[i])) fail(MG_ERR_MESH, "level %d: non-finite coordinate", l);
+}
+
+static int choose_sigma(Ctx &c, const Csr &A) {
+  if (c.opt.sell_sigma >= 1) return c.opt.sell_sigma;
+  // padding of the unsorted layout; sort rows within windows when it is large
+  std::vector<int64_t> rp;
+  download(rp, A.rowptr.p, (size_t)A.nrows + 1, c.stream);
+  int64_t stored = 0;
+  for (int64_t s0 = 0; s0 < A.nrows; s0 += SELL_C) {
+    int64_t w = 0;
+    for (int64_t r = s0; r < std::min(A.nrows, s0 + SELL_C); ++r) w = std::max(w, rp[r + 1] - rp[r]);
+    stored += w * SELL_C;
+  }
+  return (double)stored > 1.08 * (double)A.nnz ? 1024 : 1;
+}
+
+mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_threshold, int32_t patch_layers,
+                   const mg_options *opt, mg_ctx **out) {
+  if (out) *out = nullptr;
+  mg_ctx *h = nullptr;
+  try {
+    if (!levels || n_levels < 1 || !out) fail(MG_ERR_ARG, "levels, n_levels >= 1 and out are required");
+    if (patch_layers < 0 || !(quality_threshold >= 0)) fail(MG_ERR_ARG, "bad quality threshold or patch layers");
+    mg_options o;
+    if (opt) o = *opt; else mg_default_options(&o);
+    int dim = levels[0].dim;
+    if (dim != 2 && dim != 3) fail(MG_ERR_ARG, "dim must be 2 or 3");
+    if (o.degree < 1 || o.degree > 3 || (o.degree == 3 && dim != 2))
+      fail(MG_ERR_ARG, "degree must be 1 or 2 (3 on triangles)");
+    if (o.precision != MG_FP64 && o.precision != MG_MIXED) fail(MG_ERR_ARG, "bad precision");
+    if (o.nu < 0 || o.cheb_degree < 1 || !(o.cheb_lo_frac >= 0 && o.cheb_lo_frac < 1) || o.eig_maxit < 1)
+      fail(MG_ERR_ARG, "bad smoother options");
+    if (o.sell_sigma < 0 || (o.sell_sigma > 1 && o.sell_sigma % SELL_C))
+      fail(MG_ERR_ARG, "sell_sigma must be 0, 1 or a multiple of 64");
+    for (int l = 0; l < n_levels; ++l) validate_mesh(levels[l], dim, l);
+    h = new mg_ctx();
+    Ctx &c = h->impl;
+    c.opt = o;
+    c.tau = quality_threshold;
+    c.layers = patch_layers;
+    if (o.stream) {
+      c.stream = (hipStream_t)o.stream;
+    } else {
+      MG_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+      c.own_stream = true;
+    }
+    c.lv.resize(n_levels);
+    const bool mixed = o.precision == MG_MIXED;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+    for (int l = 0; l < n_levels; ++l) {
+      auto t0 = now();
+      Level &L = c.lv[l];
+      L.degree = o.degree;
+      L.coarsest = (l == n_levels - 1);
+      build_dofmap(c, L, levels[l]);
+      compute_quality(c, L);
+      if (!L.coarsest) build_patches(c, L, levels[l]);
+      if (l == 0) assemble_fine(c, L);
+      L.setup_ms += ms(t0, now());
+    }
+    for (int l = 0; l + 1 < n_levels; ++l) {
+      auto t0 = now();
+      build_prolongation(c, c.lv[l], c.lv[l + 1], levels[l + 1]);
+      galerkin_product(c, c.lv[l], c.lv[l + 1]);
+      c.lv[l].setup_ms += ms(t0, now());
+    }
+    for (int l = 0; l < n_levels; ++l) {
+      auto t0 = now();
+      Level &L = c.lv[l];
+      compute_dinv(c, L);
+      build_sell(c, L.A, L.S, choose_sigma(c, L.A), mixed && !L.coarsest);
+      if (!L.coarsest) {
+        factor_patches(c, L);
+        estimate_eigenvalues(c, L);
+      } else {
+        factor_coarsest(c, L);
+      }
+      ensure_work(c, L);
+      L.setup_ms += ms(t0, now());
+    }
+    int64_t n0 = c.lv[0].nfree;
+    c.r.alloc(n0);
+    c.z.alloc(n0);
+    c.p.alloc(n0);
+    c.q.alloc(n0);
+    c.ax.alloc(n0);
+    int64_t pb = std::max<int64_t>(1024, spmv_dot_blocks(c.lv[0].S));
+    c.partial.alloc(pb);
+    c.scal.alloc(8);
+    MG_HIP(hipHostMalloc((void **)&c.h_scal, 8 * sizeof(double), hipHostMallocDefault));
+    MG_HIP(hipStreamSynchronize(c.stream));
+    *out = h;
+    return MG_OK;
+  } catch (const Error &e) {
+    g_error = e.msg;
+    delete h;
+    return e.code;
+  } catch (const std::exception &e) {
+    g_error = e.what();
+    delete h;
+    return MG_ERR_HIP;
+  }
+}
+
+mg_status mg_smooth(mg_ctx *h, int32_t level, const double *b, double *u, int32_t nu) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || !b || !u) fail(MG_ERR_ARG, "NULL argument");
+  Ctx &c = h->impl;
+  if (level < 0 || level >= (int)c.lv.size() || c.lv[level].coarsest)
+    fail(MG_ERR_ARG, "level %d has no smoother", level);
+  if (b == u) fail(MG_ERR_ARG, "b must not alias u");
+  if (nu < 0) fail(MG_ERR_ARG, "nu must be >= 0");
+  Level &L = c.lv[level];
+  if (c.opt.precision == MG_MIXED) {
+    convert<double, float>(c.stream, b, L.w32[W_B], L.nfree);
+    convert<double, float>(c.stream, u, L.w32[W_U], L.nfree);
+    smooth<float>(c, level, L.w32[W_B], L.w32[W_U], nu);
+    convert<float, double>(c.stream, L.w32[W_U], u, L.nfree);
+  } else {
+    copy64(c.stream, b, L.w64[W_B], L.nfree);
+    copy64(c.stream, u, L.w64[W_U], L.nfree);
+    smooth<double>(c, level, L.w64[W_B], L.w64[W_U], nu);
+    copy64(c.stream, L.w64[W_U], u, L.nfree);
+  }
+  MG_HIP(hipStreamSynchronize(c.stream));
+  return MG_OK;
+  MG_API_END(cp)
+}
+
+mg_status mg_vcycle(mg_ctx *h, const double *b, double *u) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || !b || !u) fail(MG_ERR_ARG, "NULL argument");
+  Ctx &c = h->impl;
+  if (b == u) fail(MG_ERR_ARG, "b must not alias u");
+  Level &L0 = c.lv[0];
+  // V(b, u) = u + B (b - A u): the cycle is affine in its initial guess
+  sell_spmv<double>(c.stream, L0.S, u, c.r, SPMV_RESID, b);
+  precondition(c);
+  add64(c.stream, u, c.z, L0.nfree);
+  MG_HIP(hipStreamSynchronize(c.stream));
+  return MG_OK;
+  MG_API_END(cp)
+}
+
+mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32_t maxit, mg_solve_stats *st) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || !b || !u) fail(MG_ERR_ARG, "NULL argument");
+  Ctx &c = h->impl;
+  if (b == u) fail(MG_ERR_ARG, "b must not alias u");
+  if (maxit < 0 || !(rtol >= 0)) fail(MG_ERR_ARG, "bad rtol or maxit");
+  Level &L0 = c.lv[0];
+  const int64_t n = L0.nfree;
+  hipStream_t s = c.stream;
+  if (st) std::memset(st, 0, sizeof(*st));
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } guard{e0, e1};
+  MG_HIP(hipEventRecord(e0, s));
+  double *scal = c.scal.p;
+  fill<double>(s, scal, 8, 0.0);
+  fill<double>(s, u, n, 0.0);
+  copy64(s, b, c.r, n);
+  dot_to(c, b, b, n, scal + 7);
+  double bb = read_scalar(c, scal + 7);
+  double bnorm = std::sqrt(bb);
+  std::vector<double> hist{bnorm > 0 ? 1.0 : 0.0};
+  int it = 0;
+  bool converged = bnorm == 0.0, breakdown = false;
+  double rel = bnorm > 0 ? 1.0 : 0.0;
+  if (!converged) {
+    precondition(c);
+    copy64(s, c.z, c.p, n);
+    dot_to(c, c.r, c.z, n, scal + 0);
+    const int nb = dot_blocks(n);
+    while (it < maxit) {
+      // q = A p with p.q
+      int sb = spmv_dot_blocks(L0.S);
+      spmv_dot(s, L0.S, c.p, c.q, c.partial);
+      finish_sum(s, c.partial, sb, scal + 1);
+      cg_alpha(s, scal);
+      cg_update_xr(s, u, c.r, c.p, c.q, scal, n, c.partial, nb);
+      finish_sum(s, c.partial, nb, scal + 3);
+      MG_HIP(hipMemcpyAsync(c.h_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      MG_HIP(hipStreamSynchronize(s));
+      ++it;
+      double rr = c.h_scal[3];
+      if (c.h_scal[6] != 0.0 || !std::isfinite(rr)) {
+        breakdown = true;
+        break;
+      }
+      rel = std::sqrt(rr) / bnorm;
+      hist.push_back(rel);
+      if (rel <= rtol) {
+        converged = true;
+        break;
+      }
+      precondition(c);
+      dot_to(c, c.r, c.z, n, scal + 4);
+      cg_beta(s, scal);
+      cg_update_p(s, c.p, c.z, scal, n);
+    }
+  }
+  MG_HIP(hipEventRecord(e1, s));
+  MG_HIP(hipEventSynchronize(e1));
+  float tms = 0;
+  MG_HIP(hipEventElapsedTime(&tms, e0, e1));
+  // true residual in FP64
+  double true_rel = 0;
+  if (bnorm > 0) {
+    sell_spmv<double>(s, L0.S, u, c.ax, SPMV_RESID, b);
+    dot_to(c, c.ax, c.ax, n, scal + 7);
+    true_rel = std::sqrt(read_scalar(c, scal + 7)) / bnorm;
+  }
+  if (st) {
+    st->iterations = it;
+    st->converged = converged ? 1 : 0;
+    st->rel_residual = rel;
+    st->true_rel_residual = true_rel;
+    st->solve_ms = tms;
+    st->n_history = (int32_t)std::min<size_t>(hist.size(), MG_MAX_HISTORY);
+    for (int k = 0; k < st->n_history; ++k) st->history[k] = hist[k];
+  }
+  if (breakdown) fail(MG_ERR_BREAKDOWN, "CG breakdown at iteration %d (p.Ap <= 0 or a non-finite value)", it);
+  return converged ? MG_OK : MG_NOT_CONVERGED;
+  MG_API_END(cp)
+}
+
+mg_status mg_rhs_from_nodal(mg_ctx *h, const double *f, double *b) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || !f || !b) fail(MG_ERR_ARG, "NULL argument");
+  Ctx &c = h->impl;
+  if (c.M.nrows == 0) {
+    assemble_mass(c, c.lv[0]);
+    build_sell(c, c.M, c.Ms, 1, false);
+  }
+  sell_spmv<double>(c.stream, c.Ms, f, b, SPMV_SET, nullptr);
+  MG_HIP(hipStreamSynchronize(c.stream));
+  return MG_OK;
+  MG_API_END(cp)
+}
+
+mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
+  if (!h || !o) return MG_ERR_ARG;
+  const Ctx &c = h->impl;
+  if (level < 0 || level >= (int)c.lv.size()) return MG_ERR_ARG;
+  const Level &L = c.lv[level];
+  std::memset(o, 0, sizeof(*o));
+  o->n_vertices = L.nv;
+  o->n_cells = L.nc;
+  o->n_dofs = L.ndofs;
+  o->n_free = L.nfree;
+  o->nnz = L.A.nnz;
+  o->n_flagged = L.nflagged;
+  o->n_patches = L.patch.n;
+  o->n_colours = L.patch.ncolour;
+  o->max_patch = L.patch.maxn;
+  o->sum_patch_dofs = L.patch.total;
+  o->gamma_min = L.gamma_min;
+  o->lambda_max = L.lam;
+  o->lambda_adj = L.lam_adj;
+  o->cheb_lo = L.lo;
+  o->cheb_hi = L.hi;
+  o->lanczos_steps = L.lanczos_steps;
+  o->lanczos_steps_adj = L.lanczos_steps_adj;
+  o->sell_sigma = L.S.sigma;
+  o->sell_stored = L.S.stored;
+  o->is_coarsest = L.coarsest ? 1 : 0;
+  o->setup_ms = L.setup_ms;
+  return MG_OK;
+}
+
+mg_status mg_get_array(const mg_ctx *h, int32_t level, int32_t what, void *out) {
+  const Ctx *cp = h ? &h->impl : nullptr;
+  Ctx *mcp = const_cast<Ctx *>(cp);
+  MG_API_BEGIN
+  if (!h || !out) fail(MG_ERR_ARG, "NULL argument");
+  const Ctx &c = h->impl;
+  if (level < 0 || level >= (int)c.lv.size()) fail(MG_ERR_ARG, "bad level");
+  const Level &L = c.lv[level];
+  hipStream_t s = c.stream;
+  switch (what) {
+    case MG_ARR_QUALITY: copy_out(s, L.gamma.p, L.nc, out); break;
+    case MG_ARR_FLAGS: copy_out(s, L.flags.p, L.nc, out); break;
+    case MG_ARR_PATCH_PTR: std::memcpy(out, L.patch.h_ptr.data(), L.patch.h_ptr.size() * 4); break;
+    case MG_ARR_PATCH_DOFS: std::memcpy(out, L.patch.h_dofs.data(), L.patch.h_dofs.size() * 4); break;
+    case MG_ARR_PATCH_COLOUR: std::memcpy(out, L.patch.h_colour.data(), L.patch.h_colour.size() * 4); break;
+    case MG_ARR_LOCATE: copy_out(s, L.locate.p, L.coarsest ? 0 : L.nfree, out); break;
+    case MG_ARR_FREE_DOFS: copy_out(s, L.free_dofs.p, L.nfree, out); break;
+    case MG_ARR_DOF_NODES: copy_out(s, L.nodes.p, L.ndofs * L.dim, out); break;
+    case MG_ARR_A_ROWPTR: copy_out(s, L.A.rowptr.p, L.nfree + 1, out); break;
+    case MG_ARR_A_COLS: copy_out(s, L.A.col.p, L.A.nnz, out); break;
+    case MG_ARR_A_VALS: copy_out(s, L.A.val.p, L.A.nnz, out); break;
+    case MG_ARR_P_COLS: copy_out(s, L.pcol.p, L.coarsest ? 0 : L.nfree * L.pw, out); break;
+    case MG_ARR_P_VALS: copy_out(s, L.pval.p, L.coarsest ? 0 : L.nfree * L.pw, out); break;
+    case MG_ARR_CELL_DOFS: copy_out(s, L.cell_dofs.p, L.nc * L.nloc, out); break;
+    case MG_ARR_P_WIDTH: *(int32_t *)out = L.pw; break;
+    default: fail(MG_ERR_ARG, "unknown array %d", what);
+  }
+  return MG_OK;
+  MG_API_END(mcp)
+}
+
+mg_status mg_enable_kernel_timing(mg_ctx *h, int32_t enable) {
+  if (!h) return MG_ERR_ARG;
+  Ctx &c = h->impl;
+  c.timing = enable != 0;
+  c.events_used = 0;
+  c.timed_launches = 0;
+  c.timed_ms = 0;
+  return MG_OK;
+}
+
+mg_status mg_kernel_time(mg_ctx *h, int64_t *launches, double *total_ms) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || !launches || !total_ms) fail(MG_ERR_ARG, "NULL argument");
+  Ctx &c = h->impl;
+  MG_HIP(hipStreamSynchronize(c.stream));
+  for (size_t k = 0; k < c.events_used; ++k) {
+    float t = 0;
+    MG_HIP(hipEventElapsedTime(&t, c.events[k].first, c.events[k].second));
+    c.timed_ms += t;
+    ++c.timed_launches;
+  }
+  c.events_used = 0;
+  *launches = c.timed_launches;
+  *total_ms = c.timed_ms;
+  return MG_OK;
+  MG_API_END(cp)
+}
+
+mg_status mg_cheb_algorithmic_bytes(const mg_ctx *h, double *bytes) {
+  if (!h || !bytes) return MG_ERR_ARG;
+  const Level &L = h->impl.lv[0];
+  if (L.coarsest) return MG_ERR_ARG;
+  double nnz = (double)L.A.nnz, n = (double)L.nfree;
+  *bytes = h->impl.opt.precision == MG_MIXED ? 8.0 * nnz + 24.0 * n : 12.0 * nnz + 48.0 * n;
+  return MG_OK;
+}
+
+}  // extern "C"

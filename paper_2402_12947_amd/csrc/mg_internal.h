@@ -1,0 +1,260 @@
+// Internal definitions of the gfx950 global-local multigrid library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <type_traits>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mgpcg.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws Error; the C entry points catch it.
+// ---------------------------------------------------------------------------
+struct Error {
+  mg_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(mg_status code, const char *fmt, ...);
+
+#define MG_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      ::mg::fail(MG_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                 __FILE__, __LINE__);                                             \
+  } while (0)
+
+#define MG_LAUNCH_CHECK() MG_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// device buffer owning its allocation
+// ---------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf &operator=(DBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      fail(MG_ERR_OOM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    }
+    n = count;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  operator T *() const { return p; }
+};
+
+template <class T>
+void upload(DBuf<T> &d, const T *h, size_t n, hipStream_t s) {
+  d.alloc(n);
+  if (n) MG_HIP(hipMemcpyAsync(d.p, h, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
+void download(std::vector<T> &h, const T *d, size_t n, hipStream_t s) {
+  h.resize(n);
+  if (n) MG_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// sliced ELL (SELL-C-sigma) with C = 64: one wavefront lane per row; inside a
+// slice the entries of column position j of the 64 rows are contiguous.
+// ---------------------------------------------------------------------------
+constexpr int SELL_C = 64;
+
+struct Sell {
+  int64_t nrows = 0, ncols = 0, nslices = 0, stored = 0;
+  int sigma = 1;
+  DBuf<int64_t> slice_ptr;  // [nslices + 1]
+  DBuf<int32_t> perm;       // [nslices * 64] row at each position, -1 = empty
+  DBuf<int32_t> iperm;      // [nrows] position of each row
+  DBuf<int32_t> col;        // [stored]
+  DBuf<double> v64;         // [stored] (FP64 copy)
+  DBuf<float> v32;          // [stored] (FP32 copy, mixed precision)
+};
+
+struct Csr {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  DBuf<int64_t> rowptr;
+  DBuf<int32_t> col;
+  DBuf<double> val;
+};
+
+// Patches of one level in kernel order (sorted by colour, then canonical id).
+struct Patches {
+  int n = 0, ncolour = 0, maxn = 0;
+  int64_t total = 0;          // sum of patch sizes
+  std::vector<int> colour_first;   // [ncolour + 1] kernel-order patch ranges
+  std::vector<int32_t> h_ptr, h_dofs, h_colour;  // canonical order (export)
+  std::vector<int32_t> h_kptr;     // [n + 1] kernel-order offsets (host copy)
+  DBuf<int32_t> ptr;          // [n + 1] kernel order
+  DBuf<int32_t> dofs;         // [total]
+  DBuf<int64_t> inv_off;      // [n] offset of the patch inverse (n_d^2 entries)
+  DBuf<double> inv64;
+  DBuf<float> inv32;
+};
+
+struct Level {
+  // mesh and DOF map
+  int dim = 0, degree = 0, nloc = 0;
+  int64_t nv = 0, nc = 0, ne = 0, ndofs = 0, nfree = 0;
+  DBuf<double> coords;
+  DBuf<int32_t> cells;
+  DBuf<uint8_t> dirv;
+  DBuf<int32_t> cell_dofs;     // [nc * nloc]
+  DBuf<int32_t> free_index;    // [ndofs] -> free id or -1
+  DBuf<int32_t> free_dofs;     // [nfree] -> canonical id
+  DBuf<double> nodes;          // [ndofs * dim]
+  DBuf<double> gamma;
+  DBuf<uint8_t> flags;
+  int64_t nflagged = 0;
+  double gamma_min = 0;
+  // operator
+  Csr A;
+  Sell S;
+  DBuf<double> dinv64;
+  DBuf<float> dinv32;
+  // transfer to the next coarser level (absent on the coarsest)
+  int pw = 0;
+  DBuf<int32_t> locate;        // [nfree]
+  DBuf<int32_t> pcol;          // [nfree * pw] row-major, -1 = dropped
+  DBuf<double> pval;           // [nfree * pw]
+  Csr Pc, Rc;                  // P and R = P^T as CSR (Galerkin product)
+  Sell P, R;                   // y += P x_c ; y = R r
+  // local correction
+  Patches patch;
+  // Chebyshev
+  double lam = 0, lam_adj = 0, lo = 0, hi = 0;
+  int lanczos_steps = 0, lanczos_steps_adj = 0;
+  // coarsest: dense inverse
+  bool coarsest = false;
+  DBuf<double> cinv;           // [nfree * nfree]
+  DBuf<double> cpart;          // partial sums of the dense product
+  // V-cycle work vectors, precision of the cycle
+  DBuf<double> w64[6];
+  DBuf<float> w32[6];
+  DBuf<double> res64;          // patch residuals [patch.total]
+  DBuf<float> res32;
+  double setup_ms = 0;
+};
+
+struct Ctx {
+  mg_options opt{};
+  double tau = 0.1;
+  int layers = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<Level> lv;
+  std::string err;
+  // PCG work (FP64, level 0)
+  DBuf<double> r, z, p, q, ax;
+  DBuf<double> partial;        // dot-product block partials
+  DBuf<double> scal;           // device scalars of CG
+  double *h_scal = nullptr;    // pinned host mirror
+  // mass matrix (free rows x all DOFs) for mg_rhs_from_nodal, built lazily
+  Csr M;
+  Sell Ms;
+  // kernel timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+  int64_t timed_launches = 0;
+  double timed_ms = 0;
+  // captured V-cycle graph
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  ~Ctx();
+};
+
+// ---------------------------------------------------------------------------
+// setup stages (setup_*.hip)
+// ---------------------------------------------------------------------------
+void build_dofmap(Ctx &c, Level &L, const mg_mesh &m);
+void compute_quality(Ctx &c, Level &L);
+void assemble_fine(Ctx &c, Level &L);
+void assemble_mass(Ctx &c, Level &L);
+void build_prolongation(Ctx &c, Level &fine, const Level &coarse, const mg_mesh &cm);
+void galerkin_product(Ctx &c, Level &fine, Level &coarse);
+void build_patches(Ctx &c, Level &L, const mg_mesh &m);
+void factor_patches(Ctx &c, Level &L);
+void factor_coarsest(Ctx &c, Level &L);
+void estimate_eigenvalues(Ctx &c, Level &L);
+void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);
+void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,
+                bool transpose, Csr &A);
+void spgemm(Ctx &c, const Csr &A, const Csr &B, Csr &C);
+void compute_dinv(Ctx &c, Level &L);
+void ensure_work(Ctx &c, Level &L);
+
+// ---------------------------------------------------------------------------
+// solve-phase kernels (solve.hip)
+// ---------------------------------------------------------------------------
+template <class T>
+void sell_spmv(hipStream_t s, const Sell &S, const T *x, T *y, int mode, const T *b);
+// modes of sell_spmv
+enum { SPMV_SET = 0, SPMV_ADD = 1, SPMV_RESID = 2 };
+
+template <class T>
+void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T *x, T *xout, T *d,
+               int first, double c_d, double c_r);
+
+template <class T>
+void patch_residual(hipStream_t s, const Sell &S, const Patches &pt, int colour, const T *b,
+                    const T *u, T *res);
+template <class T>
+void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *u);
+
+template <class T>
+void dense_symv(hipStream_t s, int64_t n, const double *M, const T *x, T *y, double *part);
+
+template <class T>
+void fill(hipStream_t s, T *x, int64_t n, T v);
+template <class A, class B>
+void convert(hipStream_t s, const A *x, B *y, int64_t n);
+void copy64(hipStream_t s, const double *x, double *y, int64_t n);
+void add64(hipStream_t s, double *y, const double *x, int64_t n);
+int64_t dense_part_size(int64_t n);
+int spmv_dot_blocks(const Sell &S);
+void spmv_dot(hipStream_t s, const Sell &S, const double *p, double *q, double *part);
+
+// dot products: partial sums into part, then finalisation into out[0]
+void dot_partials(hipStream_t s, const double *x, const double *y, int64_t n, double *part,
+                  int nblocks);
+int dot_blocks(int64_t n);
+void finish_sum(hipStream_t s, const double *part, int nblocks, double *out);
+
+// CG helpers working on device scalars
+void cg_alpha(hipStream_t s, double *scal);
+void cg_update_xr(hipStream_t s, double *x, double *r, const double *p, const double *q,
+                  const double *scal, int64_t n, double *part, int nblocks);
+void cg_beta(hipStream_t s, double *scal);
+void cg_update_p(hipStream_t s, double *p, const double *z, const double *scal, int64_t n);
+
+}  // namespace mg

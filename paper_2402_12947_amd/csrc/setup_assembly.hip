@@ -1,0 +1,416 @@
+// Fine-level finite-element assembly (paper Sec. 2, eq. system_finest; Sec. 6.1)
+// and the sparse formats used by the solve kernels.
+//
+// Element stiffness of a simplex T with barycentric gradients g_a:
+//   K_T[i][j] = |T| sum_{a,b} (g_a . g_b) Kref[a][b][i][j],
+//   Kref[a][b][i][j] = (1/|T_ref|) int dphi_i/dlam_a dphi_j/dlam_b,
+// where the reference tensors are integrated on the host with a collapsed
+// (Duffy) tensor Gauss-Legendre rule that is exact for the polynomial degrees
+// involved.  Global assembly is atomic-free and deterministic: every element
+// entry becomes a (row * n + col, value) pair, the pairs are radix-sorted
+// (stable, so equal keys keep cell order) and each run of equal keys is summed
+// sequentially.  Dirichlet rows and columns are dropped (u = 0 on Gamma_D).
+#include <array>
+#include <cmath>
+
+#include "basis.h"
+#include "devutil.h"
+#include "geom.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// reference tensors (host)
+// ---------------------------------------------------------------------------
+static void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1);
+    x[i] = 0.5 * (1 - z);
+    w[i] = 1.0 / ((1 - z * z) * dp * dp);  // 2/((1-z^2)dp^2) scaled by 1/2 for [0,1]
+  }
+}
+
+// barycentric quadrature points and weights on the reference simplex
+static void simplex_rule(int dim, std::vector<std::array<double, 4>> &pts, std::vector<double> &wts) {
+  const int n = 8;
+  std::vector<double> x, w;
+  gauss_legendre01(n, x, w);
+  pts.clear();
+  wts.clear();
+  if (dim == 2) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double u = x[i], v = x[j] * (1 - u);
+        pts.push_back({1 - u - v, u, v, 0});
+        wts.push_back(w[i] * w[j] * (1 - u));
+      }
+  } else {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+          double u = x[i], v = x[j] * (1 - u), t = x[k] * (1 - x[i]) * (1 - x[j]);
+          pts.push_back({1 - u - v - t, u, v, t});
+          wts.push_back(w[i] * w[j] * w[k] * (1 - x[i]) * (1 - x[i]) * (1 - x[j]));
+        }
+  }
+}
+
+__constant__ double c_ref[1600];  // Kref[a][b][i][j] or Mref[i][j]
+
+static void reference_tensor(int dim, int degree, bool mass, std::vector<double> &out) {
+  int nl = n_local(dim, degree), nb = dim + 1;
+  std::vector<std::array<double, 4>> pts;
+  std::vector<double> wts;
+  simplex_rule(dim, pts, wts);
+  double vref = dim == 2 ? 0.5 : 1.0 / 6.0;
+  if (mass) {
+    out.assign(nl * nl, 0.0);
+    for (size_t q = 0; q < pts.size(); ++q)
+      for (int i = 0; i < nl; ++i)
+        for (int j = 0; j < nl; ++j)
+          out[i * nl + j] += wts[q] * basis_value(dim, degree, i, pts[q].data()) *
+                             basis_value(dim, degree, j, pts[q].data()) / vref;
+  } else {
+    out.assign(nb * nb * nl * nl, 0.0);
+    for (size_t q = 0; q < pts.size(); ++q)
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b)
+          for (int i = 0; i < nl; ++i)
+            for (int j = 0; j < nl; ++j)
+              out[((a * nb + b) * nl + i) * nl + j] += wts[q] * basis_dlam(dim, degree, i, a, pts[q].data()) *
+                                                      basis_dlam(dim, degree, j, b, pts[q].data()) / vref;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// element matrices -> (key, value) pairs
+// ---------------------------------------------------------------------------
+// one thread per (cell, local row i): writes nloc pairs
+__global__ void k_element_pairs(const double *X, const int32_t *cells, const int32_t *cell_dofs,
+                                const int32_t *row_index, const int32_t *col_index, int64_t nc, int dim,
+                                int nloc, int mass, uint64_t ncols, uint64_t sentinel, uint64_t *keys,
+                                double *vals) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * nloc) return;
+  int64_t c = t / nloc;
+  int i = (int)(t - c * nloc);
+  int nb = dim + 1;
+  double g[4][3];
+  double vol = simplex_grads(X, cells + c * nb, dim, g);
+  double G[4][4];
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      double s = 0;
+      for (int x = 0; x < dim; ++x) s += g[a][x] * g[b][x];
+      G[a][b] = s;
+    }
+  const int32_t *cd = cell_dofs + c * nloc;
+  int32_t ri = row_index[cd[i]];
+  for (int j = 0; j < nloc; ++j) {
+    double v;
+    if (mass) {
+      v = vol * c_ref[i * nloc + j];
+    } else {
+      double s = 0;
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) s += G[a][b] * c_ref[((a * nb + b) * nloc + i) * nloc + j];
+      v = vol * s;
+    }
+    int32_t cj = col_index ? col_index[cd[j]] : cd[j];
+    int64_t o = t * nloc + j;
+    keys[o] = (ri >= 0 && cj >= 0) ? (uint64_t)ri * ncols + (uint64_t)cj : sentinel;
+    vals[o] = v;
+  }
+}
+
+__global__ void k_segment_sum(const double *vals, const int32_t *len, const int64_t *off, int64_t n, double *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0;
+  int64_t b = off[i];
+  for (int32_t k = 0; k < len[i]; ++k) s += vals[b + k];
+  out[i] = s;
+}
+
+__global__ void k_keys_to_csr(const uint64_t *keys, int64_t nnz, uint64_t ncols, int64_t nrows, int32_t *col,
+                              int64_t *rowptr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  uint64_t k = keys[i];
+  int64_t r = (int64_t)(k / ncols);
+  col[i] = (int32_t)(k % ncols);
+  int64_t rp = i == 0 ? -1 : (int64_t)(keys[i - 1] / ncols);
+  for (int64_t q = rp + 1; q <= r; ++q) rowptr[q] = i;
+  if (i == nnz - 1)
+    for (int64_t q = r + 1; q <= nrows; ++q) rowptr[q] = nnz;
+}
+
+// Sorted unique keys (row * ncols + col) with values -> CSR.
+static void csr_from_keys(hipStream_t s, const uint64_t *keys, const double *vals, int64_t nnz, int64_t nrows,
+                          int64_t ncols, Csr &A) {
+  A.nrows = nrows;
+  A.ncols = ncols;
+  A.nnz = nnz;
+  A.rowptr.alloc(nrows + 1);
+  A.col.alloc(nnz);
+  A.val.alloc(nnz);
+  if (nnz == 0) {
+    MG_HIP(hipMemsetAsync(A.rowptr.p, 0, (nrows + 1) * sizeof(int64_t), s));
+    return;
+  }
+  k_keys_to_csr<<<grid_for(nnz, 256), 256, 0, s>>>(keys, nnz, (uint64_t)ncols, nrows, A.col, A.rowptr);
+  MG_LAUNCH_CHECK();
+  MG_HIP(hipMemcpyAsync(A.val.p, vals, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+// Sort (key, value) pairs, sum duplicates, drop the sentinel, build CSR.
+static void assemble_pairs(hipStream_t s, DBuf<uint64_t> &keys, DBuf<double> &vals, int64_t npairs,
+                           uint64_t sentinel, int64_t nrows, int64_t ncols, Csr &A) {
+  int endbit = bits_for(sentinel);
+  DBuf<uint64_t> ks;
+  DBuf<double> vs;
+  ks.alloc(npairs);
+  vs.alloc(npairs);
+  sort_pairs(s, keys.p, ks.p, vals.p, vs.p, npairs, endbit);
+  keys.release();
+  vals.release();
+  DBuf<uint64_t> uk;
+  DBuf<int32_t> len;
+  uk.alloc(npairs);
+  len.alloc(npairs);
+  int64_t nrun = run_length(s, ks.p, uk.p, len.p, npairs);
+  uint64_t lastkey = 0;
+  MG_HIP(hipMemcpyAsync(&lastkey, uk.p + nrun - 1, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  int64_t nnz = (lastkey == sentinel) ? nrun - 1 : nrun;
+  DBuf<int64_t> off;
+  off.alloc(nrun);
+  exclusive_scan(s, len.p, off.p, nrun);
+  DBuf<double> sum;
+  sum.alloc(nnz > 0 ? nnz : 1);
+  if (nnz > 0) {
+    k_segment_sum<<<grid_for(nnz, 256), 256, 0, s>>>(vs, len, off, nnz, sum);
+    MG_LAUNCH_CHECK();
+  }
+  csr_from_keys(s, uk.p, sum.p, nnz, nrows, ncols, A);
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+static void element_assembly(Ctx &c, Level &L, bool mass, Csr &A) {
+  hipStream_t s = c.stream;
+  std::vector<double> ref;
+  reference_tensor(L.dim, L.degree, mass, ref);
+  MG_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_ref), ref.data(), ref.size() * sizeof(double), 0,
+                                hipMemcpyHostToDevice, s));
+  int64_t npairs = L.nc * L.nloc * L.nloc;
+  uint64_t ncols = mass ? (uint64_t)L.ndofs : (uint64_t)L.nfree;
+  uint64_t sentinel = (uint64_t)L.nfree * ncols;
+  DBuf<uint64_t> keys;
+  DBuf<double> vals;
+  keys.alloc(npairs);
+  vals.alloc(npairs);
+  k_element_pairs<<<grid_for(L.nc * L.nloc, 256), 256, 0, s>>>(
+      L.coords, L.cells, L.cell_dofs, L.free_index, mass ? nullptr : L.free_index.p, L.nc, L.dim, L.nloc,
+      mass ? 1 : 0, ncols, sentinel, keys, vals);
+  MG_LAUNCH_CHECK();
+  assemble_pairs(s, keys, vals, npairs, sentinel, L.nfree, (int64_t)ncols, A);
+}
+
+void assemble_fine(Ctx &c, Level &L) { element_assembly(c, L, false, L.A); }
+
+void assemble_mass(Ctx &c, Level &L) { element_assembly(c, L, true, c.M); }
+
+// ---------------------------------------------------------------------------
+// diagonal
+// ---------------------------------------------------------------------------
+__global__ void k_dinv(const int64_t *rowptr, const int32_t *col, const double *val, int64_t n, double *d64,
+                       float *d32, int *bad) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double d = 0;
+  for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+    if (col[k] == r) d = val[k];
+  if (!(d > 0)) atomicMin(bad, (int)r);
+  d64[r] = 1.0 / d;
+  if (d32) d32[r] = (float)(1.0 / d);
+}
+
+void compute_dinv(Ctx &c, Level &L) {
+  hipStream_t s = c.stream;
+  L.dinv64.alloc(L.nfree);
+  bool mixed = c.opt.precision == MG_MIXED;
+  if (mixed) L.dinv32.alloc(L.nfree);
+  DBuf<int> bad;
+  bad.alloc(1);
+  int init = 2147483647;
+  MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
+  k_dinv<<<grid_for(L.nfree, 256), 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, L.nfree, L.dinv64,
+                                               mixed ? L.dinv32.p : nullptr, bad);
+  MG_LAUNCH_CHECK();
+  int hb = 0;
+  MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  if (hb != 2147483647)
+    fail(MG_ERR_NOT_SPD, "operator row %d has a non-positive diagonal (a coarse basis function that no "
+                         "fine DOF node sees, or a singular system)", hb);
+}
+
+// ---------------------------------------------------------------------------
+// SELL-C-sigma from CSR
+// ---------------------------------------------------------------------------
+__global__ void k_sort_keys_len(const int64_t *rowptr, int64_t n, int sigma, uint64_t *keys, int32_t *rows) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  uint64_t len = (uint64_t)(rowptr[r + 1] - rowptr[r]);
+  uint64_t win = (uint64_t)(r / sigma);
+  keys[r] = (win << 32) | (0xFFFFFFFFULL - len);
+  rows[r] = (int32_t)r;
+}
+
+__global__ void k_identity_perm(int32_t *perm, int64_t npos, int64_t n) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npos) perm[p] = p < n ? (int32_t)p : -1;
+}
+
+__global__ void k_inverse_perm(const int32_t *perm, int64_t npos, int32_t *iperm) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < npos && perm[p] >= 0) iperm[perm[p]] = (int32_t)p;
+}
+
+__global__ void k_slice_width(const int64_t *rowptr, const int32_t *perm, int64_t nslices, int64_t *w64) {
+  int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslices) return;
+  int64_t w = 0;
+  for (int l = 0; l < SELL_C; ++l) {
+    int32_t r = perm[sl * SELL_C + l];
+    if (r >= 0) {
+      int64_t len = rowptr[r + 1] - rowptr[r];
+      w = len > w ? len : w;
+    }
+  }
+  w64[sl] = w * SELL_C;
+}
+
+__global__ void k_sell_fill(const int64_t *rowptr, const int32_t *ccol, const double *cval, const int32_t *perm,
+                            const int64_t *sptr, int64_t npos, int32_t *col, double *v64, float *v32) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npos) return;
+  int64_t sl = p / SELL_C;
+  int lane = (int)(p - sl * SELL_C);
+  int64_t base = sptr[sl];
+  int64_t w = (sptr[sl + 1] - base) / SELL_C;
+  int32_t r = perm[p];
+  int64_t b = r >= 0 ? rowptr[r] : 0, len = r >= 0 ? rowptr[r + 1] - rowptr[r] : 0;
+  int32_t pad = len > 0 ? ccol[b] : 0;
+  for (int64_t j = 0; j < w; ++j) {
+    int64_t o = base + j * SELL_C + lane;
+    int32_t cc = j < len ? ccol[b + j] : pad;
+    double vv = j < len ? cval[b + j] : 0.0;
+    col[o] = cc;
+    v64[o] = vv;
+    if (v32) v32[o] = (float)vv;
+  }
+}
+
+void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
+  hipStream_t s = c.stream;
+  if (sigma > 1 && sigma % SELL_C) fail(MG_ERR_ARG, "SELL sigma must be 1 or a multiple of 64");
+  S.nrows = A.nrows;
+  S.ncols = A.ncols;
+  S.sigma = sigma;
+  S.nslices = (A.nrows + SELL_C - 1) / SELL_C;
+  int64_t npos = S.nslices * SELL_C;
+  S.perm.alloc(npos);
+  if (sigma > 1) {
+    DBuf<uint64_t> k, ks;
+    DBuf<int32_t> r;
+    k.alloc(A.nrows);
+    ks.alloc(A.nrows);
+    r.alloc(A.nrows);
+    k_sort_keys_len<<<grid_for(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.nrows, sigma, k, r);
+    MG_LAUNCH_CHECK();
+    k_identity_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, A.nrows);
+    MG_LAUNCH_CHECK();
+    int64_t nwin = (A.nrows + sigma - 1) / sigma;
+    sort_pairs(s, k.p, ks.p, r.p, S.perm.p, A.nrows, 32 + bits_for((uint64_t)nwin));
+  } else {
+    k_identity_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, A.nrows);
+    MG_LAUNCH_CHECK();
+  }
+  S.iperm.alloc(A.nrows);
+  k_inverse_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, S.iperm);
+  MG_LAUNCH_CHECK();
+  DBuf<int64_t> w;
+  w.alloc(S.nslices);
+  k_slice_width<<<grid_for(S.nslices, 256), 256, 0, s>>>(A.rowptr, S.perm, S.nslices, w);
+  MG_LAUNCH_CHECK();
+  S.slice_ptr.alloc(S.nslices + 1);
+  S.stored = exclusive_scan(s, w.p, S.slice_ptr.p, S.nslices);
+  MG_HIP(hipMemcpyAsync(S.slice_ptr.p + S.nslices, &S.stored, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  S.col.alloc(S.stored);
+  S.v64.alloc(S.stored);
+  if (want32) S.v32.alloc(S.stored);
+  k_sell_fill<<<grid_for(npos, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, S.perm, S.slice_ptr, npos, S.col, S.v64,
+                                                 want32 ? S.v32.p : nullptr);
+  MG_LAUNCH_CHECK();
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// ELL (row-major, -1 = empty) -> CSR, and its transpose
+// ---------------------------------------------------------------------------
+__global__ void k_ell_keys(const int32_t *col, const double *val, int64_t nrows, int width, uint64_t ncols,
+                           int transpose, uint64_t nr_out, uint64_t sentinel, uint64_t *keys, double *vals) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * width) return;
+  int64_t r = t / width;
+  int32_t cc = col[t];
+  if (cc < 0) {
+    keys[t] = sentinel;
+  } else {
+    keys[t] = transpose ? (uint64_t)cc * (uint64_t)nrows + (uint64_t)r : (uint64_t)r * ncols + (uint64_t)cc;
+  }
+  vals[t] = val[t];
+  (void)nr_out;
+}
+
+void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,
+                bool transpose, Csr &A) {
+  hipStream_t s = c.stream;
+  int64_t n = nrows * width;
+  uint64_t sentinel = (uint64_t)nrows * (uint64_t)ncols;
+  DBuf<uint64_t> keys;
+  DBuf<double> vals;
+  keys.alloc(n);
+  vals.alloc(n);
+  k_ell_keys<<<grid_for(n, 256), 256, 0, s>>>(col, val, nrows, width, (uint64_t)ncols, transpose ? 1 : 0,
+                                             transpose ? ncols : nrows, sentinel, keys, vals);
+  MG_LAUNCH_CHECK();
+  if (transpose)
+    assemble_pairs(s, keys, vals, n, sentinel, ncols, nrows, A);
+  else
+    assemble_pairs(s, keys, vals, n, sentinel, nrows, ncols, A);
+}
+
+}  // namespace mg

@@ -1,0 +1,402 @@
+// Dense direct solvers of the method: the patch systems A^[d] = I_d^T A I_d of
+// the local correction (paper Sec. 4.1, eqs. local_system and local) and the
+// coarsest-level system (Sec. 2, direct solver on the coarsest grid).
+//
+// Each system is factored A = L L^T (Cholesky, FP64) and the factor is turned
+// into the explicit inverse A^-1 = L^-T L^-1, which the solve phase applies as
+// a dense matrix-vector product: that product is fully parallel, whereas a
+// triangular substitution is a chain of n dependent steps.
+//
+// * Patches: one workgroup per patch.  The patch matrix is gathered from the
+//   CSR operator, factored by a right-looking column sweep, and inverted by
+//   forward/backward substitution with one thread per column of the identity.
+// * Coarsest level (large n): blocked right-looking Cholesky with 64x64 tiles
+//   (diagonal factor, panel triangular solve, trailing symmetric update), then
+//   W = L^-1 block row by block row and A^-1 = W^T W, all from 64x64x64
+//   LDS-tiled FP64 products.
+#include <cmath>
+
+#include "devutil.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// patches: one workgroup per system
+// ---------------------------------------------------------------------------
+__device__ inline int find_sorted(const int32_t *a, int n, int32_t key) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return (lo < n && a[lo] == key) ? lo : -1;
+}
+
+// Gathers A[B, B] into M (n x n, row-major).  B == nullptr means all rows.
+__device__ void gather_block(const int64_t *rp, const int32_t *col, const double *val, const int32_t *B, int n,
+                             double *M) {
+  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) M[t] = 0.0;
+  __syncthreads();
+  int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
+  for (int i = wave; i < n; i += nw) {
+    int32_t r = B ? B[i] : i;
+    for (int64_t k = rp[r] + lane; k < rp[r + 1]; k += 64) {
+      int j = B ? find_sorted(B, n, col[k]) : col[k];
+      if (j >= 0) M[(int64_t)i * n + j] = val[k];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place lower Cholesky of M (n x n row-major).  Returns false (uniformly) on
+// a non-positive pivot.
+__device__ bool cholesky_inplace(double *M, int n) {
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    double piv = M[(int64_t)k * n + k];
+    if (!(piv > 0.0)) return false;
+    double d = sqrt(piv);
+    __syncthreads();
+    if (threadIdx.x == 0) M[(int64_t)k * n + k] = d;
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) M[(int64_t)i * n + k] /= d;
+    __syncthreads();
+    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
+      double ljk = M[(int64_t)j * n + k];
+      for (int i = j; i < n; ++i) M[(int64_t)i * n + j] -= M[(int64_t)i * n + k] * ljk;
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// X = (L L^T)^-1 with one thread per column: forward L Y = I, backward L^T X = Y.
+__device__ void inverse_from_factor(const double *Lf, int n, double *X) {
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int i = 0; i < j; ++i) X[(int64_t)i * n + j] = 0.0;
+    for (int i = j; i < n; ++i) {
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) acc -= Lf[(int64_t)i * n + k] * X[(int64_t)k * n + j];
+      X[(int64_t)i * n + j] = acc / Lf[(int64_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double acc = X[(int64_t)i * n + j];
+      for (int k = i + 1; k < n; ++k) acc -= Lf[(int64_t)k * n + i] * X[(int64_t)k * n + j];
+      X[(int64_t)i * n + j] = acc / Lf[(int64_t)i * n + i];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_patch_factor(const int64_t *rp, const int32_t *col, const double *val,
+                                                      const int32_t *ptr, const int32_t *dofs, const int64_t *off,
+                                                      double *scratch, double *inv, int *bad) {
+  int p = blockIdx.x;
+  int n = ptr[p + 1] - ptr[p];
+  const int32_t *B = dofs + ptr[p];
+  double *Lf = scratch + off[p];
+  gather_block(rp, col, val, B, n, Lf);
+  if (!cholesky_inplace(Lf, n)) {
+    if (threadIdx.x == 0) atomicMin(bad, p);
+    return;
+  }
+  inverse_from_factor(Lf, n, inv + off[p]);
+}
+
+__global__ void k_to_float(const double *x, float *y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+void factor_patches(Ctx &c, Level &L) {
+  Patches &P = L.patch;
+  if (P.n == 0) return;
+  hipStream_t s = c.stream;
+  int64_t total = (int64_t)P.inv64.n;
+  DBuf<double> scratch;
+  scratch.alloc(total);
+  DBuf<int> bad;
+  bad.alloc(1);
+  int init = 2147483647;
+  MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
+  k_patch_factor<<<P.n, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, P.ptr, P.dofs, P.inv_off, scratch, P.inv64,
+                                     bad);
+  MG_LAUNCH_CHECK();
+  int hb = 0;
+  MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "patch system %d has a non-positive Cholesky pivot", hb);
+  if (c.opt.precision == MG_MIXED) {
+    P.inv32.alloc(total);
+    k_to_float<<<grid_for(total, 256), 256, 0, s>>>(P.inv64, P.inv32, total);
+    MG_LAUNCH_CHECK();
+    MG_HIP(hipStreamSynchronize(s));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// large dense SPD inverse: 64x64 tiles
+// ---------------------------------------------------------------------------
+constexpr int TB = 64;
+
+__global__ void k_dense_from_csr(const int64_t *rp, const int32_t *col, const double *val, int64_t n, double *M) {
+  int64_t r = blockIdx.x;
+  if (r >= n) return;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) M[r * n + j] = 0.0;
+  __syncthreads();
+  for (int64_t k = rp[r] + threadIdx.x; k < rp[r + 1]; k += blockDim.x) M[r * n + col[k]] = val[k];
+}
+
+// factor the diagonal tile kb in LDS (one workgroup)
+__global__ __launch_bounds__(256) void k_chol_diag(double *A, int64_t n, int kb, int *bad) {
+  __shared__ double D[TB][TB + 1];
+  int64_t o = (int64_t)kb * TB;
+  int m = (int)min((int64_t)TB, n - o);
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) D[t / m][t % m] = A[(o + t / m) * n + o + t % m];
+  for (int k = 0; k < m; ++k) {
+    __syncthreads();
+    double piv = D[k][k];
+    if (!(piv > 0.0)) {
+      if (threadIdx.x == 0) atomicMin(bad, (int)(o + k));
+      return;
+    }
+    double d = sqrt(piv);
+    __syncthreads();
+    if (threadIdx.x == 0) D[k][k] = d;
+    for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) D[i][k] /= d;
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+      int i = t / m, j = t % m;
+      if (j > k && i >= j) D[i][j] -= D[i][k] * D[j][k];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+    int i = t / m, j = t % m;
+    A[(o + i) * n + o + j] = j <= i ? D[i][j] : 0.0;
+  }
+}
+
+// rows of block ib > kb: X = A[ib, kb] L[kb, kb]^-T (64 threads, one per row)
+__global__ __launch_bounds__(64) void k_chol_panel(double *A, int64_t n, int kb) {
+  __shared__ double Lk[TB][TB + 1];
+  __shared__ double R[TB][TB + 1];
+  int64_t o = (int64_t)kb * TB;
+  int m = (int)min((int64_t)TB, n - o);
+  int64_t ro = (int64_t)(kb + 1 + blockIdx.x) * TB;
+  int mr = (int)min((int64_t)TB, n - ro);
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) Lk[t / m][t % m] = A[(o + t / m) * n + o + t % m];
+  for (int t = threadIdx.x; t < mr * m; t += blockDim.x) R[t / m][t % m] = A[(ro + t / m) * n + o + t % m];
+  __syncthreads();
+  int r = threadIdx.x;
+  if (r < mr) {
+    for (int cc = 0; cc < m; ++cc) {
+      double x = R[r][cc];
+      for (int k = 0; k < cc; ++k) x -= R[r][k] * Lk[cc][k];
+      R[r][cc] = x / Lk[cc][cc];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < mr * m; t += blockDim.x) A[(ro + t / m) * n + o + t % m] = R[t / m][t % m];
+}
+
+// 16x16 threads, each owning a 4x4 block of the 64x64 output tile:
+// acc[a][b] += sum_k As[ty*4+a][k] * Bs[k][tx*4+b]
+__device__ inline void tile_mac(double acc[4][4], double (*As)[TB + 1], double (*Bs)[TB + 1]) {
+  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll 4
+  for (int k = 0; k < TB; ++k) {
+    double a[4], b[4];
+    for (int q = 0; q < 4; ++q) {
+      a[q] = As[ty * 4 + q][k];
+      b[q] = Bs[k][tx * 4 + q];
+    }
+    for (int p = 0; p < 4; ++p)
+      for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+  }
+}
+
+// load tile (row block rb, col block cb) of M (n x n) into S, transposed or not,
+// zero outside the matrix
+__device__ inline void load_tile(const double *M, int64_t n, int rb, int cb, bool trans, double (*S)[TB + 1]) {
+  for (int t = threadIdx.x; t < TB * TB; t += blockDim.x) {
+    int i = t / TB, j = t % TB;
+    int64_t r = (int64_t)rb * TB + i, cc = (int64_t)cb * TB + j;
+    double v = (r < n && cc < n) ? M[r * n + cc] : 0.0;
+    if (trans) S[j][i] = v; else S[i][j] = v;
+  }
+}
+
+__device__ inline void tri_index(int64_t t, int &i, int &j) {
+  // t -> (i, j) with 0 <= j <= i, t = i (i + 1) / 2 + j
+  int64_t ii = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (ii * (ii + 1) / 2 > t) --ii;
+  while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+  i = (int)ii;
+  j = (int)(t - ii * (ii + 1) / 2);
+}
+
+// trailing update: A[ib, jb] -= L[ib, kb] L[jb, kb]^T for kb < jb <= ib
+__global__ __launch_bounds__(256) void k_chol_update(double *A, int64_t n, int kb) {
+  __shared__ double As[TB][TB + 1];
+  __shared__ double Bs[TB][TB + 1];
+  int i, j;
+  tri_index(blockIdx.x, i, j);
+  int ib = kb + 1 + i, jb = kb + 1 + j;
+  load_tile(A, n, ib, kb, false, As);
+  load_tile(A, n, jb, kb, true, Bs);
+  __syncthreads();
+  double acc[4][4] = {};
+  tile_mac(acc, As, Bs);
+  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) {
+      int64_t r = (int64_t)ib * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
+      if (r < n && cc < n) A[r * n + cc] -= acc[p][q];
+    }
+}
+
+// W[jb, jb] = L[jb, jb]^-1 (one workgroup of 64 threads per diagonal tile)
+__global__ __launch_bounds__(64) void k_trtri_diag(const double *Lm, double *W, int64_t n) {
+  __shared__ double Lk[TB][TB + 1];
+  __shared__ double X[TB][TB + 1];
+  int64_t o = (int64_t)blockIdx.x * TB;
+  int m = (int)min((int64_t)TB, n - o);
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) Lk[t / m][t % m] = Lm[(o + t / m) * n + o + t % m];
+  __syncthreads();
+  int cc = threadIdx.x;
+  if (cc < m) {
+    for (int r = 0; r < m; ++r) {
+      if (r < cc) { X[r][cc] = 0.0; continue; }
+      double acc = (r == cc) ? 1.0 : 0.0;
+      for (int k = cc; k < r; ++k) acc -= Lk[r][k] * X[k][cc];
+      X[r][cc] = acc / Lk[r][r];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) W[(o + t / m) * n + o + t % m] = X[t / m][t % m];
+}
+
+// block row ib of W = L^-1: W[ib, jb] = -W[ib, ib] sum_{k=jb}^{ib-1} L[ib, k] W[k, jb], jb < ib
+__global__ __launch_bounds__(256) void k_trtri_row(const double *Lm, double *W, int64_t n, int ib) {
+  __shared__ double As[TB][TB + 1];
+  __shared__ double Bs[TB][TB + 1];
+  int jb = blockIdx.x;
+  double acc[4][4] = {};
+  for (int k = jb; k < ib; ++k) {
+    __syncthreads();
+    load_tile(Lm, n, ib, k, false, As);
+    load_tile(W, n, k, jb, false, Bs);
+    __syncthreads();
+    tile_mac(acc, As, Bs);
+  }
+  __syncthreads();
+  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) Bs[ty * 4 + p][tx * 4 + q] = acc[p][q];
+  load_tile(W, n, ib, ib, false, As);
+  __syncthreads();
+  double out[4][4] = {};
+  tile_mac(out, As, Bs);
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) {
+      int64_t r = (int64_t)ib * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
+      if (r < n && cc < n) W[r * n + cc] = -out[p][q];
+    }
+}
+
+// X[ib, jb] = sum_{k>=ib} W[k, ib]^T W[k, jb] for jb <= ib; mirrored to X[jb, ib]
+__global__ __launch_bounds__(256) void k_lauum(const double *W, double *X, int64_t n, int nb) {
+  __shared__ double As[TB][TB + 1];
+  __shared__ double Bs[TB][TB + 1];
+  int ib, jb;
+  tri_index(blockIdx.x, ib, jb);
+  double acc[4][4] = {};
+  for (int k = ib; k < nb; ++k) {
+    __syncthreads();
+    load_tile(W, n, k, ib, true, As);
+    load_tile(W, n, k, jb, false, Bs);
+    __syncthreads();
+    tile_mac(acc, As, Bs);
+  }
+  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q) {
+      int64_t r = (int64_t)ib * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
+      if (r < n && cc < n) {
+        X[r * n + cc] = acc[p][q];
+        X[cc * n + r] = acc[p][q];
+      }
+    }
+}
+
+__global__ void k_zero_upper(double *W, int64_t n) {
+  int64_t r = blockIdx.x;
+  for (int64_t j = r + 1 + threadIdx.x; j < n; j += blockDim.x) W[r * n + j] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_single_inverse(const int64_t *rp, const int32_t *col, const double *val,
+                                                        int n, double *scratch, double *inv, int *bad) {
+  gather_block(rp, col, val, nullptr, n, scratch);
+  if (!cholesky_inplace(scratch, n)) {
+    if (threadIdx.x == 0) atomicMin(bad, 0);
+    return;
+  }
+  inverse_from_factor(scratch, n, inv);
+}
+
+void factor_coarsest(Ctx &c, Level &L) {
+  hipStream_t s = c.stream;
+  int64_t n = L.nfree;
+  if (n > 60000) fail(MG_ERR_LIMIT, "coarsest level has %lld unknowns (limit 60000 for the dense solver)",
+                      (long long)n);
+  L.cinv.alloc(n * n);
+  DBuf<int> bad;
+  bad.alloc(1);
+  int init = 2147483647;
+  MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
+  DBuf<double> Lm;
+  Lm.alloc(n * n);
+  if (n <= 512) {
+    k_single_inverse<<<1, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, (int)n, Lm, L.cinv, bad);
+    MG_LAUNCH_CHECK();
+  } else {
+    k_dense_from_csr<<<(unsigned)n, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, n, Lm);
+    MG_LAUNCH_CHECK();
+    int nb = (int)((n + TB - 1) / TB);
+    for (int kb = 0; kb < nb; ++kb) {
+      k_chol_diag<<<1, 256, 0, s>>>(Lm, n, kb, bad);
+      MG_LAUNCH_CHECK();
+      int rest = nb - kb - 1;
+      if (rest > 0) {
+        k_chol_panel<<<rest, 64, 0, s>>>(Lm, n, kb);
+        MG_LAUNCH_CHECK();
+        int64_t tiles = (int64_t)rest * (rest + 1) / 2;
+        k_chol_update<<<(unsigned)tiles, 256, 0, s>>>(Lm, n, kb);
+        MG_LAUNCH_CHECK();
+      }
+    }
+    int hb0 = 0;
+    MG_HIP(hipMemcpyAsync(&hb0, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (hb0 != 2147483647) fail(MG_ERR_NOT_SPD, "coarsest operator: non-positive pivot at row %d", hb0);
+    DBuf<double> W;
+    W.alloc(n * n);
+    k_zero_upper<<<(unsigned)n, 256, 0, s>>>(W, n);
+    MG_LAUNCH_CHECK();
+    k_trtri_diag<<<nb, 64, 0, s>>>(Lm, W, n);
+    MG_LAUNCH_CHECK();
+    for (int ib = 1; ib < nb; ++ib) {
+      k_trtri_row<<<ib, 256, 0, s>>>(Lm, W, n, ib);
+      MG_LAUNCH_CHECK();
+    }
+    int64_t tiles = (int64_t)nb * (nb + 1) / 2;
+    k_lauum<<<(unsigned)tiles, 256, 0, s>>>(W, L.cinv, n, nb);
+    MG_LAUNCH_CHECK();
+  }
+  int hb = 0;
+  MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "coarsest operator is not positive definite");
+}
+
+}  // namespace mg

@@ -1,0 +1,233 @@
+// Local-correction subdomains (paper Sec. 4.1, Sec. 4.4 eq. identify).
+//
+// Omega_b = cells with gamma < tau (flags computed on the GPU).  The integer
+// graph work over the flagged region runs on the host: components of Omega_b
+// under "shares a vertex" (each started from its lowest cell id), growth by
+// `layers` vertex layers, and under the MERGE policy the union of grown sets
+// that share a vertex, so that subdomains have pairwise disjoint closures.
+// Patches are ordered by their smallest cell id.  B_d = the free DOFs of the
+// patch's cells (gathered from the device DOF map), ascending.  Colours: greedy
+// in patch order over the "shares a DOF" conflict graph (MERGE gives one).
+#include <algorithm>
+#include <numeric>
+#include <unordered_map>
+
+#include "devutil.h"
+
+namespace mg {
+
+__global__ void k_gather_cell_free_dofs(const int32_t *cells, int64_t n, const int32_t *cell_dofs, int nloc,
+                                        const int32_t *free_index, int32_t *out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nloc) return;
+  int64_t k = t / nloc;
+  int j = (int)(t - k * nloc);
+  out[t] = free_index[cell_dofs[(int64_t)cells[k] * nloc + j]];
+}
+
+void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
+  hipStream_t s = c.stream;
+  Patches &P = L.patch;
+  std::vector<uint8_t> flags;
+  download(flags, L.flags.p, (size_t)L.nc, s);
+  std::vector<int32_t> flagged;
+  for (int64_t i = 0; i < L.nc; ++i)
+    if (flags[i]) flagged.push_back((int32_t)i);
+  L.nflagged = (int64_t)flagged.size();
+  P.n = 0;
+  P.ncolour = 0;
+  P.maxn = 0;
+  P.total = 0;
+  P.colour_first.assign(1, 0);
+  P.h_ptr.assign(1, 0);
+  P.h_dofs.clear();
+  P.h_colour.clear();
+  if (flagged.empty() || !c.opt.local_correction) return;
+
+  const int nvert = L.dim + 1;
+  const int32_t *cells = m.cells;
+  // vertex -> cells
+  std::vector<int64_t> vptr(L.nv + 1, 0);
+  for (int64_t i = 0; i < L.nc * nvert; ++i) vptr[cells[i] + 1]++;
+  for (int64_t v = 0; v < L.nv; ++v) vptr[v + 1] += vptr[v];
+  std::vector<int32_t> vcell(vptr[L.nv]);
+  {
+    std::vector<int64_t> cur(vptr.begin(), vptr.end() - 1);
+    for (int64_t cc = 0; cc < L.nc; ++cc)
+      for (int a = 0; a < nvert; ++a) vcell[cur[cells[cc * nvert + a]]++] = (int32_t)cc;
+  }
+  // components of Omega_b
+  std::vector<int32_t> stamp(L.nc, -1);
+  std::vector<std::vector<int32_t>> comps;
+  for (int32_t c0 : flagged) {
+    if (stamp[c0] >= 0) continue;
+    int id = (int)comps.size();
+    std::vector<int32_t> comp, queue{c0};
+    stamp[c0] = id;
+    for (size_t qi = 0; qi < queue.size(); ++qi) {
+      int32_t cc = queue[qi];
+      comp.push_back(cc);
+      for (int a = 0; a < nvert; ++a) {
+        int32_t v = cells[(int64_t)cc * nvert + a];
+        for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+          int32_t nb = vcell[k];
+          if (flags[nb] && stamp[nb] < 0) {
+            stamp[nb] = id;
+            queue.push_back(nb);
+          }
+        }
+      }
+    }
+    std::sort(comp.begin(), comp.end());
+    comps.push_back(std::move(comp));
+  }
+  // vertex-layer growth
+  std::vector<int32_t> mark(L.nc, -1), vmark(L.nv, -1);
+  std::vector<std::vector<int32_t>> grown(comps.size());
+  int epoch = 0;
+  for (size_t p = 0; p < comps.size(); ++p) {
+    std::vector<int32_t> cur = comps[p];
+    ++epoch;
+    for (int32_t cc : cur) mark[cc] = epoch;
+    for (int layer = 0; layer < c.layers; ++layer) {
+      std::vector<int32_t> add;
+      for (int32_t cc : cur)
+        for (int a = 0; a < nvert; ++a) {
+          int32_t v = cells[(int64_t)cc * nvert + a];
+          if (vmark[v] == epoch) continue;
+          vmark[v] = epoch;
+          for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k)
+            if (mark[vcell[k]] != epoch) {
+              mark[vcell[k]] = epoch;
+              add.push_back(vcell[k]);
+            }
+        }
+      cur.insert(cur.end(), add.begin(), add.end());
+    }
+    std::sort(cur.begin(), cur.end());
+    grown[p] = std::move(cur);
+  }
+  // merge grown sets sharing a vertex (union-find)
+  std::vector<std::vector<int32_t>> sets;
+  if (c.opt.patch_policy == MG_PATCH_MERGE) {
+    std::vector<int> parent(grown.size());
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int a) {
+      while (parent[a] != a) {
+        parent[a] = parent[parent[a]];
+        a = parent[a];
+      }
+      return a;
+    };
+    std::vector<int32_t> owner(L.nv, -1);
+    for (size_t p = 0; p < grown.size(); ++p)
+      for (int32_t cc : grown[p])
+        for (int a = 0; a < nvert; ++a) {
+          int32_t v = cells[(int64_t)cc * nvert + a];
+          if (owner[v] < 0) {
+            owner[v] = (int32_t)p;
+          } else {
+            int ra = find(owner[v]), rb = find((int)p);
+            if (ra != rb) parent[std::max(ra, rb)] = std::min(ra, rb);
+          }
+        }
+    std::unordered_map<int, size_t> slot;
+    for (size_t p = 0; p < grown.size(); ++p) {
+      int r = find((int)p);
+      auto it = slot.find(r);
+      if (it == slot.end()) {
+        slot[r] = sets.size();
+        sets.push_back(grown[p]);
+      } else {
+        auto &dst = sets[it->second];
+        dst.insert(dst.end(), grown[p].begin(), grown[p].end());
+      }
+    }
+    for (auto &st : sets) {
+      std::sort(st.begin(), st.end());
+      st.erase(std::unique(st.begin(), st.end()), st.end());
+    }
+  } else {
+    sets = grown;
+  }
+  std::stable_sort(sets.begin(), sets.end(),
+                   [](const std::vector<int32_t> &a, const std::vector<int32_t> &b) { return a[0] < b[0]; });
+  // DOF sets from the device DOF map
+  std::vector<int32_t> allcells;
+  for (auto &st : sets) allcells.insert(allcells.end(), st.begin(), st.end());
+  DBuf<int32_t> dcells, dout;
+  upload(dcells, allcells.data(), allcells.size(), s);
+  dout.alloc(allcells.size() * L.nloc);
+  k_gather_cell_free_dofs<<<grid_for((int64_t)allcells.size() * L.nloc, 256), 256, 0, s>>>(
+      dcells, (int64_t)allcells.size(), L.cell_dofs, L.nloc, L.free_index, dout);
+  MG_LAUNCH_CHECK();
+  std::vector<int32_t> fd;
+  download(fd, dout.p, allcells.size() * L.nloc, s);
+  std::vector<std::vector<int32_t>> dofs;
+  size_t pos = 0;
+  for (auto &st : sets) {
+    std::vector<int32_t> d;
+    for (size_t k = 0; k < st.size() * L.nloc; ++k)
+      if (fd[pos + k] >= 0) d.push_back(fd[pos + k]);
+    pos += st.size() * L.nloc;
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    if (!d.empty()) dofs.push_back(std::move(d));
+  }
+  // greedy colouring over shared DOFs
+  std::unordered_map<int32_t, std::vector<int>> owners;
+  std::vector<int> colour(dofs.size(), 0);
+  int ncol = 0;
+  for (size_t p = 0; p < dofs.size(); ++p) {
+    std::vector<char> used;
+    for (int32_t d : dofs[p]) {
+      auto it = owners.find(d);
+      if (it == owners.end()) continue;
+      for (int q : it->second) {
+        if ((size_t)colour[q] >= used.size()) used.resize(colour[q] + 1, 0);
+        used[colour[q]] = 1;
+      }
+    }
+    int col = 0;
+    while ((size_t)col < used.size() && used[col]) ++col;
+    colour[p] = col;
+    ncol = std::max(ncol, col + 1);
+    for (int32_t d : dofs[p]) owners[d].push_back((int)p);
+  }
+  // canonical-order export arrays
+  P.n = (int)dofs.size();
+  P.ncolour = ncol;
+  P.h_ptr.assign(P.n + 1, 0);
+  for (int p = 0; p < P.n; ++p) {
+    P.h_ptr[p + 1] = P.h_ptr[p] + (int32_t)dofs[p].size();
+    P.h_dofs.insert(P.h_dofs.end(), dofs[p].begin(), dofs[p].end());
+    P.h_colour.push_back(colour[p]);
+    P.maxn = std::max(P.maxn, (int)dofs[p].size());
+  }
+  P.total = P.h_ptr[P.n];
+  // kernel order: by colour, then canonical id
+  std::vector<int> order(P.n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return colour[a] < colour[b]; });
+  std::vector<int32_t> kptr(P.n + 1, 0), kdofs;
+  std::vector<int64_t> off(P.n, 0);
+  P.colour_first.assign(ncol + 1, P.n);
+  int64_t acc = 0;
+  for (int k = 0; k < P.n; ++k) {
+    int p = order[k];
+    if (k == 0 || colour[order[k - 1]] != colour[p]) P.colour_first[colour[p]] = k;
+    kptr[k + 1] = kptr[k] + (int32_t)dofs[p].size();
+    kdofs.insert(kdofs.end(), dofs[p].begin(), dofs[p].end());
+    off[k] = acc;
+    acc += (int64_t)dofs[p].size() * (int64_t)dofs[p].size();
+  }
+  P.colour_first[ncol] = P.n;
+  P.h_kptr = kptr;
+  upload(P.ptr, kptr.data(), kptr.size(), s);
+  upload(P.dofs, kdofs.data(), kdofs.size(), s);
+  upload(P.inv_off, off.data(), off.size(), s);
+  P.inv64.alloc(acc);
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace mg

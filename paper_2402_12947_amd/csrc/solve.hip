@@ -1,0 +1,421 @@
+// Solve-phase kernels: the hot path of every V-cycle and CG iteration.
+//
+// * SELL-C-sigma sparse products (C = 64, one wavefront lane per row): the
+//   column indices and values of the 64 rows of a slice are read as
+//   contiguous 256/512-byte lines, the source vector is gathered.  Blocks are
+//   renumbered so that each of the 8 XCDs of the MI355X processes one
+//   contiguous range of slices, which keeps the gathered neighbour entries in
+//   that XCD's L2.
+// * The Chebyshev-Jacobi step of the global smoother S_g (paper Sec. 3.2,
+//   Sec. 5; classical Chebyshev acceleration on D^-1 A) is one fused pass:
+//   r = D^-1 (b - A x), d = c_d d + c_r r, x' = x + d.
+// * Local correction S_c (Sec. 4.1): patch-row residuals, then one workgroup
+//   per patch applies the precomputed inverse of A^[d] (dense product) and
+//   adds the correction to its own DOFs; patches of one colour share no DOF.
+// * Coarsest level: dense product with the precomputed inverse (FP64).
+// * CG vector updates and deterministic two-stage inner products.
+#include "mg_internal.h"
+
+namespace mg {
+
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  // hardware dispatches block b to XCD b % 8; give XCD x a contiguous range
+  int64_t per = nb / 8, rem = nb % 8, x = b % 8;
+  int64_t start = x * per + (x < rem ? x : rem);
+  return start + b / 8;
+}
+
+template <class T>
+__device__ inline T sell_row(const int64_t *__restrict__ sptr, const int32_t *__restrict__ col,
+                             const T *__restrict__ val, const T *__restrict__ x, int64_t sl, int lane) {
+  int64_t base = sptr[sl];
+  int w = (int)((sptr[sl + 1] - base) >> 6);
+  const int32_t *cp = col + base + lane;
+  const T *vp = val + base + lane;
+  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  int j = 0;
+  for (; j + 3 < w; j += 4) {
+    int c0 = cp[(j + 0) * 64], c1 = cp[(j + 1) * 64], c2 = cp[(j + 2) * 64], c3 = cp[(j + 3) * 64];
+    T v0 = vp[(j + 0) * 64], v1 = vp[(j + 1) * 64], v2 = vp[(j + 2) * 64], v3 = vp[(j + 3) * 64];
+    a0 += v0 * x[c0];
+    a1 += v1 * x[c1];
+    a2 += v2 * x[c2];
+    a3 += v3 * x[c3];
+  }
+  for (; j < w; ++j) a0 += vp[j * 64] * x[cp[j * 64]];
+  return (a0 + a1) + (a2 + a3);
+}
+
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, const int64_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
+                                                   const T *__restrict__ val, const T *__restrict__ x,
+                                                   T *__restrict__ y, const T *__restrict__ b) {
+  int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  int64_t pos = blk * 256 + threadIdx.x;
+  int64_t sl = pos >> 6;
+  if (sl >= nslices) return;
+  T acc = sell_row(sptr, col, val, x, sl, (int)(pos & 63));
+  int32_t row = perm[pos];
+  if (row < 0) return;
+  if (MODE == SPMV_SET) y[row] = acc;
+  else if (MODE == SPMV_ADD) y[row] += acc;
+  else y[row] = b[row] - acc;
+}
+
+template <class T>
+static const T *sell_vals(const Sell &S);
+template <>
+const double *sell_vals<double>(const Sell &S) { return S.v64.p; }
+template <>
+const float *sell_vals<float>(const Sell &S) { return S.v32.p; }
+
+static inline unsigned sell_grid(const Sell &S) { return (unsigned)((S.nslices * 64 + 255) / 256); }
+
+template <class T>
+void sell_spmv(hipStream_t s, const Sell &S, const T *x, T *y, int mode, const T *b) {
+  if (S.nslices == 0) return;
+  const T *v = sell_vals<T>(S);
+  unsigned g = sell_grid(S);
+  if (mode == SPMV_SET)
+    k_sell_spmv<T, SPMV_SET><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, x, y, b);
+  else if (mode == SPMV_ADD)
+    k_sell_spmv<T, SPMV_ADD><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, x, y, b);
+  else
+    k_sell_spmv<T, SPMV_RESID><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, x, y, b);
+  MG_LAUNCH_CHECK();
+}
+template void sell_spmv<double>(hipStream_t, const Sell &, const double *, double *, int, const double *);
+template void sell_spmv<float>(hipStream_t, const Sell &, const float *, float *, int, const float *);
+
+// ---------------------------------------------------------------------------
+// Chebyshev-Jacobi step
+// ---------------------------------------------------------------------------
+template <class T, int FIRST>
+__global__ __launch_bounds__(256) void k_cheb(int64_t nslices, const int64_t *__restrict__ sptr,
+                                              const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
+                                              const T *__restrict__ val, const T *__restrict__ dinv,
+                                              const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ xout,
+                                              T *__restrict__ d, T c_d, T c_r) {
+  int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  int64_t pos = blk * 256 + threadIdx.x;
+  int64_t sl = pos >> 6;
+  if (sl >= nslices) return;
+  T acc = sell_row(sptr, col, val, x, sl, (int)(pos & 63));
+  int32_t row = perm[pos];
+  if (row < 0) return;
+  T r = dinv[row] * (b[row] - acc);
+  T dn = FIRST ? c_r * r : c_d * d[row] + c_r * r;
+  d[row] = dn;
+  xout[row] = x[row] + dn;
+}
+
+template <class T>
+void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T *x, T *xout, T *d, int first,
+               double c_d, double c_r) {
+  const T *v = sell_vals<T>(S);
+  unsigned g = sell_grid(S);
+  if (first)
+    k_cheb<T, 1><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+  else
+    k_cheb<T, 0><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+  MG_LAUNCH_CHECK();
+}
+template void cheb_step<double>(hipStream_t, const Sell &, const double *, const double *, const double *, double *,
+                                double *, int, double, double);
+template void cheb_step<float>(hipStream_t, const Sell &, const float *, const float *, const float *, float *,
+                               float *, int, double, double);
+
+// ---------------------------------------------------------------------------
+// local correction
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_patch_residual(int64_t k0, int64_t k1, const int32_t *__restrict__ dofs,
+                                 const int32_t *__restrict__ iperm, const int64_t *__restrict__ sptr,
+                                 const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ b,
+                                 const T *__restrict__ u, T *__restrict__ res) {
+  int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= k1) return;
+  int32_t row = dofs[k];
+  int64_t pos = iperm[row];
+  int64_t sl = pos >> 6;
+  int lane = (int)(pos & 63);
+  int64_t base = sptr[sl];
+  int w = (int)((sptr[sl + 1] - base) >> 6);
+  T acc = 0;
+  for (int j = 0; j < w; ++j) acc += val[base + j * 64 + lane] * u[col[base + j * 64 + lane]];
+  res[k] = b[row] - acc;
+}
+
+template <class T>
+void patch_residual(hipStream_t s, const Sell &S, const Patches &pt, int colour, const T *b, const T *u, T *res) {
+  int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
+  int64_t k0 = pt.h_kptr[p0], k1 = pt.h_kptr[p1];
+  if (k1 <= k0) return;
+  int g = (int)((k1 - k0 + 255) / 256);
+  k_patch_residual<T><<<g, 256, 0, s>>>(k0, k1, pt.dofs, S.iperm, S.slice_ptr, S.col, sell_vals<T>(S), b, u, res);
+  MG_LAUNCH_CHECK();
+}
+template void patch_residual<double>(hipStream_t, const Sell &, const Patches &, int, const double *,
+                                     const double *, double *);
+template void patch_residual<float>(hipStream_t, const Sell &, const Patches &, int, const float *, const float *,
+                                    float *);
+
+template <class T>
+__global__ __launch_bounds__(256) void k_patch_apply(int p0, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ dofs,
+                                                     const int64_t *__restrict__ off, const T *__restrict__ inv,
+                                                     const T *__restrict__ res, T *__restrict__ u) {
+  extern __shared__ unsigned char smem[];
+  T *r = reinterpret_cast<T *>(smem);
+  int p = p0 + blockIdx.x;
+  int k0 = ptr[p], n = ptr[p + 1] - k0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) r[j] = res[k0 + j];
+  __syncthreads();
+  const T *M = inv + off[p];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T e0 = 0, e1 = 0;
+    int j = 0;
+    for (; j + 1 < n; j += 2) {
+      e0 += M[(int64_t)j * n + i] * r[j];
+      e1 += M[(int64_t)(j + 1) * n + i] * r[j + 1];
+    }
+    if (j < n) e0 += M[(int64_t)j * n + i] * r[j];
+    u[dofs[k0 + i]] += e0 + e1;
+  }
+}
+
+template <class T>
+void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *u) {
+  int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
+  if (p1 <= p0) return;
+  const T *inv = std::is_same<T, double>::value ? (const T *)pt.inv64.p : (const T *)pt.inv32.p;
+  size_t shm = (size_t)pt.maxn * sizeof(T);
+  k_patch_apply<T><<<p1 - p0, 256, shm, s>>>(p0, pt.ptr, pt.dofs, pt.inv_off, inv, res, u);
+  MG_LAUNCH_CHECK();
+}
+template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *);
+template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *);
+
+// ---------------------------------------------------------------------------
+// coarsest: y = M x with the dense symmetric inverse (FP64 arithmetic)
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_part(int64_t n, int64_t chunk, const double *__restrict__ M,
+                                                    const T *__restrict__ x, double *__restrict__ part) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
+  if (i >= n) return;
+  double a0 = 0, a1 = 0;
+  int64_t j = j0;
+  for (; j + 1 < j1; j += 2) {
+    a0 += M[j * n + i] * (double)x[j];
+    a1 += M[(j + 1) * n + i] * (double)x[j + 1];
+  }
+  if (j < j1) a0 += M[j * n + i] * (double)x[j];
+  part[(int64_t)blockIdx.y * n + i] = a0 + a1;
+}
+template <class T>
+__global__ void k_dense_finish(int64_t n, int nsplit, const double *__restrict__ part, T *__restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0;
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+  y[i] = (T)s;
+}
+
+static int dense_split(int64_t n) {
+  int64_t rows = (n + 255) / 256;
+  int64_t want = (2048 + rows - 1) / rows;
+  int64_t maxs = (n + 63) / 64;
+  int64_t sp = want < maxs ? want : maxs;
+  return (int)(sp < 1 ? 1 : sp);
+}
+
+template <class T>
+void dense_symv(hipStream_t s, int64_t n, const double *M, const T *x, T *y, double *part) {
+  int nsplit = dense_split(n);
+  int64_t chunk = (n + nsplit - 1) / nsplit;
+  dim3 g((unsigned)((n + 255) / 256), (unsigned)nsplit);
+  k_dense_part<T><<<g, 256, 0, s>>>(n, chunk, M, x, part);
+  MG_LAUNCH_CHECK();
+  k_dense_finish<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, nsplit, part, y);
+  MG_LAUNCH_CHECK();
+}
+template void dense_symv<double>(hipStream_t, int64_t, const double *, const double *, double *, double *);
+template void dense_symv<float>(hipStream_t, int64_t, const double *, const float *, float *, double *);
+
+int64_t dense_part_size(int64_t n) { return (int64_t)dense_split(n) * n; }
+
+// ---------------------------------------------------------------------------
+// vector kernels
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T *x, int64_t n, T v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+template <class T>
+void fill(hipStream_t s, T *x, int64_t n, T v) {
+  if (n <= 0) return;
+  k_fill<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, v);
+  MG_LAUNCH_CHECK();
+}
+template void fill<double>(hipStream_t, double *, int64_t, double);
+template void fill<float>(hipStream_t, float *, int64_t, float);
+
+template <class A, class B>
+__global__ void k_convert(const A *x, B *y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (B)x[i];
+}
+template <class A, class B>
+void convert(hipStream_t s, const A *x, B *y, int64_t n) {
+  if (n <= 0) return;
+  k_convert<A, B><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, y, n);
+  MG_LAUNCH_CHECK();
+}
+template void convert<double, float>(hipStream_t, const double *, float *, int64_t);
+template void convert<float, double>(hipStream_t, const float *, double *, int64_t);
+template void convert<double, double>(hipStream_t, const double *, double *, int64_t);
+template void convert<float, float>(hipStream_t, const float *, float *, int64_t);
+
+void copy64(hipStream_t s, const double *x, double *y, int64_t n) { convert<double, double>(s, x, y, n); }
+
+template <class T>
+__global__ void k_add(T *y, const T *x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+void add64(hipStream_t s, double *y, const double *x, int64_t n) {
+  k_add<double><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(y, x, n);
+  MG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// inner products: per-block partial sums, then one block sums them in order
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+int dot_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+__global__ __launch_bounds__(256) void k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
+                                             double *__restrict__ part) {
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += x[i] * y[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+void dot_partials(hipStream_t s, const double *x, const double *y, int64_t n, double *part, int nblocks) {
+  k_dot<<<nblocks, 256, 0, s>>>(x, y, n, part);
+  MG_LAUNCH_CHECK();
+}
+__global__ __launch_bounds__(256) void k_finish(const double *part, int nb, double *out) {
+  double s = 0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+void finish_sum(hipStream_t s, const double *part, int nblocks, double *out) {
+  k_finish<<<1, 256, 0, s>>>(part, nblocks, out);
+  MG_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// CG: scalars live on the device.  scal[]: 0 rho=r.z  1 p.q  2 alpha  3 r.r
+// 4 rho_new  5 beta  6 breakdown flag
+// ---------------------------------------------------------------------------
+__global__ void k_cg_alpha(double *scal) {
+  double pq = scal[1];
+  bool bad = !(pq > 0.0) || !isfinite(pq) || !isfinite(scal[0]);
+  scal[2] = bad ? 0.0 : scal[0] / pq;
+  if (bad) scal[6] = 1.0;
+}
+void cg_alpha(hipStream_t s, double *scal) {
+  k_cg_alpha<<<1, 1, 0, s>>>(scal);
+  MG_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_cg_xr(double *__restrict__ x, double *__restrict__ r,
+                                               const double *__restrict__ p, const double *__restrict__ q,
+                                               const double *__restrict__ scal, int64_t n, double *__restrict__ part) {
+  double a = scal[2];
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] += a * p[i];
+    double ri = r[i] - a * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+void cg_update_xr(hipStream_t s, double *x, double *r, const double *p, const double *q, const double *scal,
+                  int64_t n, double *part, int nblocks) {
+  k_cg_xr<<<nblocks, 256, 0, s>>>(x, r, p, q, scal, n, part);
+  MG_LAUNCH_CHECK();
+}
+
+__global__ void k_cg_beta(double *scal) {
+  double rn = scal[4];
+  bool bad = !isfinite(rn) || scal[0] == 0.0;
+  scal[5] = bad ? 0.0 : rn / scal[0];
+  scal[0] = rn;
+  if (bad) scal[6] = 1.0;
+}
+void cg_beta(hipStream_t s, double *scal) {
+  k_cg_beta<<<1, 1, 0, s>>>(scal);
+  MG_LAUNCH_CHECK();
+}
+
+__global__ void k_cg_p(double *__restrict__ p, const double *__restrict__ z, const double *__restrict__ scal,
+                       int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i] + scal[5] * p[i];
+}
+void cg_update_p(hipStream_t s, double *p, const double *z, const double *scal, int64_t n) {
+  k_cg_p<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, z, scal, n);
+  MG_LAUNCH_CHECK();
+}
+
+// q = A p (FP64 SELL) with partial sums of p.q
+__global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, const int64_t *__restrict__ sptr,
+                                                  const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
+                                                  const double *__restrict__ val, const double *__restrict__ p,
+                                                  double *__restrict__ q, double *__restrict__ part) {
+  int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  int64_t pos = blk * 256 + threadIdx.x;
+  int64_t sl = pos >> 6;
+  double contrib = 0;
+  if (sl < nslices) {
+    double acc = sell_row(sptr, col, val, p, sl, (int)(pos & 63));
+    int32_t row = perm[pos];
+    if (row >= 0) {
+      q[row] = acc;
+      contrib = acc * p[row];
+    }
+  }
+  contrib = block_sum(contrib);
+  if (threadIdx.x == 0) part[blk] = contrib;
+}
+int spmv_dot_blocks(const Sell &S) { return (int)sell_grid(S); }
+void spmv_dot(hipStream_t s, const Sell &S, const double *p, double *q, double *part) {
+  k_spmv_dot<<<sell_grid(S), 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, S.v64, p, q, part);
+  MG_LAUNCH_CHECK();
+}
+
+}  // namespace mg

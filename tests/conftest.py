@@ -3,6 +3,10 @@ import sys
 
 import pytest
 
+# torch bundles a HIP runtime with the same soname as the system one; import it
+# before anything loads libmgpcg.so so that the process holds one runtime.
+import torch  # noqa: F401,E402
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
