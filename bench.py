@@ -1,0 +1,217 @@
+"""Benchmark: DOFs solved per second by global-local MG-preconditioned CG.
+
+Workload (default): 2D Poisson on a 1025x1025 jittered triangulation of the
+unit square with 256 clusters of 1-8 degraded cells, P2 elements (4.2M DOFs),
+Dirichlet on y = 0, 1, four non-nested coarse levels (513^2 ... 65^2 vertex
+grids), combined smoother S_c -> Chebyshev-Jacobi(2) -> S_c with the adjusted
+lambda_max, V(2,2) cycle, CG to rtol 1e-8, FP64 on the GPU.
+
+A step is one MG-PCG solve of one synthetic right-hand side (uniform [-1, 1],
+seeded, resident in HBM before the timed region) with the hierarchy already
+set up; setup time is reported separately.  value = total DOFs solved / time.
+The level-0 Chebyshev-Jacobi kernel is timed with HIP events on the library's
+stream during the timed steps for the roofline entry.  Extra arms (plain
+smoother, mixed precision) are reported as extra fields.  The CPU baseline is
+the oracle on a bounded sample (the same recipe at 1/8 of the size per side).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (meshgen recipe, degree, scale, layers, rtol)
+    "square_1025_p2": ("square_1025", 2, 1, 1, 1e-8),
+    "square_1025_p3": ("square_1025", 3, 1, 1, 1e-8),
+    "cube_129_p1": ("cube_129", 1, 1, 1, 1e-8),
+    "cube_129_p2": ("cube_129", 2, 1, 1, 1e-8),
+    "square_p1_4k": ("square_p1_4k", 1, 1, 2, 1e-10),
+}
+PEAK_HBM_GBS = 8000.0
+CHEB_KERNEL = "k_cheb"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("solve.hip", "mg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2402_12947_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str, precision: str):
+    """HBM bytes per launch of the Chebyshev kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"cheb_step_{workload}_{precision}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local=True, timing=False,
+            use_graph=False, seed0=1000, sigma=0):
+    import torch
+
+    from paper_2402_12947_amd import Solver
+    t0 = time.perf_counter()
+    s = Solver(meshes, degree=degree, tau=0.1, layers=layers, precision=precision,
+               local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma)
+    setup_s = time.perf_counter() - t0
+    n = s.n_free(0)
+    bs = [torch.as_tensor(_rhs(n, seed0 + k)).cuda() for k in range(steps + warmup)]
+    us = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(steps + warmup)]
+    its = []
+    for k in range(warmup):
+        st = s.pcg(bs[k], us[k], rtol, 1000)
+        its.append(st["iterations"])
+    if timing:
+        s.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(warmup, warmup + steps):
+        stats.append(s.pcg(bs[k], us[k], rtol, 1000))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = {"n": n, "setup_s": setup_s, "elapsed_s": elapsed, "iterations": [x["iterations"] for x in stats],
+           "converged": all(x["converged"] for x in stats),
+           "true_rel_residual": max(x["true_rel_residual"] for x in stats),
+           "levels": [s.level_info(l) for l in range(s.n_levels)]}
+    if timing:
+        launches, total_ms = s.kernel_time()
+        out["cheb_launches"] = launches
+        out["cheb_avg_ms"] = total_ms / max(launches, 1)
+        out["cheb_bytes"] = s.cheb_bytes()
+        s.enable_kernel_timing(False)
+    s.close()
+    return out
+
+
+def _rhs(n, seed):
+    import meshgen
+    return meshgen.random_rhs(n, seed)
+
+
+def cpu_baseline(recipe, degree, layers, rtol, scale, budget_s=12.0):
+    import meshgen
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        ctx = None
+    meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
+    H = oracle.Hierarchy(meshes, tau=0.1, layers=layers, opts=oracle.Options(degree=degree))
+    n = H.levels[0].A.shape[0]
+    solved, t0 = 0, time.perf_counter()
+    its = []
+    while True:
+        _, it, conv, _ = H.pcg(_rhs(n, 5000 + solved), rtol, 1000)
+        its.append(it)
+        solved += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or solved >= 50:
+            break
+    if ctx is not None:
+        ctx.unregister() if hasattr(ctx, "unregister") else None
+    return {"value": n * solved / el, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{recipe} recipe at 1/{scale} size per side (P{degree}, {n} DOFs, "
+                      f"{len(meshes)} levels), {solved} full MG-PCG solves to rtol {rtol:g}, setup untimed, "
+                      f"iterations {its[0]}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="square_1025_p2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--arms", default="gl,plain,mixed", help="comma list of gl, plain, mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the V-cycle from a hipGraph")
+    ap.add_argument("--sigma", type=int, default=0, help="SELL sorting window (0 = library's choice)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU (single-GPU build); "
+                                   f"--gpus {args.gpus} is not supported"}))
+        sys.exit(2)
+    import torch
+    import meshgen
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    recipe, degree, scale, layers, rtol = WORKLOADS[args.workload]
+    meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
+    arms = args.arms.split(",")
+    main_arm = run_arm(meshes, degree, layers, rtol, args.steps, args.warmup, precision=args.precision,
+                       local=True, timing=True, use_graph=args.graph, sigma=args.sigma)
+    n = main_arm["n"]
+    value = n * args.steps / main_arm["elapsed_s"]
+    extra = {}
+    if "plain" in arms:
+        p = run_arm(meshes, degree, layers, rtol, max(1, args.steps // 2), 1, precision="fp64", local=False)
+        extra["plain_fp64"] = {"dofs_per_s": p["n"] * len(p["iterations"]) / p["elapsed_s"],
+                               "iterations": p["iterations"][0], "setup_s": round(p["setup_s"], 3),
+                               "true_rel_residual": p["true_rel_residual"]}
+    if "mixed" in arms and args.precision == "fp64":
+        mx = run_arm(meshes, degree, layers, rtol, args.steps, 1, precision="mixed", local=True)
+        extra["global_local_mixed"] = {"dofs_per_s": mx["n"] * len(mx["iterations"]) / mx["elapsed_s"],
+                                       "iterations": mx["iterations"][0], "setup_s": round(mx["setup_s"], 3),
+                                       "true_rel_residual": mx["true_rel_residual"]}
+    avg_ms = main_arm["cheb_avg_ms"]
+    achieved = main_arm["cheb_bytes"] / (avg_ms * 1e-3) / 1e9
+    traffic = read_traffic(args.workload, args.precision)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": CHEB_KERNEL, "avg_launch_ms": round(avg_ms, 5),
+                "algorithmic_bytes_per_launch": main_arm["cheb_bytes"], "launches": main_arm["cheb_launches"]}
+    line = {
+        "metric": "DOFs solved/sec to rtol 1e-8 (MG-PCG, global-local smoother)",
+        "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * main_arm["elapsed_s"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-in-f64",
+        "data": "synthetic (seeded meshes and right-hand sides)",
+        "config": {"workload": args.workload, "dofs": n, "levels": len(meshes), "rtol": rtol,
+                   "smoother": "S_c -> Chebyshev-Jacobi(2) -> S_c, V(2,2), adjusted lambda_max",
+                   "precision": args.precision, "iterations": main_arm["iterations"][0],
+                   "setup_s": round(main_arm["setup_s"], 3),
+                   "true_rel_residual": main_arm["true_rel_residual"],
+                   "patches_level0": main_arm["levels"][0]["n_patches"],
+                   "coarsest_dofs": main_arm["levels"][-1]["n_free"], "graph": bool(args.graph),
+                   "sell_sigma_level0": main_arm["levels"][0]["sell_sigma"],
+                   "sell_padding_level0": round(main_arm["levels"][0]["sell_stored"]
+                                                / main_arm["levels"][0]["nnz"], 4)},
+        "roofline": roofline,
+        "arms": extra,
+    }
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

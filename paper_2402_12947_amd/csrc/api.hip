@@ -266,20 +266,6 @@ static void validate_mesh(const mg_mesh &m, int dim, int l) {
     if (!std::isfinite(m.coords[i])) fail(MG_ERR_MESH, "level %d: non-finite coordinate", l);
 }
 
-static int choose_sigma(Ctx &c, const Csr &A) {
-  if (c.opt.sell_sigma >= 1) return c.opt.sell_sigma;
-  // padding of the unsorted layout; sort rows within windows when it is large
-  std::vector<int64_t> rp;
-  download(rp, A.rowptr.p, (size_t)A.nrows + 1, c.stream);
-  int64_t stored = 0;
-  for (int64_t s0 = 0; s0 < A.nrows; s0 += SELL_C) {
-    int64_t w = 0;
-    for (int64_t r = s0; r < std::min(A.nrows, s0 + SELL_C); ++r) w = std::max(w, rp[r + 1] - rp[r]);
-    stored += w * SELL_C;
-  }
-  return (double)stored > 1.08 * (double)A.nnz ? 1024 : 1;
-}
-
 mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_threshold, int32_t patch_layers,
                    const mg_options *opt, mg_ctx **out) {
   if (out) *out = nullptr;
@@ -334,9 +320,17 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     for (int l = 0; l < n_levels; ++l) {
       auto t0 = now();
       Level &L = c.lv[l];
-      compute_dinv(c, L);
-      build_sell(c, L.A, L.S, choose_sigma(c, L.A), mixed && !L.coarsest);
+      solve_order(c, L, L.coarsest ? 1 : c.opt.sell_sigma, mixed && !L.coarsest);
+      permute_patches(c, L);
+      L.setup_ms += ms(t0, now());
+    }
+    for (int l = 0; l < n_levels; ++l) {
+      auto t0 = now();
+      Level &L = c.lv[l];
       if (!L.coarsest) {
+        build_transfer_sell(c, L, c.lv[l + 1], mixed);
+        L.Pc = Csr();
+        L.Rc = Csr();
         factor_patches(c, L);
         estimate_eigenvalues(c, L);
       } else {
@@ -351,6 +345,8 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     c.p.alloc(n0);
     c.q.alloc(n0);
     c.ax.alloc(n0);
+    c.bpos.alloc(n0);
+    c.xpos.alloc(n0);
     int64_t pb = std::max<int64_t>(1024, spmv_dot_blocks(c.lv[0].S));
     c.partial.alloc(pb);
     c.scal.alloc(8);
@@ -380,15 +376,15 @@ mg_status mg_smooth(mg_ctx *h, int32_t level, const double *b, double *u, int32_
   if (nu < 0) fail(MG_ERR_ARG, "nu must be >= 0");
   Level &L = c.lv[level];
   if (c.opt.precision == MG_MIXED) {
-    convert<double, float>(c.stream, b, L.w32[W_B], L.nfree);
-    convert<double, float>(c.stream, u, L.w32[W_U], L.nfree);
+    gather_perm<double, float>(c.stream, b, L.perm, L.w32[W_B], L.nfree);
+    gather_perm<double, float>(c.stream, u, L.perm, L.w32[W_U], L.nfree);
     smooth<float>(c, level, L.w32[W_B], L.w32[W_U], nu);
-    convert<float, double>(c.stream, L.w32[W_U], u, L.nfree);
+    scatter_perm<float, double>(c.stream, L.w32[W_U], L.perm, u, L.nfree);
   } else {
-    copy64(c.stream, b, L.w64[W_B], L.nfree);
-    copy64(c.stream, u, L.w64[W_U], L.nfree);
+    gather_perm<double, double>(c.stream, b, L.perm, L.w64[W_B], L.nfree);
+    gather_perm<double, double>(c.stream, u, L.perm, L.w64[W_U], L.nfree);
     smooth<double>(c, level, L.w64[W_B], L.w64[W_U], nu);
-    copy64(c.stream, L.w64[W_U], u, L.nfree);
+    scatter_perm<double, double>(c.stream, L.w64[W_U], L.perm, u, L.nfree);
   }
   MG_HIP(hipStreamSynchronize(c.stream));
   return MG_OK;
@@ -403,9 +399,12 @@ mg_status mg_vcycle(mg_ctx *h, const double *b, double *u) {
   if (b == u) fail(MG_ERR_ARG, "b must not alias u");
   Level &L0 = c.lv[0];
   // V(b, u) = u + B (b - A u): the cycle is affine in its initial guess
-  sell_spmv<double>(c.stream, L0.S, u, c.r, SPMV_RESID, b);
+  gather_perm<double, double>(c.stream, b, L0.perm, c.bpos, L0.nfree);
+  gather_perm<double, double>(c.stream, u, L0.perm, c.xpos, L0.nfree);
+  sell_spmv<double>(c.stream, L0.S, c.xpos, c.r, SPMV_RESID, c.bpos);
   precondition(c);
-  add64(c.stream, u, c.z, L0.nfree);
+  add64(c.stream, c.xpos, c.z, L0.nfree);
+  scatter_perm<double, double>(c.stream, c.xpos, L0.perm, u, L0.nfree);
   MG_HIP(hipStreamSynchronize(c.stream));
   return MG_OK;
   MG_API_END(cp)
@@ -431,10 +430,12 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
   } guard{e0, e1};
   MG_HIP(hipEventRecord(e0, s));
   double *scal = c.scal.p;
+  double *x = c.xpos.p;
   fill<double>(s, scal, 8, 0.0);
-  fill<double>(s, u, n, 0.0);
-  copy64(s, b, c.r, n);
-  dot_to(c, b, b, n, scal + 7);
+  fill<double>(s, x, n, 0.0);
+  gather_perm<double, double>(s, b, L0.perm, c.bpos, n);
+  copy64(s, c.bpos, c.r, n);
+  dot_to(c, c.bpos, c.bpos, n, scal + 7);
   double bb = read_scalar(c, scal + 7);
   double bnorm = std::sqrt(bb);
   std::vector<double> hist{bnorm > 0 ? 1.0 : 0.0};
@@ -452,7 +453,7 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
       spmv_dot(s, L0.S, c.p, c.q, c.partial);
       finish_sum(s, c.partial, sb, scal + 1);
       cg_alpha(s, scal);
-      cg_update_xr(s, u, c.r, c.p, c.q, scal, n, c.partial, nb);
+      cg_update_xr(s, x, c.r, c.p, c.q, scal, n, c.partial, nb);
       finish_sum(s, c.partial, nb, scal + 3);
       MG_HIP(hipMemcpyAsync(c.h_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
       MG_HIP(hipStreamSynchronize(s));
@@ -474,6 +475,7 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
       cg_update_p(s, c.p, c.z, scal, n);
     }
   }
+  scatter_perm<double, double>(s, x, L0.perm, u, n);
   MG_HIP(hipEventRecord(e1, s));
   MG_HIP(hipEventSynchronize(e1));
   float tms = 0;
@@ -481,7 +483,7 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
   // true residual in FP64
   double true_rel = 0;
   if (bnorm > 0) {
-    sell_spmv<double>(s, L0.S, u, c.ax, SPMV_RESID, b);
+    sell_spmv<double>(s, L0.S, x, c.ax, SPMV_RESID, c.bpos);
     dot_to(c, c.ax, c.ax, n, scal + 7);
     true_rel = std::sqrt(read_scalar(c, scal + 7)) / bnorm;
   }

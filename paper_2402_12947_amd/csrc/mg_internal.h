@@ -84,8 +84,11 @@ void download(std::vector<T> &h, const T *d, size_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// sliced ELL (SELL-C-sigma) with C = 64: one wavefront lane per row; inside a
-// slice the entries of column position j of the 64 rows are contiguous.
+// sliced ELL (SELL-C) with C = 64: one wavefront lane per row; inside a slice
+// the entries of column position j of the 64 rows are contiguous.  Rows keep
+// the order of the matrix they are built from: the length sorting of
+// SELL-C-sigma is applied to the unknowns beforehand (Level::perm), so that
+// row p of the layout is unknown p of every vector.
 // ---------------------------------------------------------------------------
 constexpr int SELL_C = 64;
 
@@ -93,8 +96,7 @@ struct Sell {
   int64_t nrows = 0, ncols = 0, nslices = 0, stored = 0;
   int sigma = 1;
   DBuf<int64_t> slice_ptr;  // [nslices + 1]
-  DBuf<int32_t> perm;       // [nslices * 64] row at each position, -1 = empty
-  DBuf<int32_t> iperm;      // [nrows] position of each row
+  DBuf<int32_t> perm;       // [nslices * 64] row at each position (identity), -1 = padding
   DBuf<int32_t> col;        // [stored]
   DBuf<double> v64;         // [stored] (FP64 copy)
   DBuf<float> v32;          // [stored] (FP32 copy, mixed precision)
@@ -115,7 +117,8 @@ struct Patches {
   std::vector<int32_t> h_ptr, h_dofs, h_colour;  // canonical order (export)
   std::vector<int32_t> h_kptr;     // [n + 1] kernel-order offsets (host copy)
   DBuf<int32_t> ptr;          // [n + 1] kernel order
-  DBuf<int32_t> dofs;         // [total]
+  DBuf<int32_t> dofs;         // [total] solve-order positions of the patch DOFs
+  DBuf<int32_t> dofs_canon;   // [total] canonical free ids (factorisation)
   DBuf<int64_t> inv_off;      // [n] offset of the patch inverse (n_d^2 entries)
   DBuf<double> inv64;
   DBuf<float> inv32;
@@ -136,9 +139,12 @@ struct Level {
   DBuf<uint8_t> flags;
   int64_t nflagged = 0;
   double gamma_min = 0;
-  // operator
+  // operator: A in canonical free order (export, Galerkin product, patch
+  // gathers); S is A in solve order: unknown p of every solve-phase vector is
+  // canonical unknown perm[p], rows sorted by length inside sigma windows
   Csr A;
   Sell S;
+  DBuf<int32_t> perm, iperm;   // solve order <-> canonical free order
   DBuf<double> dinv64;
   DBuf<float> dinv32;
   // transfer to the next coarser level (absent on the coarsest)
@@ -173,8 +179,8 @@ struct Ctx {
   bool own_stream = false;
   std::vector<Level> lv;
   std::string err;
-  // PCG work (FP64, level 0)
-  DBuf<double> r, z, p, q, ax;
+  // PCG work (FP64, level 0, solve order)
+  DBuf<double> r, z, p, q, ax, bpos, xpos;
   DBuf<double> partial;        // dot-product block partials
   DBuf<double> scal;           // device scalars of CG
   double *h_scal = nullptr;    // pinned host mirror
@@ -210,7 +216,9 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);
 void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,
                 bool transpose, Csr &A);
 void spgemm(Ctx &c, const Csr &A, const Csr &B, Csr &C);
-void compute_dinv(Ctx &c, Level &L);
+void solve_order(Ctx &c, Level &L, int sigma, bool want32);
+void build_transfer_sell(Ctx &c, Level &F, const Level &C, bool want32);
+void permute_patches(Ctx &c, Level &L);
 void ensure_work(Ctx &c, Level &L);
 
 // ---------------------------------------------------------------------------
@@ -239,6 +247,11 @@ void fill(hipStream_t s, T *x, int64_t n, T v);
 template <class A, class B>
 void convert(hipStream_t s, const A *x, B *y, int64_t n);
 void copy64(hipStream_t s, const double *x, double *y, int64_t n);
+// y[p] = x[perm[p]] (to solve order) and y[perm[p]] = x[p] (back)
+template <class A, class B>
+void gather_perm(hipStream_t s, const A *x, const int32_t *perm, B *y, int64_t n);
+template <class A, class B>
+void scatter_perm(hipStream_t s, const A *x, const int32_t *perm, B *y, int64_t n);
 void add64(hipStream_t s, double *y, const double *x, int64_t n);
 int64_t dense_part_size(int64_t n);
 int spmv_dot_blocks(const Sell &S);

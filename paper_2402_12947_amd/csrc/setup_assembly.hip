@@ -256,24 +256,22 @@ __global__ void k_dinv(const int64_t *rowptr, const int32_t *col, const double *
   if (d32) d32[r] = (float)(1.0 / d);
 }
 
-void compute_dinv(Ctx &c, Level &L) {
+static void dinv_of(Ctx &c, const Csr &A, DBuf<double> &d64, DBuf<float> *d32) {
   hipStream_t s = c.stream;
-  L.dinv64.alloc(L.nfree);
-  bool mixed = c.opt.precision == MG_MIXED;
-  if (mixed) L.dinv32.alloc(L.nfree);
+  d64.alloc(A.nrows);
+  if (d32) d32->alloc(A.nrows);
   DBuf<int> bad;
   bad.alloc(1);
   int init = 2147483647;
   MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
-  k_dinv<<<grid_for(L.nfree, 256), 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, L.nfree, L.dinv64,
-                                               mixed ? L.dinv32.p : nullptr, bad);
+  k_dinv<<<grid_for(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, d64, d32 ? d32->p : nullptr, bad);
   MG_LAUNCH_CHECK();
   int hb = 0;
   MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   if (hb != 2147483647)
-    fail(MG_ERR_NOT_SPD, "operator row %d has a non-positive diagonal (a coarse basis function that no "
-                         "fine DOF node sees, or a singular system)", hb);
+    fail(MG_ERR_NOT_SPD, "operator row %d (solve order) has a non-positive diagonal (a coarse basis "
+                         "function that no fine DOF node sees, or a singular system)", hb);
 }
 
 // ---------------------------------------------------------------------------
@@ -291,11 +289,6 @@ __global__ void k_sort_keys_len(const int64_t *rowptr, int64_t n, int sigma, uin
 __global__ void k_identity_perm(int32_t *perm, int64_t npos, int64_t n) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < npos) perm[p] = p < n ? (int32_t)p : -1;
-}
-
-__global__ void k_inverse_perm(const int32_t *perm, int64_t npos, int32_t *iperm) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < npos && perm[p] >= 0) iperm[perm[p]] = (int32_t)p;
 }
 
 __global__ void k_slice_width(const int64_t *rowptr, const int32_t *perm, int64_t nslices, int64_t *w64) {
@@ -333,33 +326,18 @@ __global__ void k_sell_fill(const int64_t *rowptr, const int32_t *ccol, const do
   }
 }
 
+// SELL-C layout of A with its rows in their given order (row = position); the
+// solve order (solve_order) is applied to A beforehand.
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
   hipStream_t s = c.stream;
-  if (sigma > 1 && sigma % SELL_C) fail(MG_ERR_ARG, "SELL sigma must be 1 or a multiple of 64");
+  if (sigma != 1) fail(MG_ERR_ARG, "build_sell keeps the row order (sigma must be 1)");
   S.nrows = A.nrows;
   S.ncols = A.ncols;
-  S.sigma = sigma;
+  S.sigma = 1;
   S.nslices = (A.nrows + SELL_C - 1) / SELL_C;
   int64_t npos = S.nslices * SELL_C;
   S.perm.alloc(npos);
-  if (sigma > 1) {
-    DBuf<uint64_t> k, ks;
-    DBuf<int32_t> r;
-    k.alloc(A.nrows);
-    ks.alloc(A.nrows);
-    r.alloc(A.nrows);
-    k_sort_keys_len<<<grid_for(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.nrows, sigma, k, r);
-    MG_LAUNCH_CHECK();
-    k_identity_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, A.nrows);
-    MG_LAUNCH_CHECK();
-    int64_t nwin = (A.nrows + sigma - 1) / sigma;
-    sort_pairs(s, k.p, ks.p, r.p, S.perm.p, A.nrows, 32 + bits_for((uint64_t)nwin));
-  } else {
-    k_identity_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, A.nrows);
-    MG_LAUNCH_CHECK();
-  }
-  S.iperm.alloc(A.nrows);
-  k_inverse_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, S.iperm);
+  k_identity_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, A.nrows);
   MG_LAUNCH_CHECK();
   DBuf<int64_t> w;
   w.alloc(S.nslices);
@@ -378,6 +356,135 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
 }
 
 // ---------------------------------------------------------------------------
+// solve order: rows sorted by length (descending, stable) inside windows of
+// sigma rows; the same permutation renumbers the unknowns, so every per-row
+// vector access of the solve kernels is contiguous.
+// ---------------------------------------------------------------------------
+__global__ void k_perm_rowlen(const int64_t *rp, const int32_t *perm, int64_t n, int64_t *len) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) len[p] = rp[perm[p] + 1] - rp[perm[p]];
+}
+__global__ void k_perm_fill(const int64_t *rp, const int32_t *col, const double *val, const int32_t *perm,
+                            const int32_t *iperm_cols, int64_t n, const int64_t *rp2, int32_t *col2, double *val2) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int64_t a = rp[perm[p]], b = rp[perm[p] + 1], o = rp2[p];
+  for (int64_t k = a; k < b; ++k) {
+    col2[o + k - a] = iperm_cols ? iperm_cols[col[k]] : col[k];
+    val2[o + k - a] = val[k];
+  }
+}
+__global__ void k_iperm(const int32_t *perm, int64_t n, int32_t *iperm) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) iperm[perm[p]] = (int32_t)p;
+}
+
+// B = A with rows taken in order perm and columns renumbered by iperm_cols
+static void permute_csr(Ctx &c, const Csr &A, const int32_t *perm, int64_t nrows, const int32_t *iperm_cols,
+                        int64_t ncols, Csr &B) {
+  hipStream_t s = c.stream;
+  DBuf<int64_t> len;
+  len.alloc(nrows);
+  k_perm_rowlen<<<grid_for(nrows, 256), 256, 0, s>>>(A.rowptr, perm, nrows, len);
+  MG_LAUNCH_CHECK();
+  B.nrows = nrows;
+  B.ncols = ncols;
+  B.rowptr.alloc(nrows + 1);
+  B.nnz = exclusive_scan(s, len.p, B.rowptr.p, nrows);
+  MG_HIP(hipMemcpyAsync(B.rowptr.p + nrows, &B.nnz, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  B.col.alloc(B.nnz);
+  B.val.alloc(B.nnz);
+  k_perm_fill<<<grid_for(nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, perm, iperm_cols, nrows, B.rowptr,
+                                                  B.col, B.val);
+  MG_LAUNCH_CHECK();
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+static void order_with(Ctx &c, Level &L, int sigma, bool want32) {
+  hipStream_t s = c.stream;
+  const int64_t n = L.A.nrows;
+  L.perm.alloc(n);
+  L.iperm.alloc(n);
+  if (sigma > 1) {
+    DBuf<uint64_t> k, ks;
+    DBuf<int32_t> r;
+    k.alloc(n);
+    ks.alloc(n);
+    r.alloc(n);
+    k_sort_keys_len<<<grid_for(n, 256), 256, 0, s>>>(L.A.rowptr, n, sigma, k, r);
+    MG_LAUNCH_CHECK();
+    int64_t nwin = (n + sigma - 1) / sigma;
+    sort_pairs(s, k.p, ks.p, r.p, L.perm.p, n, 32 + bits_for((uint64_t)nwin));
+  } else {
+    k_identity_perm<<<grid_for(n, 256), 256, 0, s>>>(L.perm, n, n);
+    MG_LAUNCH_CHECK();
+  }
+  k_iperm<<<grid_for(n, 256), 256, 0, s>>>(L.perm, n, L.iperm);
+  MG_LAUNCH_CHECK();
+  Csr B;
+  permute_csr(c, L.A, L.perm, n, L.iperm, n, B);
+  L.S = Sell();
+  build_sell(c, B, L.S, 1, want32);
+  L.S.sigma = sigma;
+  dinv_of(c, B, L.dinv64, want32 ? &L.dinv32 : nullptr);
+}
+
+// average time of the level's Chebyshev-step kernel in its current layout
+static double time_cheb(Ctx &c, Level &L, bool want32) {
+  hipStream_t s = c.stream;
+  const int64_t n = L.nfree;
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  float ms = 0;
+  const int reps = 5;
+  if (want32) {
+    DBuf<float> v[4];
+    for (auto &b : v) {
+      b.alloc(n);
+      fill<float>(s, b.p, n, 0.5f);
+    }
+    cheb_step<float>(s, L.S, L.dinv32, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
+    MG_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) cheb_step<float>(s, L.S, L.dinv32, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
+    MG_HIP(hipEventRecord(e1, s));
+    MG_HIP(hipEventSynchronize(e1));
+  } else {
+    DBuf<double> v[4];
+    for (auto &b : v) {
+      b.alloc(n);
+      fill<double>(s, b.p, n, 0.5);
+    }
+    cheb_step<double>(s, L.S, L.dinv64, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
+    MG_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) cheb_step<double>(s, L.S, L.dinv64, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
+    MG_HIP(hipEventRecord(e1, s));
+    MG_HIP(hipEventSynchronize(e1));
+  }
+  MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+// Solve order of a level.  sigma >= 1 is used as given; sigma == 0 lets the
+// autotuner choose: when the unsorted layout pads by more than 2 %, both the
+// unsorted layout and rows sorted inside 1024-row windows are built and the one
+// whose Chebyshev-step kernel runs faster on this GPU is kept.
+void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
+  if (sigma >= 1) {
+    order_with(c, L, sigma, want32);
+    return;
+  }
+  order_with(c, L, 1, want32);
+  if ((double)L.S.stored <= 1.02 * (double)L.A.nnz || L.nfree < 65536) return;
+  double t1 = time_cheb(c, L, want32);
+  order_with(c, L, 1024, want32);
+  double t2 = time_cheb(c, L, want32);
+  if (t1 <= t2) order_with(c, L, 1, want32);
+}
+
+// ---------------------------------------------------------------------------
 // ELL (row-major, -1 = empty) -> CSR, and its transpose
 // ---------------------------------------------------------------------------
 __global__ void k_ell_keys(const int32_t *col, const double *val, int64_t nrows, int width, uint64_t ncols,
@@ -393,6 +500,39 @@ __global__ void k_ell_keys(const int32_t *col, const double *val, int64_t nrows,
   }
   vals[t] = val[t];
   (void)nr_out;
+}
+
+__global__ void k_ell_permute(const int32_t *col, const double *val, int64_t nrows, int width,
+                              const int32_t *perm_rows, const int32_t *iperm_cols, int32_t *col2, double *val2) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * width) return;
+  int64_t p = t / width;
+  int j = (int)(t - p * width);
+  int64_t src = (int64_t)perm_rows[p] * width + j;
+  int32_t cc = col[src];
+  col2[t] = cc >= 0 ? iperm_cols[cc] : -1;
+  val2[t] = val[src];
+}
+
+void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,
+                bool transpose, Csr &A);
+
+// P and R = P^T of the transfer between fine level F and coarse level C, in the
+// two levels' solve orders
+void build_transfer_sell(Ctx &c, Level &F, const Level &C, bool want32) {
+  hipStream_t s = c.stream;
+  int64_t n = F.nfree * F.pw;
+  DBuf<int32_t> col;
+  DBuf<double> val;
+  col.alloc(n);
+  val.alloc(n);
+  k_ell_permute<<<grid_for(n, 256), 256, 0, s>>>(F.pcol, F.pval, F.nfree, F.pw, F.perm, C.iperm, col, val);
+  MG_LAUNCH_CHECK();
+  Csr Pp, Rp;
+  ell_to_csr(c, F.nfree, C.nfree, F.pw, col, val, false, Pp);
+  ell_to_csr(c, F.nfree, C.nfree, F.pw, col, val, true, Rp);
+  build_sell(c, Pp, F.P, 1, want32);
+  build_sell(c, Rp, F.R, 1, want32);
 }
 
 void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,

@@ -118,8 +118,8 @@ void factor_patches(Ctx &c, Level &L) {
   bad.alloc(1);
   int init = 2147483647;
   MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
-  k_patch_factor<<<P.n, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, P.ptr, P.dofs, P.inv_off, scratch, P.inv64,
-                                     bad);
+  k_patch_factor<<<P.n, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, P.ptr, P.dofs_canon, P.inv_off, scratch,
+                                     P.inv64, bad);
   MG_LAUNCH_CHECK();
   int hb = 0;
   MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));

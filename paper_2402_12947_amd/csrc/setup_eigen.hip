@@ -8,6 +8,9 @@
 // Ritz residual beta_(j+1) |s_j| <= tol * theta_max or after maxit steps.
 // The start vector is a fixed pseudo-random vector: SplitMix64 (Steele, Lea,
 // Flood, OOPSLA 2014) of the row index, top 53 bits mapped to [-1, 1).
+// The iteration runs in the level's solve order (a symmetric permutation of
+// the unknowns, which leaves the spectrum unchanged); the start vector is
+// indexed by the canonical unknown so that it does not depend on that order.
 // Matrix-vector products, inner products and the Gram-Schmidt sweep run on
 // the GPU; the small tridiagonal eigenproblem runs on the host (bisection on
 // the Sturm count for theta_max, inverse iteration for its eigenvector).
@@ -25,9 +28,10 @@ __device__ inline double splitmix_unit(uint64_t i) {
   return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
 }
 
-__global__ void k_lanczos_start(const uint8_t *mask, int64_t n, double *q) {
+// q[p] for solve-order unknown p = canonical unknown perm[p]
+__global__ void k_lanczos_start(const uint8_t *mask, const int32_t *perm, int64_t n, double *q) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) q[i] = (mask && !mask[i]) ? 0.0 : splitmix_unit((uint64_t)i);
+  if (i < n) q[i] = (mask && !mask[i]) ? 0.0 : splitmix_unit((uint64_t)perm[i]);
 }
 
 // t = m s q   with s = sqrt(dinv)
@@ -167,7 +171,7 @@ static double lanczos(Ctx &c, Level &L, const uint8_t *mask, int &steps) {
   const int nblk = (int)std::min<int64_t>(512, (n + 255) / 256);
   mpart.alloc((size_t)(maxit + 1) * nblk);
   const int g = grid_for(n, 256);
-  k_lanczos_start<<<g, 256, 0, s>>>(mask, n, Q);
+  k_lanczos_start<<<g, 256, 0, s>>>(mask, L.perm, n, Q);
   MG_LAUNCH_CHECK();
   double nrm = std::sqrt(host_dot(s, Q, Q, n, part, dres));
   if (nrm == 0.0) {

@@ -224,10 +224,25 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
   P.colour_first[ncol] = P.n;
   P.h_kptr = kptr;
   upload(P.ptr, kptr.data(), kptr.size(), s);
-  upload(P.dofs, kdofs.data(), kdofs.size(), s);
+  upload(P.dofs_canon, kdofs.data(), kdofs.size(), s);
   upload(P.inv_off, off.data(), off.size(), s);
   P.inv64.alloc(acc);
   MG_HIP(hipStreamSynchronize(s));
+}
+
+__global__ void k_map_dofs(const int32_t *canon, int64_t n, const int32_t *iperm, int32_t *pos) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) pos[k] = iperm[canon[k]];
+}
+
+// patch DOFs in the level's solve order (after solve_order has set iperm)
+void permute_patches(Ctx &c, Level &L) {
+  Patches &P = L.patch;
+  if (P.total == 0) return;
+  P.dofs.alloc(P.total);
+  k_map_dofs<<<grid_for(P.total, 256), 256, 0, c.stream>>>(P.dofs_canon, P.total, L.iperm, P.dofs);
+  MG_LAUNCH_CHECK();
+  MG_HIP(hipStreamSynchronize(c.stream));
 }
 
 }  // namespace mg

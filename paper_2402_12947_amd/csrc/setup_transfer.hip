@@ -187,11 +187,8 @@ void build_prolongation(Ctx &c, Level &F, const Level &C, const mg_mesh &cm) {
   MG_HIP(hipStreamSynchronize(s));
   if (hb != 2147483647)
     fail(MG_ERR_LOCATE, "free DOF %d of a fine level lies outside the next coarser mesh", hb);
-  bool mixed = c.opt.precision == MG_MIXED;
   ell_to_csr(c, F.nfree, C.nfree, F.pw, F.pcol, F.pval, false, F.Pc);
   ell_to_csr(c, F.nfree, C.nfree, F.pw, F.pcol, F.pval, true, F.Rc);
-  build_sell(c, F.Pc, F.P, 1, mixed);
-  build_sell(c, F.Rc, F.R, c.opt.sell_sigma > 1 ? c.opt.sell_sigma : 1, mixed);
 }
 
 }  // namespace mg

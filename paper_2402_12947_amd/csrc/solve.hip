@@ -1,11 +1,12 @@
 // Solve-phase kernels: the hot path of every V-cycle and CG iteration.
 //
-// * SELL-C-sigma sparse products (C = 64, one wavefront lane per row): the
-//   column indices and values of the 64 rows of a slice are read as
-//   contiguous 256/512-byte lines, the source vector is gathered.  Blocks are
-//   renumbered so that each of the 8 XCDs of the MI355X processes one
-//   contiguous range of slices, which keeps the gathered neighbour entries in
-//   that XCD's L2.
+// * SELL-C sparse products (C = 64, one wavefront lane per row): the column
+//   indices and values of the 64 rows of a slice are read as contiguous
+//   256/512-byte lines (non-temporal: they are streamed once), the source
+//   vector is gathered.  Blocks keep the hardware's round-robin spread over
+//   the 8 XCDs: renumbering them into one contiguous slice range per XCD was
+//   measured 1.6x slower on this kernel (HBM channel balance matters more than
+//   L2 reuse of the gathered vector here).
 // * The Chebyshev-Jacobi step of the global smoother S_g (paper Sec. 3.2,
 //   Sec. 5; classical Chebyshev acceleration on D^-1 A) is one fused pass:
 //   r = D^-1 (b - A x), d = c_d d + c_r r, x' = x + d.
@@ -18,13 +19,8 @@
 
 namespace mg {
 
-__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
-  // hardware dispatches block b to XCD b % 8; give XCD x a contiguous range
-  int64_t per = nb / 8, rem = nb % 8, x = b % 8;
-  int64_t start = x * per + (x < rem ? x : rem);
-  return start + b / 8;
-}
-
+// Row `lane` of slice `sl`: the matrix entries are streamed once per product,
+// so they are loaded non-temporally and leave the cache to the gathered vector.
 template <class T>
 __device__ inline T sell_row(const int64_t *__restrict__ sptr, const int32_t *__restrict__ col,
                              const T *__restrict__ val, const T *__restrict__ x, int64_t sl, int lane) {
@@ -32,35 +28,42 @@ __device__ inline T sell_row(const int64_t *__restrict__ sptr, const int32_t *__
   int w = (int)((sptr[sl + 1] - base) >> 6);
   const int32_t *cp = col + base + lane;
   const T *vp = val + base + lane;
-  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  constexpr int U = 8;  // eight independent gathers in flight per lane
+  T a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = 0;
   int j = 0;
-  for (; j + 3 < w; j += 4) {
-    int c0 = cp[(j + 0) * 64], c1 = cp[(j + 1) * 64], c2 = cp[(j + 2) * 64], c3 = cp[(j + 3) * 64];
-    T v0 = vp[(j + 0) * 64], v1 = vp[(j + 1) * 64], v2 = vp[(j + 2) * 64], v3 = vp[(j + 3) * 64];
-    a0 += v0 * x[c0];
-    a1 += v1 * x[c1];
-    a2 += v2 * x[c2];
-    a3 += v3 * x[c3];
+  for (; j + U - 1 < w; j += U) {
+    int c[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = __builtin_nontemporal_load(cp + (j + u) * 64);
+      v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] += v[u] * x[c[u]];
   }
-  for (; j < w; ++j) a0 += vp[j * 64] * x[cp[j * 64]];
-  return (a0 + a1) + (a2 + a3);
+  for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[__builtin_nontemporal_load(cp + j * 64)];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
+// Unknowns are numbered in the operator's row order (solve order), so the row
+// of a SELL position is the position itself; positions past nrows are padding.
 template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, const int64_t *__restrict__ sptr,
-                                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
-                                                   const T *__restrict__ val, const T *__restrict__ x,
-                                                   T *__restrict__ y, const T *__restrict__ b) {
-  int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nrows, const int64_t *__restrict__ sptr,
+                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                   const T *__restrict__ x, T *__restrict__ y,
+                                                   const T *__restrict__ b) {
+  int64_t blk = blockIdx.x;
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
   T acc = sell_row(sptr, col, val, x, sl, (int)(pos & 63));
-  int32_t row = perm[pos];
-  if (row < 0) return;
-  if (MODE == SPMV_SET) y[row] = acc;
-  else if (MODE == SPMV_ADD) y[row] += acc;
-  else y[row] = b[row] - acc;
+  if (pos >= nrows) return;
+  if (MODE == SPMV_SET) y[pos] = acc;
+  else if (MODE == SPMV_ADD) y[pos] += acc;
+  else y[pos] = b[pos] - acc;
 }
 
 template <class T>
@@ -78,11 +81,11 @@ void sell_spmv(hipStream_t s, const Sell &S, const T *x, T *y, int mode, const T
   const T *v = sell_vals<T>(S);
   unsigned g = sell_grid(S);
   if (mode == SPMV_SET)
-    k_sell_spmv<T, SPMV_SET><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, x, y, b);
+    k_sell_spmv<T, SPMV_SET><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, x, y, b);
   else if (mode == SPMV_ADD)
-    k_sell_spmv<T, SPMV_ADD><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, x, y, b);
+    k_sell_spmv<T, SPMV_ADD><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, x, y, b);
   else
-    k_sell_spmv<T, SPMV_RESID><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, x, y, b);
+    k_sell_spmv<T, SPMV_RESID><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, x, y, b);
   MG_LAUNCH_CHECK();
 }
 template void sell_spmv<double>(hipStream_t, const Sell &, const double *, double *, int, const double *);
@@ -92,22 +95,21 @@ template void sell_spmv<float>(hipStream_t, const Sell &, const float *, float *
 // Chebyshev-Jacobi step
 // ---------------------------------------------------------------------------
 template <class T, int FIRST>
-__global__ __launch_bounds__(256) void k_cheb(int64_t nslices, const int64_t *__restrict__ sptr,
-                                              const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
-                                              const T *__restrict__ val, const T *__restrict__ dinv,
-                                              const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ xout,
-                                              T *__restrict__ d, T c_d, T c_r) {
-  int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_cheb(int64_t nslices, int64_t nrows, const int64_t *__restrict__ sptr,
+                                              const int32_t *__restrict__ col, const T *__restrict__ val,
+                                              const T *__restrict__ dinv, const T *__restrict__ b,
+                                              const T *__restrict__ x, T *__restrict__ xout, T *__restrict__ d,
+                                              T c_d, T c_r) {
+  int64_t blk = blockIdx.x;
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
   T acc = sell_row(sptr, col, val, x, sl, (int)(pos & 63));
-  int32_t row = perm[pos];
-  if (row < 0) return;
-  T r = dinv[row] * (b[row] - acc);
-  T dn = FIRST ? c_r * r : c_d * d[row] + c_r * r;
-  d[row] = dn;
-  xout[row] = x[row] + dn;
+  if (pos >= nrows) return;
+  T r = dinv[pos] * (b[pos] - acc);
+  T dn = FIRST ? c_r * r : c_d * d[pos] + c_r * r;
+  d[pos] = dn;
+  xout[pos] = x[pos] + dn;
 }
 
 template <class T>
@@ -116,9 +118,9 @@ void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T 
   const T *v = sell_vals<T>(S);
   unsigned g = sell_grid(S);
   if (first)
-    k_cheb<T, 1><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+    k_cheb<T, 1><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
   else
-    k_cheb<T, 0><<<g, 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+    k_cheb<T, 0><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
   MG_LAUNCH_CHECK();
 }
 template void cheb_step<double>(hipStream_t, const Sell &, const double *, const double *, const double *, double *,
@@ -131,20 +133,19 @@ template void cheb_step<float>(hipStream_t, const Sell &, const float *, const f
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void k_patch_residual(int64_t k0, int64_t k1, const int32_t *__restrict__ dofs,
-                                 const int32_t *__restrict__ iperm, const int64_t *__restrict__ sptr,
-                                 const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ b,
-                                 const T *__restrict__ u, T *__restrict__ res) {
+                                 const int64_t *__restrict__ sptr, const int32_t *__restrict__ col,
+                                 const T *__restrict__ val, const T *__restrict__ b, const T *__restrict__ u,
+                                 T *__restrict__ res) {
   int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= k1) return;
-  int32_t row = dofs[k];
-  int64_t pos = iperm[row];
+  int32_t pos = dofs[k];
   int64_t sl = pos >> 6;
-  int lane = (int)(pos & 63);
+  int lane = pos & 63;
   int64_t base = sptr[sl];
   int w = (int)((sptr[sl + 1] - base) >> 6);
   T acc = 0;
   for (int j = 0; j < w; ++j) acc += val[base + j * 64 + lane] * u[col[base + j * 64 + lane]];
-  res[k] = b[row] - acc;
+  res[k] = b[pos] - acc;
 }
 
 template <class T>
@@ -153,7 +154,7 @@ void patch_residual(hipStream_t s, const Sell &S, const Patches &pt, int colour,
   int64_t k0 = pt.h_kptr[p0], k1 = pt.h_kptr[p1];
   if (k1 <= k0) return;
   int g = (int)((k1 - k0 + 255) / 256);
-  k_patch_residual<T><<<g, 256, 0, s>>>(k0, k1, pt.dofs, S.iperm, S.slice_ptr, S.col, sell_vals<T>(S), b, u, res);
+  k_patch_residual<T><<<g, 256, 0, s>>>(k0, k1, pt.dofs, S.slice_ptr, S.col, sell_vals<T>(S), b, u, res);
   MG_LAUNCH_CHECK();
 }
 template void patch_residual<double>(hipStream_t, const Sell &, const Patches &, int, const double *,
@@ -282,6 +283,33 @@ template void convert<float, float>(hipStream_t, const float *, float *, int64_t
 
 void copy64(hipStream_t s, const double *x, double *y, int64_t n) { convert<double, double>(s, x, y, n); }
 
+template <class A, class B>
+__global__ void k_gather_perm(const A *x, const int32_t *perm, B *y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (B)x[perm[i]];
+}
+template <class A, class B>
+__global__ void k_scatter_perm(const A *x, const int32_t *perm, B *y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[perm[i]] = (B)x[i];
+}
+template <class A, class B>
+void gather_perm(hipStream_t s, const A *x, const int32_t *perm, B *y, int64_t n) {
+  if (n <= 0) return;
+  k_gather_perm<A, B><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, perm, y, n);
+  MG_LAUNCH_CHECK();
+}
+template <class A, class B>
+void scatter_perm(hipStream_t s, const A *x, const int32_t *perm, B *y, int64_t n) {
+  if (n <= 0) return;
+  k_scatter_perm<A, B><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, perm, y, n);
+  MG_LAUNCH_CHECK();
+}
+template void gather_perm<double, double>(hipStream_t, const double *, const int32_t *, double *, int64_t);
+template void gather_perm<double, float>(hipStream_t, const double *, const int32_t *, float *, int64_t);
+template void scatter_perm<double, double>(hipStream_t, const double *, const int32_t *, double *, int64_t);
+template void scatter_perm<float, double>(hipStream_t, const float *, const int32_t *, double *, int64_t);
+
 template <class T>
 __global__ void k_add(T *y, const T *x, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -393,20 +421,19 @@ void cg_update_p(hipStream_t s, double *p, const double *z, const double *scal, 
 }
 
 // q = A p (FP64 SELL) with partial sums of p.q
-__global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, const int64_t *__restrict__ sptr,
-                                                  const int32_t *__restrict__ perm, const int32_t *__restrict__ col,
-                                                  const double *__restrict__ val, const double *__restrict__ p,
-                                                  double *__restrict__ q, double *__restrict__ part) {
-  int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, int64_t nrows, const int64_t *__restrict__ sptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  const double *__restrict__ p, double *__restrict__ q,
+                                                  double *__restrict__ part) {
+  int64_t blk = blockIdx.x;
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
   double contrib = 0;
   if (sl < nslices) {
     double acc = sell_row(sptr, col, val, p, sl, (int)(pos & 63));
-    int32_t row = perm[pos];
-    if (row >= 0) {
-      q[row] = acc;
-      contrib = acc * p[row];
+    if (pos < nrows) {
+      q[pos] = acc;
+      contrib = acc * p[pos];
     }
   }
   contrib = block_sum(contrib);
@@ -414,7 +441,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, const int64_t
 }
 int spmv_dot_blocks(const Sell &S) { return (int)sell_grid(S); }
 void spmv_dot(hipStream_t s, const Sell &S, const double *p, double *q, double *part) {
-  k_spmv_dot<<<sell_grid(S), 256, 0, s>>>(S.nslices, S.slice_ptr, S.perm, S.col, S.v64, p, q, part);
+  k_spmv_dot<<<sell_grid(S), 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, S.v64, p, q, part);
   MG_LAUNCH_CHECK();
 }
 
