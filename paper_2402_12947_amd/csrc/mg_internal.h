@@ -120,6 +120,9 @@ struct Patches {
   DBuf<int32_t> dofs;         // [total] solve-order positions of the patch DOFs
   DBuf<int32_t> dofs_canon;   // [total] canonical free ids (factorisation)
   DBuf<int64_t> inv_off;      // [n] offset of the patch inverse (n_d^2 entries)
+  // work items of the patch apply: 64-row chunks of the patches, kernel order
+  DBuf<int32_t> chunk_patch, chunk_row;
+  std::vector<int> colour_chunk_first;  // [ncolour + 1]
   DBuf<double> inv64;
   DBuf<float> inv32;
 };

@@ -222,6 +222,19 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
     acc += (int64_t)dofs[p].size() * (int64_t)dofs[p].size();
   }
   P.colour_first[ncol] = P.n;
+  std::vector<int32_t> cpatch, crow;
+  P.colour_chunk_first.assign(ncol + 1, 0);
+  for (int col = 0; col < ncol; ++col) {
+    P.colour_chunk_first[col] = (int)cpatch.size();
+    for (int k = P.colour_first[col]; k < P.colour_first[col + 1]; ++k)
+      for (int i0 = 0; i0 < kptr[k + 1] - kptr[k]; i0 += 64) {
+        cpatch.push_back(k);
+        crow.push_back(i0);
+      }
+  }
+  P.colour_chunk_first[ncol] = (int)cpatch.size();
+  upload(P.chunk_patch, cpatch.data(), cpatch.size(), s);
+  upload(P.chunk_row, crow.data(), crow.size(), s);
   P.h_kptr = kptr;
   upload(P.ptr, kptr.data(), kptr.size(), s);
   upload(P.dofs_canon, kdofs.data(), kdofs.size(), s);

@@ -162,37 +162,48 @@ template void patch_residual<double>(hipStream_t, const Sell &, const Patches &,
 template void patch_residual<float>(hipStream_t, const Sell &, const Patches &, int, const float *, const float *,
                                     float *);
 
+// One workgroup per 64-row chunk of a patch: e = A_d^-1 r on those rows, with
+// the four wavefronts splitting the inner dimension, then u[B_d] += e.
 template <class T>
-__global__ __launch_bounds__(256) void k_patch_apply(int p0, const int32_t *__restrict__ ptr,
+__global__ __launch_bounds__(256) void k_patch_apply(int c0, const int32_t *__restrict__ chunk_patch,
+                                                     const int32_t *__restrict__ chunk_row,
+                                                     const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ dofs,
                                                      const int64_t *__restrict__ off, const T *__restrict__ inv,
                                                      const T *__restrict__ res, T *__restrict__ u) {
   extern __shared__ unsigned char smem[];
-  T *r = reinterpret_cast<T *>(smem);
-  int p = p0 + blockIdx.x;
+  T *red = reinterpret_cast<T *>(smem);  // [4][64]
+  T *r = red + 256;                      // [n]
+  int b = c0 + blockIdx.x;
+  int p = chunk_patch[b], i0 = chunk_row[b];
   int k0 = ptr[p], n = ptr[p + 1] - k0;
   for (int j = threadIdx.x; j < n; j += blockDim.x) r[j] = res[k0 + j];
   __syncthreads();
+  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = i0 + lane;
+  int jlo = (w * n) >> 2, jhi = ((w + 1) * n) >> 2;
   const T *M = inv + off[p];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    T e0 = 0, e1 = 0;
-    int j = 0;
-    for (; j + 1 < n; j += 2) {
-      e0 += M[(int64_t)j * n + i] * r[j];
-      e1 += M[(int64_t)(j + 1) * n + i] * r[j + 1];
+  T a0 = 0, a1 = 0;
+  if (i < n) {
+    int j = jlo;
+    for (; j + 1 < jhi; j += 2) {
+      a0 += M[(int64_t)j * n + i] * r[j];
+      a1 += M[(int64_t)(j + 1) * n + i] * r[j + 1];
     }
-    if (j < n) e0 += M[(int64_t)j * n + i] * r[j];
-    u[dofs[k0 + i]] += e0 + e1;
+    if (j < jhi) a0 += M[(int64_t)j * n + i] * r[j];
   }
+  red[threadIdx.x] = a0 + a1;
+  __syncthreads();
+  if (w == 0 && i < n) u[dofs[k0 + i]] += (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
 }
 
 template <class T>
 void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *u) {
-  int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
-  if (p1 <= p0) return;
+  int c0 = pt.colour_chunk_first[colour], c1 = pt.colour_chunk_first[colour + 1];
+  if (c1 <= c0) return;
   const T *inv = std::is_same<T, double>::value ? (const T *)pt.inv64.p : (const T *)pt.inv32.p;
-  size_t shm = (size_t)pt.maxn * sizeof(T);
-  k_patch_apply<T><<<p1 - p0, 256, shm, s>>>(p0, pt.ptr, pt.dofs, pt.inv_off, inv, res, u);
+  size_t shm = (size_t)(pt.maxn + 256) * sizeof(T);
+  k_patch_apply<T><<<c1 - c0, 256, shm, s>>>(c0, pt.chunk_patch, pt.chunk_row, pt.ptr, pt.dofs, pt.inv_off, inv,
+                                             res, u);
   MG_LAUNCH_CHECK();
 }
 template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *);
