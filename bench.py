@@ -63,16 +63,22 @@ def read_traffic(workload: str, precision: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local=True, timing=False,
             use_graph=False, seed0=1000, sigma=0):
     import torch
 
     from paper_2402_12947_amd import Solver
+    log(f"setup precision={precision} local={local}")
     t0 = time.perf_counter()
     s = Solver(meshes, degree=degree, tau=0.1, layers=layers, precision=precision,
                local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma)
     setup_s = time.perf_counter() - t0
     n = s.n_free(0)
+    log(f"setup done in {setup_s:.2f} s, {n} DOFs; solving")
     bs = [torch.as_tensor(_rhs(n, seed0 + k)).cuda() for k in range(steps + warmup)]
     us = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(steps + warmup)]
     its = []

@@ -314,9 +314,11 @@ CONFIGS = {
     "square_1025": dict(kind="square", sides=[1024, 512, 256, 128, 64], jitter=0.2,
                         fine_single=0, clusters=[256, 64, 16, 4, 2],
                         dirichlet=("y0", "y1")),
-    # 3D 129^3 Kuhn grid with 2000 cap/sliver tets, coarse 65^3, 33^3, 17^3.
-    "cube_129": dict(kind="cube", sides=[128, 64, 32, 16], jitter=0.15,
-                     slivers=[2000, 250, 32, 4], dirichlet=("x0", "x1")),
+    # 3D 129^3 Kuhn grid with 2000 cap/sliver tets, coarse 65^3, 33^3, 17^3, 9^3
+    # (halving the intervals per side until the coarsest P2 system has a few
+    # thousand unknowns).
+    "cube_129": dict(kind="cube", sides=[128, 64, 32, 16, 8], jitter=0.15,
+                     slivers=[2000, 250, 32, 4, 1], dirichlet=("x0", "x1")),
 }
 
 

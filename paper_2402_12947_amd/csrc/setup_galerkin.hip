@@ -11,14 +11,17 @@
 
 namespace mg {
 
-constexpr int HT = 1024;          // hash slots per row
-constexpr int HT_MAX_FILL = 768;  // rows with more distinct columns are rejected
+// Hash tables of HT slots accept rows of up to 3 HT / 4 distinct columns.  Rows
+// are first tried with a 1024-slot table; rows that overflow it are redone with
+// a 4096-slot table (3D P2 Galerkin rows reach several hundred columns).
+template <int HT>
+__device__ inline int hash_slot(int key) {
+  return (int)(((uint32_t)key * 2654435761u) >> 16) & (HT - 1);
+}
 
-__device__ inline int hash_slot(int key) { return (int)(((uint32_t)key * 2654435761u) >> 22) & (HT - 1); }
-
-// insert key; returns slot or -1 when the table is full
+template <int HT>
 __device__ inline int ht_insert(int *keys, int key, bool &fresh) {
-  int h = hash_slot(key);
+  int h = hash_slot<HT>(key);
   fresh = false;
   for (int probe = 0; probe < HT; ++probe) {
     int old = atomicCAS(&keys[h], -1, key);
@@ -29,11 +32,15 @@ __device__ inline int ht_insert(int *keys, int key, bool &fresh) {
   return -1;
 }
 
+// cnt[row] = distinct columns of row, or -1 if the row does not fit
+template <int HT>
 __global__ __launch_bounds__(64) void k_spgemm_count(const int64_t *arp, const int32_t *acol, const int64_t *brp,
-                                                     const int32_t *bcol, int64_t nrows, int64_t *cnt, int *overflow) {
+                                                     const int32_t *bcol, int64_t nrows, const int32_t *rows,
+                                                     int64_t *cnt) {
+  constexpr int MAXF = 3 * HT / 4;
   __shared__ int keys[HT];
   __shared__ int n_new;
-  int64_t row = blockIdx.x;
+  int64_t row = rows ? rows[blockIdx.x] : (int64_t)blockIdx.x;
   if (row >= nrows) return;
   int lane = threadIdx.x;
   for (int h = lane; h < HT; h += 64) keys[h] = -1;
@@ -44,30 +51,32 @@ __global__ __launch_bounds__(64) void k_spgemm_count(const int64_t *arp, const i
     int k = acol[ka];
     for (int64_t kb = brp[k] + lane; kb < brp[k + 1]; kb += 64) {
       bool fresh;
-      int slot = ht_insert(keys, bcol[kb], fresh);
+      int slot = ht_insert<HT>(keys, bcol[kb], fresh);
       if (slot < 0) full = true;
       if (fresh) atomicAdd(&n_new, 1);
     }
     __syncthreads();
-    if (n_new > HT_MAX_FILL) full = true;
+    if (n_new > MAXF) full = true;
     if (__syncthreads_or(full)) break;
   }
-  if (lane == 0) {
-    cnt[row] = n_new;
-    if (n_new > HT_MAX_FILL || full) atomicMax(overflow, 1);
-  }
+  if (lane == 0) cnt[row] = (full || n_new > MAXF) ? -1 : n_new;
 }
 
+template <int HT>
 __global__ __launch_bounds__(64) void k_spgemm_fill(const int64_t *arp, const int32_t *acol, const double *aval,
                                                     const int64_t *brp, const int32_t *bcol, const double *bval,
-                                                    int64_t nrows, const int64_t *crp, int32_t *ccol, double *cval) {
+                                                    int64_t nrows, const int32_t *rows, const int64_t *crp,
+                                                    int32_t *ccol, double *cval) {
+  constexpr int MAXF = 3 * HT / 4;
   __shared__ int keys[HT];
   __shared__ double vals[HT];
-  __shared__ int ckey[HT_MAX_FILL];
-  __shared__ double cv[HT_MAX_FILL];
+  __shared__ int ckey[MAXF];
+  __shared__ double cv[MAXF];
   __shared__ int ncomp;
-  int64_t row = blockIdx.x;
+  int64_t row = rows ? rows[blockIdx.x] : (int64_t)blockIdx.x;
   if (row >= nrows) return;
+  int64_t base = crp[row];
+  if (!rows && crp[row + 1] - base > MAXF) return;  // redone with the larger table
   int lane = threadIdx.x;
   for (int h = lane; h < HT; h += 64) {
     keys[h] = -1;
@@ -80,7 +89,7 @@ __global__ __launch_bounds__(64) void k_spgemm_fill(const int64_t *arp, const in
     double a = aval[ka];
     for (int64_t kb = brp[k] + lane; kb < brp[k + 1]; kb += 64) {
       bool fresh;
-      int slot = ht_insert(keys, bcol[kb], fresh);
+      int slot = ht_insert<HT>(keys, bcol[kb], fresh);
       if (slot >= 0) vals[slot] += a * bval[kb];
     }
     __syncthreads();
@@ -88,15 +97,14 @@ __global__ __launch_bounds__(64) void k_spgemm_fill(const int64_t *arp, const in
   for (int h = lane; h < HT; h += 64) {
     if (keys[h] >= 0) {
       int p = atomicAdd(&ncomp, 1);
-      if (p < HT_MAX_FILL) {
+      if (p < MAXF) {
         ckey[p] = keys[h];
         cv[p] = vals[h];
       }
     }
   }
   __syncthreads();
-  int n = ncomp < HT_MAX_FILL ? ncomp : HT_MAX_FILL;
-  int64_t base = crp[row];
+  int n = ncomp < MAXF ? ncomp : MAXF;
   for (int e = lane; e < n; e += 64) {
     int key = ckey[e], rank = 0;
     for (int f = 0; f < n; ++f) rank += ckey[f] < key ? 1 : 0;
@@ -107,29 +115,43 @@ __global__ __launch_bounds__(64) void k_spgemm_fill(const int64_t *arp, const in
 
 void spgemm(Ctx &c, const Csr &A, const Csr &B, Csr &C) {
   hipStream_t s = c.stream;
+  constexpr int SMALL = 1024, LARGE = 4096;
   if (A.ncols != B.nrows) fail(MG_ERR_ARG, "spgemm shape mismatch");
   if (A.nrows > 2147483647LL) fail(MG_ERR_LIMIT, "spgemm: too many rows");
   C.nrows = A.nrows;
   C.ncols = B.ncols;
   DBuf<int64_t> cnt;
-  DBuf<int> ovf;
   cnt.alloc(A.nrows);
-  ovf.alloc(1);
-  MG_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int), s));
-  k_spgemm_count<<<(unsigned)A.nrows, 64, 0, s>>>(A.rowptr, A.col, B.rowptr, B.col, A.nrows, cnt, ovf);
+  k_spgemm_count<SMALL><<<(unsigned)A.nrows, 64, 0, s>>>(A.rowptr, A.col, B.rowptr, B.col, A.nrows, nullptr, cnt);
   MG_LAUNCH_CHECK();
-  int hovf = 0;
-  MG_HIP(hipMemcpyAsync(&hovf, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  MG_HIP(hipStreamSynchronize(s));
-  if (hovf) fail(MG_ERR_LIMIT, "Galerkin product: a coarse row has more than %d nonzeros", HT_MAX_FILL);
+  std::vector<int64_t> hc;
+  download(hc, cnt.p, (size_t)A.nrows, s);
+  std::vector<int32_t> big;
+  for (int64_t r = 0; r < A.nrows; ++r)
+    if (hc[r] < 0) big.push_back((int32_t)r);
+  DBuf<int32_t> dbig;
+  if (!big.empty()) {
+    upload(dbig, big.data(), big.size(), s);
+    k_spgemm_count<LARGE><<<(unsigned)big.size(), 64, 0, s>>>(A.rowptr, A.col, B.rowptr, B.col, A.nrows, dbig, cnt);
+    MG_LAUNCH_CHECK();
+    std::vector<int64_t> hb;
+    download(hb, cnt.p, (size_t)A.nrows, s);
+    for (int32_t r : big)
+      if (hb[r] < 0) fail(MG_ERR_LIMIT, "Galerkin product: coarse row %d has more than %d nonzeros", r, 3 * LARGE / 4);
+  }
   C.rowptr.alloc(A.nrows + 1);
   C.nnz = exclusive_scan(s, cnt.p, C.rowptr.p, A.nrows);
   MG_HIP(hipMemcpyAsync(C.rowptr.p + A.nrows, &C.nnz, sizeof(int64_t), hipMemcpyHostToDevice, s));
   C.col.alloc(C.nnz);
   C.val.alloc(C.nnz);
-  k_spgemm_fill<<<(unsigned)A.nrows, 64, 0, s>>>(A.rowptr, A.col, A.val, B.rowptr, B.col, B.val, A.nrows,
-                                                 C.rowptr, C.col, C.val);
+  k_spgemm_fill<SMALL><<<(unsigned)A.nrows, 64, 0, s>>>(A.rowptr, A.col, A.val, B.rowptr, B.col, B.val, A.nrows,
+                                                        nullptr, C.rowptr, C.col, C.val);
   MG_LAUNCH_CHECK();
+  if (!big.empty()) {
+    k_spgemm_fill<LARGE><<<(unsigned)big.size(), 64, 0, s>>>(A.rowptr, A.col, A.val, B.rowptr, B.col, B.val,
+                                                             A.nrows, dbig, C.rowptr, C.col, C.val);
+    MG_LAUNCH_CHECK();
+  }
   MG_HIP(hipStreamSynchronize(s));
 }
 
