@@ -12,8 +12,8 @@
 //   forward/backward substitution with one thread per column of the identity.
 // * Coarsest level (large n): blocked right-looking Cholesky with 64x64 tiles
 //   (diagonal factor, panel triangular solve, trailing symmetric update), then
-//   W = L^-1 block row by block row and A^-1 = W^T W, all from 64x64x64
-//   LDS-tiled FP64 products.
+//   W = L^-1 by a right-looking block solve of L W = I, and A^-1 = W^T W, all
+//   from 64x64x64 LDS-tiled FP64 products.
 #include <cmath>
 
 #include "devutil.h"
@@ -276,32 +276,47 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double *Lm, double *W, 
   for (int t = threadIdx.x; t < m * m; t += blockDim.x) W[(o + t / m) * n + o + t % m] = X[t / m][t % m];
 }
 
-// block row ib of W = L^-1: W[ib, jb] = -W[ib, ib] sum_{k=jb}^{ib-1} L[ib, k] W[k, jb], jb < ib
-__global__ __launch_bounds__(256) void k_trtri_row(const double *Lm, double *W, int64_t n, int ib) {
+// Right-looking solve of L Y = I (Y = L^-1, lower triangular), one step per
+// block row kb: Y[kb, jb] <- Linv[kb, kb] Y[kb, jb] for jb <= kb, then
+// Y[ib, jb] -= L[ib, kb] Y[kb, jb] for ib > kb, jb <= kb.  Every tile of a step
+// is independent, so each step is one wide launch.
+__global__ __launch_bounds__(256) void k_trsm_rows(const double *Dinv, double *Y, int64_t n, int kb) {
   __shared__ double As[TB][TB + 1];
   __shared__ double Bs[TB][TB + 1];
-  int jb = blockIdx.x;
-  double acc[4][4] = {};
-  for (int k = jb; k < ib; ++k) {
-    __syncthreads();
-    load_tile(Lm, n, ib, k, false, As);
-    load_tile(W, n, k, jb, false, Bs);
-    __syncthreads();
-    tile_mac(acc, As, Bs);
-  }
+  int jb = blockIdx.x;  // 0..kb
+  load_tile(Dinv, n, kb, kb, false, As);
+  load_tile(Y, n, kb, jb, false, Bs);
   __syncthreads();
+  double acc[4][4] = {};
+  tile_mac(acc, As, Bs);
   int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) Bs[ty * 4 + p][tx * 4 + q] = acc[p][q];
-  load_tile(W, n, ib, ib, false, As);
+    for (int q = 0; q < 4; ++q) {
+      int64_t r = (int64_t)kb * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
+      if (r < n && cc < n) Y[r * n + cc] = acc[p][q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_trsm_update(const double *Lm, double *Y, int64_t n, int kb) {
+  __shared__ double As[TB][TB + 1];
+  __shared__ double Bs[TB][TB + 1];
+  int ib = kb + 1 + blockIdx.x / (kb + 1), jb = blockIdx.x % (kb + 1);
+  load_tile(Lm, n, ib, kb, false, As);
+  load_tile(Y, n, kb, jb, false, Bs);
   __syncthreads();
-  double out[4][4] = {};
-  tile_mac(out, As, Bs);
+  double acc[4][4] = {};
+  tile_mac(acc, As, Bs);
+  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   for (int p = 0; p < 4; ++p)
     for (int q = 0; q < 4; ++q) {
       int64_t r = (int64_t)ib * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
-      if (r < n && cc < n) W[r * n + cc] = -out[p][q];
+      if (r < n && cc < n) Y[r * n + cc] -= acc[p][q];
     }
+}
+
+__global__ void k_identity(double *Y, int64_t n) {
+  int64_t r = blockIdx.x;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) Y[r * n + j] = (j == r) ? 1.0 : 0.0;
 }
 
 // X[ib, jb] = sum_{k>=ib} W[k, ib]^T W[k, jb] for jb <= ib; mirrored to X[jb, ib]
@@ -327,11 +342,6 @@ __global__ __launch_bounds__(256) void k_lauum(const double *W, double *X, int64
         X[cc * n + r] = acc[p][q];
       }
     }
-}
-
-__global__ void k_zero_upper(double *W, int64_t n) {
-  int64_t r = blockIdx.x;
-  for (int64_t j = r + 1 + threadIdx.x; j < n; j += blockDim.x) W[r * n + j] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_single_inverse(const int64_t *rp, const int32_t *col, const double *val,
@@ -379,16 +389,24 @@ void factor_coarsest(Ctx &c, Level &L) {
     MG_HIP(hipMemcpyAsync(&hb0, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
     MG_HIP(hipStreamSynchronize(s));
     if (hb0 != 2147483647) fail(MG_ERR_NOT_SPD, "coarsest operator: non-positive pivot at row %d", hb0);
-    DBuf<double> W;
+    // inverses of the diagonal tiles of L, then Y = L^-1 right-looking
+    DBuf<double> Dinv, W;
+    Dinv.alloc(n * n);
     W.alloc(n * n);
-    k_zero_upper<<<(unsigned)n, 256, 0, s>>>(W, n);
+    k_trtri_diag<<<nb, 64, 0, s>>>(Lm, Dinv, n);
     MG_LAUNCH_CHECK();
-    k_trtri_diag<<<nb, 64, 0, s>>>(Lm, W, n);
+    k_identity<<<(unsigned)n, 256, 0, s>>>(W, n);
     MG_LAUNCH_CHECK();
-    for (int ib = 1; ib < nb; ++ib) {
-      k_trtri_row<<<ib, 256, 0, s>>>(Lm, W, n, ib);
+    for (int kb = 0; kb < nb; ++kb) {
+      k_trsm_rows<<<kb + 1, 256, 0, s>>>(Dinv, W, n, kb);
       MG_LAUNCH_CHECK();
+      int64_t tiles = (int64_t)(nb - kb - 1) * (kb + 1);
+      if (tiles > 0) {
+        k_trsm_update<<<(unsigned)tiles, 256, 0, s>>>(Lm, W, n, kb);
+        MG_LAUNCH_CHECK();
+      }
     }
+    Dinv.release();
     int64_t tiles = (int64_t)nb * (nb + 1) / 2;
     k_lauum<<<(unsigned)tiles, 256, 0, s>>>(W, L.cinv, n, nb);
     MG_LAUNCH_CHECK();

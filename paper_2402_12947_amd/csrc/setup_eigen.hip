@@ -53,23 +53,30 @@ __global__ void k_scale(double *y, const double *x, double a, int64_t n) {
   if (i < n) y[i] = a * x[i];
 }
 
-// partial sums of Q[k] . w for k < m: part[k * nblk + block]
+// partial sums of Q[k] . w for k < m: part[k * nblk + block]; each block
+// handles eight vectors at once (blockIdx.y) to amortise the reductions
 __global__ __launch_bounds__(256) void k_multidot(const double *Q, int64_t n, int m, const double *w, double *part,
                                                   int nblk) {
-  __shared__ double red[256];
-  for (int k = 0; k < m; ++k) {
-    double s = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256)
-      s += Q[(int64_t)k * n + i] * w[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(int64_t)k * nblk + blockIdx.x] = red[0];
+  __shared__ double red[8][256];
+  const int k0 = blockIdx.y * 8;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nblk * 256) {
+    double wi = w[i];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (k0 + q < m) s[q] += Q[(int64_t)(k0 + q) * n + i] * wi;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = s[q];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
     __syncthreads();
   }
+  if (threadIdx.x < 8 && k0 + (int)threadIdx.x < m) part[(int64_t)(k0 + threadIdx.x) * nblk + blockIdx.x] =
+      red[threadIdx.x][0];
 }
 __global__ void k_multidot_finish(const double *part, int m, int nblk, double *out) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -194,7 +201,7 @@ static double lanczos(Ctx &c, Level &L, const uint8_t *mask, int &steps) {
     MG_LAUNCH_CHECK();
     // full reorthogonalisation: w -= Q (Q^T w) over q_0..q_j
     int m = j + 1;
-    k_multidot<<<nblk, 256, 0, s>>>(Q, n, m, w, mpart, nblk);
+    k_multidot<<<dim3(nblk, (m + 7) / 8), 256, 0, s>>>(Q, n, m, w, mpart, nblk);
     MG_LAUNCH_CHECK();
     k_multidot_finish<<<(m + 255) / 256, 256, 0, s>>>(mpart, m, nblk, cvec);
     MG_LAUNCH_CHECK();
