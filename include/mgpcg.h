@@ -177,6 +177,21 @@ mg_status mg_vcycle(mg_ctx *c, const double *b, double *u);
 mg_status mg_pcg_solve(mg_ctx *c, const double *b, double *u, double rtol, int32_t maxit,
                        mg_solve_stats *st);
 
+/* Many-instance solve (the serving pattern of independent problems): solves
+ * the n_inst x nrhs systems A_i u_(i,r) = b_(i,r) of the contexts cs[i] together
+ * with the same method and stopping rule as mg_pcg_solve.  b[i * nrhs + r] and
+ * u[i * nrhs + r] are device FP64 vectors of instance i's n_free.  Every
+ * instance runs on its own context stream from its own host thread, so the
+ * instances' kernels overlap on the GPU; contexts created with use_graph = 1
+ * replay their V-cycles from captured hipGraphs.  The contexts must be
+ * distinct.  st (may be NULL) receives n_inst * nrhs records; *wall_ms (may be
+ * NULL) the wall time of the whole batch.  Returns the first error of the
+ * lowest-numbered failing instance (its message in mg_last_error(cs[i])), else
+ * MG_NOT_CONVERGED if any system did not converge, else MG_OK. */
+mg_status mg_pcg_solve_batch(mg_ctx *const *cs, int32_t n_inst, int32_t nrhs, const double *const *b,
+                             double *const *u, double rtol, int32_t maxit, mg_solve_stats *st,
+                             double *wall_ms);
+
 /* b = M f_hat restricted to the free DOFs: the consistent-mass load of nodal
  * data f_hat given at ALL n_dofs DOFs of level 0 (device FP64). */
 mg_status mg_rhs_from_nodal(mg_ctx *c, const double *f_nodal, double *b);

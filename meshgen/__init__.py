@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "square_mesh", "cube_mesh", "hierarchy", "random_rhs", "CONFIGS",
-    "orientation",
+    "orientation", "instance_batch",
 ]
 
 
@@ -353,6 +353,42 @@ def hierarchy(name: str, seed: int = 0, scale: int = 1, case: str = "fine") -> l
                 ns = max(1, ns)
             out.append(cube_mesh(n, lseed, jitter=cfg["jitter"], slivers=ns,
                                  dirichlet=cfg["dirichlet"]))
+    return out
+
+
+def instance_batch(count: int = 32, seed: int = 0, dof_range=(5e4, 3e6), sliver_range=(10, 1000),
+                   coarsest_dofs: int = 5000, scale: int = 1, sliver_cubes: int = 500, progress=None) -> list:
+    """Independent unit-cube problems of uneven size for the many-instance solve.
+
+    Per instance (seeded): degree P1 or P2, a DOF target log-uniform in
+    `dof_range` (divided by scale^3), the matching Kuhn grid, a log-uniform
+    number of slivers in `sliver_range`, capped at one per `sliver_cubes` grid
+    cubes (about twice the sliver density of the 129^3 cube, so that the flagged
+    regions of small meshes do not merge into one domain-spanning patch),
+    Dirichlet on x = 0, 1, and coarse levels
+    halving the intervals per side until the coarsest has <= coarsest_dofs DOFs.
+    Returns a list of (meshes, degree).
+    """
+    rng = np.random.default_rng(77_000 + int(seed))
+    out = []
+    for i in range(count):
+        degree = int(rng.integers(1, 3))
+        target = float(np.exp(rng.uniform(np.log(dof_range[0]), np.log(dof_range[1])))) / scale ** 3
+        per_side = target ** (1.0 / 3.0)
+        n = max(2, int(round(per_side - 1)) if degree == 1 else int(round((per_side - 1) / 2)))
+        nsl = int(np.exp(rng.uniform(np.log(sliver_range[0]), np.log(sliver_range[1]))))
+        nsl = max(1, nsl // scale ** 3)
+        sides = [n]
+        while (degree * sides[-1] + 1) ** 3 > coarsest_dofs and sides[-1] > 2:
+            sides.append(max(2, sides[-1] // 2))
+        meshes = []
+        for lvl, m in enumerate(sides):
+            meshes.append(cube_mesh(m, seed * 100_000 + i * 100 + lvl, jitter=0.15,
+                                    slivers=min(nsl, max(1, m ** 3 // sliver_cubes)) if lvl == 0 else 0,
+                                    dirichlet=("x0", "x1")))
+        out.append((meshes, degree))
+        if progress is not None:
+            progress(i, meshes, degree)
     return out
 
 

@@ -74,6 +74,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mg_vcycle": (C.c_int, [P, P, P]),
         "mg_pcg_solve": (C.c_int, [P, P, P, C.c_double, C.c_int32, C.POINTER(MgSolveStats)]),
         "mg_rhs_from_nodal": (C.c_int, [P, P, P]),
+        "mg_pcg_solve_batch": (C.c_int, [C.POINTER(P), C.c_int32, C.c_int32, C.POINTER(P), C.POINTER(P),
+                                         C.c_double, C.c_int32, C.POINTER(MgSolveStats), C.POINTER(C.c_double)]),
         "mg_get_level_info": (C.c_int, [P, C.c_int32, C.POINTER(MgLevelInfo)]),
         "mg_get_array": (C.c_int, [P, C.c_int32, C.c_int32, P]),
         "mg_enable_kernel_timing": (C.c_int, [P, C.c_int32]),
@@ -263,6 +265,34 @@ class Solver:
         b = C.c_double()
         self._check(lib().mg_cheb_algorithmic_bytes(self._h, C.byref(b)))
         return b.value
+
+
+def pcg_solve_batch(solvers: list, bs: list, us: list, rtol: float = 1e-8, maxit: int = 500) -> dict:
+    """mg_pcg_solve_batch: bs[i][r], us[i][r] are instance i's right-hand sides
+    and solutions (device float64 tensors).  Returns status, wall time and the
+    per-system statistics."""
+    n_inst = len(solvers)
+    nrhs = len(bs[0]) if n_inst else 0
+    if any(len(x) != nrhs for x in bs) or any(len(x) != nrhs for x in us) or len(bs) != n_inst:
+        raise ValueError("bs and us must be n_inst x nrhs")
+    _sync()
+    hs = (C.c_void_p * n_inst)(*[s._h.value for s in solvers])
+    pb = (C.c_void_p * (n_inst * nrhs))(*[_ptr(t) for row in bs for t in row])
+    pu = (C.c_void_p * (n_inst * nrhs))(*[_ptr(t) for row in us for t in row])
+    st = (MgSolveStats * max(1, n_inst * nrhs))()
+    wall = C.c_double()
+    code = lib().mg_pcg_solve_batch(hs, n_inst, nrhs, pb, pu, rtol, maxit, st, C.byref(wall))
+    if code < 0:
+        msg = lib().mg_global_error().decode()
+        for s in solvers:
+            m = lib().mg_last_error(s._h).decode()
+            if m:
+                msg = m
+                break
+        raise MgError(code, msg)
+    stats = [{"iterations": x.iterations, "converged": bool(x.converged), "true_rel_residual": x.true_rel_residual,
+              "solve_ms": x.solve_ms} for x in st[:n_inst * nrhs]]
+    return {"status": code, "wall_ms": wall.value, "stats": stats}
 
 
 def setup_status(meshes: list, **kw) -> tuple:

@@ -3,7 +3,9 @@
 // Sec. 6.2).  Host code here only orchestrates: every numerical step of the
 // solve phase is one of the HIP kernels of solve.hip.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstring>
 
@@ -499,6 +501,49 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
   if (breakdown) fail(MG_ERR_BREAKDOWN, "CG breakdown at iteration %d (p.Ap <= 0 or a non-finite value)", it);
   return converged ? MG_OK : MG_NOT_CONVERGED;
   MG_API_END(cp)
+}
+
+mg_status mg_pcg_solve_batch(mg_ctx *const *cs, int32_t n_inst, int32_t nrhs, const double *const *b,
+                             double *const *u, double rtol, int32_t maxit, mg_solve_stats *st, double *wall_ms) {
+  if (!cs || !b || !u || n_inst < 0 || nrhs < 0) {
+    g_error = "mg_pcg_solve_batch: NULL argument or negative count";
+    return MG_ERR_ARG;
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    if (!cs[i]) {
+      g_error = "mg_pcg_solve_batch: NULL context";
+      return MG_ERR_ARG;
+    }
+    for (int j = 0; j < i; ++j)
+      if (cs[j] == cs[i]) {
+        g_error = "mg_pcg_solve_batch: a context appears twice";
+        return MG_ERR_ARG;
+      }
+  }
+  std::vector<mg_status> status(n_inst, MG_OK);
+  auto t0 = std::chrono::steady_clock::now();
+  auto work = [&](int i) {
+    for (int r = 0; r < nrhs; ++r) {
+      int k = i * nrhs + r;
+      mg_status code = mg_pcg_solve(cs[i], b[k], u[k], rtol, maxit, st ? st + k : nullptr);
+      if (code < 0) {
+        status[i] = code;
+        return;
+      }
+      if (code == MG_NOT_CONVERGED) status[i] = MG_NOT_CONVERGED;
+    }
+  };
+  std::vector<std::thread> threads;
+  threads.reserve(n_inst);
+  for (int i = 0; i < n_inst; ++i) threads.emplace_back(work, i);
+  for (auto &t : threads) t.join();
+  if (wall_ms) *wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  mg_status worst = MG_OK;
+  for (int i = 0; i < n_inst; ++i) {
+    if (status[i] < 0) return status[i];
+    if (status[i] == MG_NOT_CONVERGED) worst = MG_NOT_CONVERGED;
+  }
+  return worst;
 }
 
 mg_status mg_rhs_from_nodal(mg_ctx *h, const double *f, double *b) {

@@ -7,9 +7,11 @@
 // a dense matrix-vector product: that product is fully parallel, whereas a
 // triangular substitution is a chain of n dependent steps.
 //
-// * Patches: one workgroup per patch.  The patch matrix is gathered from the
-//   CSR operator, factored by a right-looking column sweep, and inverted by
-//   forward/backward substitution with one thread per column of the identity.
+// * Patches: one workgroup per patch of up to 384 DOFs.  The patch matrix is
+//   gathered from the CSR operator, factored by a right-looking column sweep,
+//   and inverted by forward/backward substitution with one thread per column
+//   of the identity.  Larger patches go one at a time through the blocked path
+//   below.
 // * Coarsest level (large n): blocked right-looking Cholesky with 64x64 tiles
 //   (diagonal factor, panel triangular solve, trailing symmetric update), then
 //   W = L^-1 by a right-looking block solve of L W = I, and A^-1 = W^T W, all
@@ -87,10 +89,34 @@ __device__ void inverse_from_factor(const double *Lf, int n, double *X) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_patch_factor(const int64_t *rp, const int32_t *col, const double *val,
-                                                      const int32_t *ptr, const int32_t *dofs, const int64_t *off,
-                                                      double *scratch, double *inv, int *bad) {
-  int p = blockIdx.x;
+__global__ void k_to_float(const double *x, float *y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+// patches up to this size are factored by one workgroup each; larger ones by
+// the blocked multi-workgroup path of the coarsest level
+constexpr int SMALL_PATCH = 384;
+constexpr int MAX_PATCH = 16384;
+
+__global__ void k_gather_patch_dense(const int64_t *rp, const int32_t *col, const double *val, const int32_t *B,
+                                     int n, double *M) {
+  int i = blockIdx.x;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) M[(int64_t)i * n + j] = 0.0;
+  __syncthreads();
+  int32_t r = B[i];
+  for (int64_t k = rp[r] + threadIdx.x; k < rp[r + 1]; k += blockDim.x) {
+    int j = find_sorted(B, n, col[k]);
+    if (j >= 0) M[(int64_t)i * n + j] = val[k];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_patch_factor_list(const int64_t *rp, const int32_t *col,
+                                                           const double *val, const int32_t *list,
+                                                           const int32_t *ptr, const int32_t *dofs,
+                                                           const int64_t *off, double *scratch, double *inv,
+                                                           int *bad) {
+  int p = list[blockIdx.x];
   int n = ptr[p + 1] - ptr[p];
   const int32_t *B = dofs + ptr[p];
   double *Lf = scratch + off[p];
@@ -102,26 +128,49 @@ __global__ __launch_bounds__(256) void k_patch_factor(const int64_t *rp, const i
   inverse_from_factor(Lf, n, inv + off[p]);
 }
 
-__global__ void k_to_float(const double *x, float *y, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (float)x[i];
-}
+static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, int *bad);
 
 void factor_patches(Ctx &c, Level &L) {
   Patches &P = L.patch;
   if (P.n == 0) return;
   hipStream_t s = c.stream;
+  if (P.maxn > MAX_PATCH)
+    fail(MG_ERR_LIMIT, "a local-correction patch has %d DOFs (limit %d): the low-quality regions merge into "
+                       "one large subdomain", P.maxn, MAX_PATCH);
   int64_t total = (int64_t)P.inv64.n;
-  DBuf<double> scratch;
-  scratch.alloc(total);
+  std::vector<int32_t> small, large;
+  for (int k = 0; k < P.n; ++k) (P.h_kptr[k + 1] - P.h_kptr[k] <= SMALL_PATCH ? small : large).push_back(k);
   DBuf<int> bad;
   bad.alloc(1);
   int init = 2147483647;
   MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
-  k_patch_factor<<<P.n, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, P.ptr, P.dofs_canon, P.inv_off, scratch,
-                                     P.inv64, bad);
-  MG_LAUNCH_CHECK();
+  if (!small.empty()) {
+    DBuf<double> scratch;
+    scratch.alloc(total);
+    DBuf<int32_t> list;
+    upload(list, small.data(), small.size(), s);
+    k_patch_factor_list<<<(unsigned)small.size(), 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, list, P.ptr,
+                                                               P.dofs_canon, P.inv_off, scratch, P.inv64, bad);
+    MG_LAUNCH_CHECK();
+    MG_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<int64_t> hoff;
+  download(hoff, P.inv_off.p, (size_t)P.n, s);
   int hb = 0;
+  for (int32_t k : large) {
+    int n = P.h_kptr[k + 1] - P.h_kptr[k];
+    DBuf<double> M;
+    M.alloc((int64_t)n * n);
+    DBuf<int> badl;
+    badl.alloc(1);
+    MG_HIP(hipMemcpyAsync(badl.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
+    k_gather_patch_dense<<<n, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, P.dofs_canon.p + P.h_kptr[k], n, M);
+    MG_LAUNCH_CHECK();
+    dense_spd_inverse(s, M, n, P.inv64.p + hoff[k], badl);
+    MG_HIP(hipMemcpyAsync(&hb, badl.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "patch system %d has a non-positive Cholesky pivot", k);
+  }
   MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "patch system %d has a non-positive Cholesky pivot", hb);
@@ -354,6 +403,46 @@ __global__ __launch_bounds__(256) void k_single_inverse(const int64_t *rp, const
   inverse_from_factor(scratch, n, inv);
 }
 
+// In-place blocked Cholesky of the n x n SPD matrix M (row-major) and its
+// explicit inverse in X; *bad receives the first non-positive pivot row.
+static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, int *bad) {
+  int nb = (int)((n + TB - 1) / TB);
+  for (int kb = 0; kb < nb; ++kb) {
+    k_chol_diag<<<1, 256, 0, s>>>(M, n, kb, bad);
+    MG_LAUNCH_CHECK();
+    int rest = nb - kb - 1;
+    if (rest > 0) {
+      k_chol_panel<<<rest, 64, 0, s>>>(M, n, kb);
+      MG_LAUNCH_CHECK();
+      int64_t tiles = (int64_t)rest * (rest + 1) / 2;
+      k_chol_update<<<(unsigned)tiles, 256, 0, s>>>(M, n, kb);
+      MG_LAUNCH_CHECK();
+    }
+  }
+  // inverses of the diagonal tiles of L, then W = L^-1 right-looking, X = W^T W
+  DBuf<double> Dinv, W;
+  Dinv.alloc(n * n);
+  W.alloc(n * n);
+  k_trtri_diag<<<nb, 64, 0, s>>>(M, Dinv, n);
+  MG_LAUNCH_CHECK();
+  k_identity<<<(unsigned)n, 256, 0, s>>>(W, n);
+  MG_LAUNCH_CHECK();
+  for (int kb = 0; kb < nb; ++kb) {
+    k_trsm_rows<<<kb + 1, 256, 0, s>>>(Dinv, W, n, kb);
+    MG_LAUNCH_CHECK();
+    int64_t tiles = (int64_t)(nb - kb - 1) * (kb + 1);
+    if (tiles > 0) {
+      k_trsm_update<<<(unsigned)tiles, 256, 0, s>>>(M, W, n, kb);
+      MG_LAUNCH_CHECK();
+    }
+  }
+  Dinv.release();
+  int64_t tiles = (int64_t)nb * (nb + 1) / 2;
+  k_lauum<<<(unsigned)tiles, 256, 0, s>>>(W, X, n, nb);
+  MG_LAUNCH_CHECK();
+  MG_HIP(hipStreamSynchronize(s));
+}
+
 void factor_coarsest(Ctx &c, Level &L) {
   hipStream_t s = c.stream;
   int64_t n = L.nfree;
@@ -372,49 +461,12 @@ void factor_coarsest(Ctx &c, Level &L) {
   } else {
     k_dense_from_csr<<<(unsigned)n, 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, n, Lm);
     MG_LAUNCH_CHECK();
-    int nb = (int)((n + TB - 1) / TB);
-    for (int kb = 0; kb < nb; ++kb) {
-      k_chol_diag<<<1, 256, 0, s>>>(Lm, n, kb, bad);
-      MG_LAUNCH_CHECK();
-      int rest = nb - kb - 1;
-      if (rest > 0) {
-        k_chol_panel<<<rest, 64, 0, s>>>(Lm, n, kb);
-        MG_LAUNCH_CHECK();
-        int64_t tiles = (int64_t)rest * (rest + 1) / 2;
-        k_chol_update<<<(unsigned)tiles, 256, 0, s>>>(Lm, n, kb);
-        MG_LAUNCH_CHECK();
-      }
-    }
-    int hb0 = 0;
-    MG_HIP(hipMemcpyAsync(&hb0, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    MG_HIP(hipStreamSynchronize(s));
-    if (hb0 != 2147483647) fail(MG_ERR_NOT_SPD, "coarsest operator: non-positive pivot at row %d", hb0);
-    // inverses of the diagonal tiles of L, then Y = L^-1 right-looking
-    DBuf<double> Dinv, W;
-    Dinv.alloc(n * n);
-    W.alloc(n * n);
-    k_trtri_diag<<<nb, 64, 0, s>>>(Lm, Dinv, n);
-    MG_LAUNCH_CHECK();
-    k_identity<<<(unsigned)n, 256, 0, s>>>(W, n);
-    MG_LAUNCH_CHECK();
-    for (int kb = 0; kb < nb; ++kb) {
-      k_trsm_rows<<<kb + 1, 256, 0, s>>>(Dinv, W, n, kb);
-      MG_LAUNCH_CHECK();
-      int64_t tiles = (int64_t)(nb - kb - 1) * (kb + 1);
-      if (tiles > 0) {
-        k_trsm_update<<<(unsigned)tiles, 256, 0, s>>>(Lm, W, n, kb);
-        MG_LAUNCH_CHECK();
-      }
-    }
-    Dinv.release();
-    int64_t tiles = (int64_t)nb * (nb + 1) / 2;
-    k_lauum<<<(unsigned)tiles, 256, 0, s>>>(W, L.cinv, n, nb);
-    MG_LAUNCH_CHECK();
+    dense_spd_inverse(s, Lm, n, L.cinv, bad);
   }
   int hb = 0;
   MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
-  if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "coarsest operator is not positive definite");
+  if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "coarsest operator: non-positive pivot at row %d", hb);
 }
 
 }  // namespace mg

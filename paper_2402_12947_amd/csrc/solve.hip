@@ -163,8 +163,10 @@ template void patch_residual<float>(hipStream_t, const Sell &, const Patches &, 
                                     float *);
 
 // One workgroup per 64-row chunk of a patch: e = A_d^-1 r on those rows, with
-// the four wavefronts splitting the inner dimension, then u[B_d] += e.
-template <class T>
+// the four wavefronts splitting the inner dimension, then u[B_d] += e.  The
+// patch residual is staged in LDS when the largest patch fits in 64 KiB,
+// otherwise read from global memory (through L2).
+template <class T, bool STAGE>
 __global__ __launch_bounds__(256) void k_patch_apply(int c0, const int32_t *__restrict__ chunk_patch,
                                                      const int32_t *__restrict__ chunk_row,
                                                      const int32_t *__restrict__ ptr,
@@ -173,12 +175,16 @@ __global__ __launch_bounds__(256) void k_patch_apply(int c0, const int32_t *__re
                                                      const T *__restrict__ res, T *__restrict__ u) {
   extern __shared__ unsigned char smem[];
   T *red = reinterpret_cast<T *>(smem);  // [4][64]
-  T *r = red + 256;                      // [n]
   int b = c0 + blockIdx.x;
   int p = chunk_patch[b], i0 = chunk_row[b];
   int k0 = ptr[p], n = ptr[p + 1] - k0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) r[j] = res[k0 + j];
-  __syncthreads();
+  const T *r = res + k0;
+  if (STAGE) {
+    T *rs = red + 256;  // [n]
+    for (int j = threadIdx.x; j < n; j += blockDim.x) rs[j] = res[k0 + j];
+    __syncthreads();
+    r = rs;
+  }
   int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = i0 + lane;
   int jlo = (w * n) >> 2, jhi = ((w + 1) * n) >> 2;
   const T *M = inv + off[p];
@@ -202,8 +208,12 @@ void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *
   if (c1 <= c0) return;
   const T *inv = std::is_same<T, double>::value ? (const T *)pt.inv64.p : (const T *)pt.inv32.p;
   size_t shm = (size_t)(pt.maxn + 256) * sizeof(T);
-  k_patch_apply<T><<<c1 - c0, 256, shm, s>>>(c0, pt.chunk_patch, pt.chunk_row, pt.ptr, pt.dofs, pt.inv_off, inv,
-                                             res, u);
+  if (shm <= 65536)
+    k_patch_apply<T, true><<<c1 - c0, 256, shm, s>>>(c0, pt.chunk_patch, pt.chunk_row, pt.ptr, pt.dofs,
+                                                     pt.inv_off, inv, res, u);
+  else
+    k_patch_apply<T, false><<<c1 - c0, 256, 256 * sizeof(T), s>>>(c0, pt.chunk_patch, pt.chunk_row, pt.ptr,
+                                                                  pt.dofs, pt.inv_off, inv, res, u);
   MG_LAUNCH_CHECK();
 }
 template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *);
