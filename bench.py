@@ -227,7 +227,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay the V-cycle from a hipGraph")
     ap.add_argument("--sigma", type=int, default=0, help="SELL sorting window (0 = library's choice)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+                    help="also run a plain 1 GiB read + 1 GiB write kernel (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU (single-GPU build); "
@@ -280,17 +280,23 @@ def main():
                    "coarsest_dofs": main_arm["levels"][-1]["n_free"], "graph": bool(args.graph),
                    "sell_sigma_level0": main_arm["levels"][0]["sell_sigma"],
                    "sell_padding_level0": round(main_arm["levels"][0]["sell_stored"]
-                                                / main_arm["levels"][0]["nnz"], 4)},
+                                                / main_arm["levels"][0]["nnz"], 4),
+                   "levels_n_nnz_padding_sigma": [[lv["n_free"], lv["nnz"],
+                                                   round(lv["sell_stored"] / max(1, lv["nnz"]), 4),
+                                                   lv["sell_sigma"]] for lv in main_arm["levels"]]},
         "roofline": roofline,
         "arms": extra,
     }
     if args.copy_calibration:
+        # a plain streaming kernel of known traffic: dst = 2 * src over 1 GiB,
+        # reads 1 GiB and writes 1 GiB (torch's elementwise multiply)
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
-        line["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        line["copy_calibration_bytes"] = {"kernel": "elementwise MulFunctor", "read": src.numel() * 8,
+                                          "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8)
     print(json.dumps(line), flush=True)
