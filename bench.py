@@ -31,12 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # name: (meshgen recipe, degree, scale, layers, rtol)
-    "square_1025_p2": ("square_1025", 2, 1, 1, 1e-8),
-    "square_1025_p3": ("square_1025", 3, 1, 1, 1e-8),
-    "cube_129_p1": ("cube_129", 1, 1, 1, 1e-8),
-    "cube_129_p2": ("cube_129", 2, 1, 1, 1e-8),
-    "square_p1_4k": ("square_p1_4k", 1, 1, 2, 1e-10),
+    # name: (meshgen recipe, degree, scale, layers, rtol, patch policy)
+    "square_1025_p2": ("square_1025", 2, 1, 1, 1e-8, "merge"),
+    "square_1025_p3": ("square_1025", 3, 1, 1, 1e-8, "merge"),
+    "cube_129_p1": ("cube_129", 1, 1, 1, 1e-8, "merge"),
+    "cube_129_p2": ("cube_129", 2, 1, 1, 1e-8, "merge"),
+    "square_p1_4k": ("square_p1_4k", 1, 1, 2, 1e-10, "merge"),
+    # patch stress: ~20k separate flattened regions, the regions themselves
+    # are the subdomains (no extension layer), ~40 % of the DOFs in patches
+    "cube_129_stress_p2": ("cube_129_stress", 2, 1, 0, 1e-8, "overlap"),
 }
 # many-instance workload: 32 unit-cube problems of 50k-3M DOFs, 4 right-hand sides each
 BATCH_WORKLOADS = {"cube_batch_32x4": (32, 4, 1), "cube_batch_small": (4, 2, 4)}
@@ -70,14 +73,14 @@ def log(msg):
 
 
 def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local=True, timing=False,
-            use_graph=False, seed0=1000, sigma=0):
+            use_graph=False, seed0=1000, sigma=0, policy="merge"):
     import torch
 
     from paper_2402_12947_amd import Solver
     log(f"setup precision={precision} local={local}")
     t0 = time.perf_counter()
     s = Solver(meshes, degree=degree, tau=0.1, layers=layers, precision=precision,
-               local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma)
+               local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma, policy=policy)
     setup_s = time.perf_counter() - t0
     n = s.n_free(0)
     log(f"setup done in {setup_s:.2f} s, {n} DOFs; solving")
@@ -115,7 +118,7 @@ def _rhs(n, seed):
     return meshgen.random_rhs(n, seed)
 
 
-def cpu_baseline(recipe, degree, layers, rtol, scale, budget_s=12.0):
+def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", budget_s=12.0):
     import meshgen
     import oracle
     try:
@@ -124,7 +127,9 @@ def cpu_baseline(recipe, degree, layers, rtol, scale, budget_s=12.0):
     except Exception:  # pragma: no cover
         ctx = None
     meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
-    H = oracle.Hierarchy(meshes, tau=0.1, layers=layers, opts=oracle.Options(degree=degree))
+    H = oracle.Hierarchy(meshes, tau=0.1, layers=layers,
+                         opts=oracle.Options(degree=degree, patch_policy=oracle.OVERLAP if policy == "overlap"
+                                             else oracle.MERGE))
     n = H.levels[0].A.shape[0]
     solved, t0 = 0, time.perf_counter()
     its = []
@@ -239,11 +244,11 @@ def main():
     if args.workload in BATCH_WORKLOADS:
         print(json.dumps(run_batch(args.workload, args.steps, args.warmup)), flush=True)
         return
-    recipe, degree, scale, layers, rtol = WORKLOADS[args.workload]
+    recipe, degree, scale, layers, rtol, policy = WORKLOADS[args.workload]
     meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
     arms = args.arms.split(",")
     main_arm = run_arm(meshes, degree, layers, rtol, args.steps, args.warmup, precision=args.precision,
-                       local=True, timing=True, use_graph=args.graph, sigma=args.sigma)
+                       local=True, timing=True, use_graph=args.graph, sigma=args.sigma, policy=policy)
     n = main_arm["n"]
     value = n * args.steps / main_arm["elapsed_s"]
     extra = {}
@@ -253,7 +258,7 @@ def main():
                                "iterations": p["iterations"][0], "setup_s": round(p["setup_s"], 3),
                                "true_rel_residual": p["true_rel_residual"]}
     if "mixed" in arms and args.precision == "fp64":
-        mx = run_arm(meshes, degree, layers, rtol, args.steps, 1, precision="mixed", local=True)
+        mx = run_arm(meshes, degree, layers, rtol, args.steps, 1, precision="mixed", local=True, policy=policy)
         extra["global_local_mixed"] = {"dofs_per_s": mx["n"] * len(mx["iterations"]) / mx["elapsed_s"],
                                        "iterations": mx["iterations"][0], "setup_s": round(mx["setup_s"], 3),
                                        "true_rel_residual": mx["true_rel_residual"]}
@@ -273,7 +278,8 @@ def main():
         "data": "synthetic (seeded meshes and right-hand sides)",
         "config": {"workload": args.workload, "dofs": n, "levels": len(meshes), "rtol": rtol,
                    "smoother": "S_c -> Chebyshev-Jacobi(2) -> S_c, V(2,2), adjusted lambda_max",
-                   "precision": args.precision, "iterations": main_arm["iterations"][0],
+                   "precision": args.precision, "patch_layers": layers, "patch_policy": policy,
+                   "iterations": main_arm["iterations"][0],
                    "setup_s": round(main_arm["setup_s"], 3),
                    "true_rel_residual": main_arm["true_rel_residual"],
                    "patches_level0": main_arm["levels"][0]["n_patches"],
@@ -298,7 +304,7 @@ def main():
         line["copy_calibration_bytes"] = {"kernel": "elementwise MulFunctor", "read": src.numel() * 8,
                                           "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8)
+        line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8, policy)
     print(json.dumps(line), flush=True)
 
 

@@ -7,7 +7,8 @@ vertex-displacement idea of Sec. 6 intro) and random right-hand sides.  It holds
 none of the solver's arithmetic: no cell-quality measure, no basis functions, no
 degree-of-freedom numbering.  Degraded cells are produced purely geometrically,
 by moving a vertex to a small distance from the line/plane through the opposite
-facet of one incident cell; the only geometric test used is the sign of the
+facet of one incident cell, or (for the patch stress workload) by flattening
+thin slabs of the cube grid; the only geometric test used is the sign of the
 simplex orientation (so no cell inverts).
 
 A mesh is a dict::
@@ -24,7 +25,7 @@ import numpy as np
 
 __all__ = [
     "square_mesh", "cube_mesh", "hierarchy", "random_rhs", "CONFIGS",
-    "orientation", "instance_batch",
+    "orientation", "instance_batch", "stress_cube_mesh",
 ]
 
 
@@ -296,6 +297,62 @@ def cube_mesh(n: int, seed: int, jitter: float = 0.15, slivers: int = 0,
             "moved_vertices": np.array(moved, dtype=np.int64)}
 
 
+def stress_cube_mesh(n: int, seed: int, jitter: float = 0.15, flat: float = 0.01, width=(2, 11),
+                     dirichlet=("x0", "x1")) -> dict:
+    """Kuhn cube grid with many separate flat regions (the patch stress case).
+
+    The z levels are grouped in slabs of three (a fixed level, then two
+    levels that are pressed towards their mid-plane to `flat` times their
+    distance from it).  Inside a slab, the y direction is cut into strips and
+    every strip is cut along x, with log-uniform box widths in `width`
+    (interior grid columns between fixed lines).  The vertices of a box
+    interior are pressed; vertices on the fixed levels and lines keep their
+    place, so each box yields one connected region of flattened cells, and
+    the regions of different boxes share no vertex.  All vertices of one grid
+    column within a slab share their x, y position (the jitter of the slab's
+    fixed level), which keeps every cell positively oriented.
+    """
+    rng = np.random.default_rng(seed)
+    coords, cells, _interior = _cube_grid(n, rng, jitter)
+    m = n + 1
+    c3 = coords.reshape(m, m, m, 3)          # [k, j, i, :]
+    lo, hi = np.log(width[0]), np.log(width[1] + 1)
+
+    def cuts():
+        c = [0]
+        while c[-1] < n:
+            w = int(np.exp(rng.uniform(lo, hi)))
+            c.append(min(n, c[-1] + w + 1))
+        return np.array(c)
+
+    def interior_mask(c):
+        mask = np.ones(m, dtype=bool)
+        mask[c] = False
+        return mask
+
+    for k0 in range(0, n, 3):
+        k1 = min(k0 + 3, n)                  # levels k0+1, k0+2 (< n) are pressed
+        c3[k0 + 1:k1 + 1, :, :, :2] = c3[k0, :, :, :2]
+        if k0 + 1 >= n:
+            continue
+        levels = np.arange(k0 + 1, min(k0 + 3, n))
+        cy = cuts()
+        ymask = interior_mask(cy)
+        mid = (k0 + 1.5) / n
+        for t in range(len(cy) - 1):
+            j0, j1 = cy[t] + 1, cy[t + 1]
+            if j1 <= j0:
+                continue
+            xmask = interior_mask(cuts())
+            block = c3[levels[0]:levels[-1] + 1, j0:j1, :, 2]
+            sel = ymask[j0:j1][:, None] & xmask[None, :]
+            block[:, sel] = mid + flat * (block[:, sel] - mid)
+    coords = c3.reshape(-1, 3)
+    assert np.all(orientation(coords, cells) > 0)
+    return {"dim": 3, "coords": coords, "cells": np.ascontiguousarray(cells),
+            "dirichlet_vertex": _dirichlet_3d(coords, dirichlet)}
+
+
 # ----------------------------------------------------------------------------
 # workload hierarchies
 # ----------------------------------------------------------------------------
@@ -319,6 +376,11 @@ CONFIGS = {
     # thousand unknowns).
     "cube_129": dict(kind="cube", sides=[128, 64, 32, 16, 8], jitter=0.15,
                      slivers=[2000, 250, 32, 4, 1], dirichlet=("x0", "x1")),
+    # patch stress: the 129^3 cube with ~20k separate flattened regions on the
+    # finest level (boxes 2-11 columns wide); coarse levels as cube_129 without
+    # degraded cells.
+    "cube_129_stress": dict(kind="cube_stress", sides=[128, 64, 32, 16, 8], jitter=0.15,
+                            dirichlet=("x0", "x1")),
 }
 
 
@@ -347,6 +409,11 @@ def hierarchy(name: str, seed: int = 0, scale: int = 1, case: str = "fine") -> l
                                    n_single=nsingle,
                                    single_depth=cfg.get("single_depth", 1e-3),
                                    dirichlet=cfg["dirichlet"]))
+        elif cfg["kind"] == "cube_stress":
+            if degrade:
+                out.append(stress_cube_mesh(n, lseed, jitter=cfg["jitter"], dirichlet=cfg["dirichlet"]))
+            else:
+                out.append(cube_mesh(n, lseed, jitter=cfg["jitter"], dirichlet=cfg["dirichlet"]))
         else:
             ns = (cfg["slivers"][lvl] // (scale ** 3)) if degrade else 0
             if degrade and cfg["slivers"][lvl] > 0:

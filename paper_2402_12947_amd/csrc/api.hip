@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <thread>
 #include <cmath>
 #include <cstring>
@@ -302,6 +304,16 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     const bool mixed = o.precision == MG_MIXED;
     auto now = [] { return std::chrono::steady_clock::now(); };
     auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+    // MG_SETUP_LOG=1 reports every finished setup phase on stderr
+    const char *env = std::getenv("MG_SETUP_LOG");
+    const bool verbose = env && env[0] == '1';
+    auto t_start = now();
+    auto phase = [&](const char *what, int l) {
+      if (verbose) {
+        std::fprintf(stderr, "[mg setup] %8.1f ms  level %d: %s\n", ms(t_start, now()), l, what);
+        std::fflush(stderr);
+      }
+    };
     for (int l = 0; l < n_levels; ++l) {
       auto t0 = now();
       Level &L = c.lv[l];
@@ -312,12 +324,14 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       if (!L.coarsest) build_patches(c, L, levels[l]);
       if (l == 0) assemble_fine(c, L);
       L.setup_ms += ms(t0, now());
+      phase(l == 0 ? "DOF map, quality, patches, assembly" : "DOF map, quality, patches", l);
     }
     for (int l = 0; l + 1 < n_levels; ++l) {
       auto t0 = now();
       build_prolongation(c, c.lv[l], c.lv[l + 1], levels[l + 1]);
       galerkin_product(c, c.lv[l], c.lv[l + 1]);
       c.lv[l].setup_ms += ms(t0, now());
+      phase("prolongation and Galerkin product", l);
     }
     for (int l = 0; l < n_levels; ++l) {
       auto t0 = now();
@@ -325,6 +339,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       solve_order(c, L, L.coarsest ? 1 : c.opt.sell_sigma, mixed && !L.coarsest);
       permute_patches(c, L);
       L.setup_ms += ms(t0, now());
+      phase("solve order", l);
     }
     for (int l = 0; l < n_levels; ++l) {
       auto t0 = now();
@@ -334,9 +349,12 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
         L.Pc = Csr();
         L.Rc = Csr();
         factor_patches(c, L);
+        phase("patch factorisation", l);
         estimate_eigenvalues(c, L);
+        phase("eigenvalue estimates", l);
       } else {
         factor_coarsest(c, L);
+        phase("coarsest factorisation", l);
       }
       ensure_work(c, L);
       L.setup_ms += ms(t0, now());

@@ -213,6 +213,7 @@ void build_prolongation(Ctx &c, Level &fine, const Level &coarse, const mg_mesh 
 void galerkin_product(Ctx &c, Level &fine, Level &coarse);
 void build_patches(Ctx &c, Level &L, const mg_mesh &m);
 void factor_patches(Ctx &c, Level &L);
+void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad);
 void factor_coarsest(Ctx &c, Level &L);
 void estimate_eigenvalues(Ctx &c, Level &L);
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);

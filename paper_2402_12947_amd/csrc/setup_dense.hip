@@ -94,9 +94,9 @@ __global__ void k_to_float(const double *x, float *y, int64_t n) {
   if (i < n) y[i] = (float)x[i];
 }
 
-// patches up to this size are factored by one workgroup each; larger ones by
-// the blocked multi-workgroup path of the coarsest level
-constexpr int SMALL_PATCH = 384;
+// patches above BATCH_MAX DOFs are factored one at a time by the blocked
+// multi-workgroup path of the coarsest level; above MAX_PATCH they are refused
+constexpr int BATCH_MAX = 2048;
 constexpr int MAX_PATCH = 16384;
 
 __global__ void k_gather_patch_dense(const int64_t *rp, const int32_t *col, const double *val, const int32_t *B,
@@ -111,23 +111,6 @@ __global__ void k_gather_patch_dense(const int64_t *rp, const int32_t *col, cons
   }
 }
 
-__global__ __launch_bounds__(256) void k_patch_factor_list(const int64_t *rp, const int32_t *col,
-                                                           const double *val, const int32_t *list,
-                                                           const int32_t *ptr, const int32_t *dofs,
-                                                           const int64_t *off, double *scratch, double *inv,
-                                                           int *bad) {
-  int p = list[blockIdx.x];
-  int n = ptr[p + 1] - ptr[p];
-  const int32_t *B = dofs + ptr[p];
-  double *Lf = scratch + off[p];
-  gather_block(rp, col, val, B, n, Lf);
-  if (!cholesky_inplace(Lf, n)) {
-    if (threadIdx.x == 0) atomicMin(bad, p);
-    return;
-  }
-  inverse_from_factor(Lf, n, inv + off[p]);
-}
-
 static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, int *bad);
 
 void factor_patches(Ctx &c, Level &L) {
@@ -138,22 +121,12 @@ void factor_patches(Ctx &c, Level &L) {
     fail(MG_ERR_LIMIT, "a local-correction patch has %d DOFs (limit %d): the low-quality regions merge into "
                        "one large subdomain", P.maxn, MAX_PATCH);
   int64_t total = (int64_t)P.inv64.n;
-  std::vector<int32_t> small, large;
-  for (int k = 0; k < P.n; ++k) (P.h_kptr[k + 1] - P.h_kptr[k] <= SMALL_PATCH ? small : large).push_back(k);
   DBuf<int> bad;
   bad.alloc(1);
   int init = 2147483647;
   MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
-  if (!small.empty()) {
-    DBuf<double> scratch;
-    scratch.alloc(total);
-    DBuf<int32_t> list;
-    upload(list, small.data(), small.size(), s);
-    k_patch_factor_list<<<(unsigned)small.size(), 256, 0, s>>>(L.A.rowptr, L.A.col, L.A.val, list, P.ptr,
-                                                               P.dofs_canon, P.inv_off, scratch, P.inv64, bad);
-    MG_LAUNCH_CHECK();
-    MG_HIP(hipStreamSynchronize(s));
-  }
+  std::vector<int32_t> large;
+  factor_patches_batched(c, L, BATCH_MAX, large, bad);
   std::vector<int64_t> hoff;
   download(hoff, P.inv_off.p, (size_t)P.n, s);
   int hb = 0;
