@@ -44,12 +44,16 @@ template <>
 struct LV<double> {
   static double *w(Level &L, int k) { return L.w64[k].p; }
   static double *res(Level &L) { return L.res64.p; }
+  static double *py(Level &L) { return L.py64.p; }
+  static double *pz(Level &L) { return L.pz64.p; }
   static const double *dinv(Level &L) { return L.dinv64.p; }
 };
 template <>
 struct LV<float> {
   static float *w(Level &L, int k) { return L.w32[k].p; }
   static float *res(Level &L) { return L.res32.p; }
+  static float *py(Level &L) { return L.py32.p; }
+  static float *pz(Level &L) { return L.pz32.p; }
   static const float *dinv(Level &L) { return L.dinv32.p; }
 };
 
@@ -59,7 +63,15 @@ void ensure_work(Ctx &c, Level &L) {
     if (mixed) L.w32[k].alloc(L.nfree); else L.w64[k].alloc(L.nfree);
   }
   if (L.patch.total > 0) {
-    if (mixed) L.res32.alloc(L.patch.total); else L.res64.alloc(L.patch.total);
+    if (mixed) {
+      L.res32.alloc(L.patch.total);
+      L.py32.alloc(L.patch.ysize);
+      L.pz32.alloc(std::max<int64_t>(1, L.patch.zsize));
+    } else {
+      L.res64.alloc(L.patch.total);
+      L.py64.alloc(L.patch.ysize);
+      L.pz64.alloc(std::max<int64_t>(1, L.patch.zsize));
+    }
   }
   if (L.coarsest) L.cpart.alloc(dense_part_size(L.nfree));
 }
@@ -87,8 +99,8 @@ template <class T>
 static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending) {
   for (int k = 0; k < L.patch.ncolour; ++k) {
     int col = descending ? L.patch.ncolour - 1 - k : k;
-    patch_residual<T>(c.stream, L.S, L.patch, col, b, u, LV<T>::res(L));
-    patch_apply<T>(c.stream, L.patch, col, LV<T>::res(L), u);
+    patch_residual<T>(c.stream, L.patch, col, b, u, LV<T>::res(L));
+    patch_apply<T>(c.stream, L.patch, col, LV<T>::res(L), LV<T>::py(L), LV<T>::pz(L), u);
   }
 }
 
@@ -338,6 +350,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       Level &L = c.lv[l];
       solve_order(c, L, L.coarsest ? 1 : c.opt.sell_sigma, mixed && !L.coarsest);
       permute_patches(c, L);
+      if (!L.coarsest) build_patch_rows(c, L, mixed);
       L.setup_ms += ms(t0, now());
       phase("solve order", l);
     }

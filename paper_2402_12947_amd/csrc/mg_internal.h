@@ -119,12 +119,22 @@ struct Patches {
   DBuf<int32_t> ptr;          // [n + 1] kernel order
   DBuf<int32_t> dofs;         // [total] solve-order positions of the patch DOFs
   DBuf<int32_t> dofs_canon;   // [total] canonical free ids (factorisation)
-  DBuf<int64_t> inv_off;      // [n] offset of the patch inverse (n_d^2 entries)
-  // work items of the patch apply: 64-row chunks of the patches, kernel order
-  DBuf<int32_t> chunk_patch, chunk_row;
-  std::vector<int> colour_chunk_first;  // [ncolour + 1]
-  DBuf<double> inv64;
-  DBuf<float> inv32;
+  DBuf<int64_t> inv_off;      // [n] offset of the full inverse (n_d^2 entries, setup only)
+  DBuf<double> inv64;         // full inverses, row-major (setup only)
+  // Solve phase: the inverse of every patch as the lower triangle of 32 x 32
+  // tiles (tile (I, J), J <= I, at tile_off + (I (I + 1) / 2 + J) * 1024,
+  // row-major inside the tile, zero beyond n_d).  Work items are (patch, tile
+  // row); per patch the apply keeps the row products (yoff, PT entries per
+  // tile row) and the transposed products of the off-diagonal tiles (zoff, PT
+  // entries per tile below the diagonal).
+  int64_t packed = 0, ysize = 0, zsize = 0;
+  DBuf<int64_t> tile_off, yoff, zoff;   // [n]
+  DBuf<int32_t> item_patch, item_row;   // kernel order
+  std::vector<int> colour_item_first;   // [ncolour + 1]
+  DBuf<double> pk64;
+  DBuf<float> pk32;
+  // rows of A at the patch DOFs (kernel order), columns in solve order
+  Sell rows;
 };
 
 struct Level {
@@ -171,6 +181,8 @@ struct Level {
   DBuf<float> w32[6];
   DBuf<double> res64;          // patch residuals [patch.total]
   DBuf<float> res32;
+  DBuf<double> py64, pz64;     // patch apply partial products [patch.ysize], [patch.zsize]
+  DBuf<float> py32, pz32;
   double setup_ms = 0;
 };
 
@@ -214,6 +226,8 @@ void galerkin_product(Ctx &c, Level &fine, Level &coarse);
 void build_patches(Ctx &c, Level &L, const mg_mesh &m);
 void factor_patches(Ctx &c, Level &L);
 void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad);
+void build_patch_rows(Ctx &c, Level &L, bool want32);
+constexpr int PATCH_TILE = 32;
 void factor_coarsest(Ctx &c, Level &L);
 void estimate_eigenvalues(Ctx &c, Level &L);
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);
@@ -238,10 +252,9 @@ void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T 
                int first, double c_d, double c_r);
 
 template <class T>
-void patch_residual(hipStream_t s, const Sell &S, const Patches &pt, int colour, const T *b,
-                    const T *u, T *res);
+void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, const T *u, T *res);
 template <class T>
-void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *u);
+void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u);
 
 template <class T>
 void dense_symv(hipStream_t s, int64_t n, const double *M, const T *x, T *y, double *part);

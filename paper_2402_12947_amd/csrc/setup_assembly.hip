@@ -429,6 +429,17 @@ static void order_with(Ctx &c, Level &L, int sigma, bool want32) {
   dinv_of(c, B, L.dinv64, want32 ? &L.dinv32 : nullptr);
 }
 
+// Rows of A at the patch DOFs, one row per kernel-order patch entry, columns in
+// the level's solve order: the patch residual streams them as a SELL matrix.
+void build_patch_rows(Ctx &c, Level &L, bool want32) {
+  Patches &P = L.patch;
+  if (P.total == 0) return;
+  Csr B;
+  permute_csr(c, L.A, P.dofs_canon, P.total, L.iperm, L.nfree, B);
+  build_sell(c, B, P.rows, 1, want32);
+  P.rows.perm.release();
+}
+
 // average time of the level's Chebyshev-step kernel in its current layout
 static double time_cheb(Ctx &c, Level &L, bool want32) {
   hipStream_t s = c.stream;

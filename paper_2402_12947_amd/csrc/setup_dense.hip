@@ -89,11 +89,6 @@ __device__ void inverse_from_factor(const double *Lf, int n, double *X) {
   __syncthreads();
 }
 
-__global__ void k_to_float(const double *x, float *y, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (float)x[i];
-}
-
 // patches above BATCH_MAX DOFs are factored one at a time by the blocked
 // multi-workgroup path of the coarsest level; above MAX_PATCH they are refused
 constexpr int BATCH_MAX = 2048;
@@ -112,6 +107,25 @@ __global__ void k_gather_patch_dense(const int64_t *rp, const int32_t *col, cons
 }
 
 static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, int *bad);
+
+// one workgroup per patch: full row-major inverse -> packed lower tiles
+template <class T>
+__global__ __launch_bounds__(256) void k_pack_patch(const int32_t *ptr, const int64_t *ioff, const double *inv,
+                                                    const int64_t *toff, T *pk) {
+  constexpr int PT = PATCH_TILE;
+  const int k = blockIdx.x;
+  const int n = ptr[k + 1] - ptr[k];
+  const int nb = (n + PT - 1) / PT;
+  const double *X = inv + ioff[k];
+  T *out = pk + toff[k];
+  int64_t t = 0;
+  for (int I = 0; I < nb; ++I)
+    for (int J = 0; J <= I; ++J, ++t)
+      for (int e = threadIdx.x; e < PT * PT; e += blockDim.x) {
+        int r = I * PT + e / PT, cc = J * PT + e % PT;
+        out[t * PT * PT + e] = (r < n && cc < n) ? (T)X[(int64_t)r * n + cc] : (T)0;
+      }
+}
 
 void factor_patches(Ctx &c, Level &L) {
   Patches &P = L.patch;
@@ -147,12 +161,18 @@ void factor_patches(Ctx &c, Level &L) {
   MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "patch system %d has a non-positive Cholesky pivot", hb);
+  // lower 32 x 32 tiles of every inverse, in the precision of the cycle
+  (void)total;
   if (c.opt.precision == MG_MIXED) {
-    P.inv32.alloc(total);
-    k_to_float<<<grid_for(total, 256), 256, 0, s>>>(P.inv64, P.inv32, total);
-    MG_LAUNCH_CHECK();
-    MG_HIP(hipStreamSynchronize(s));
+    P.pk32.alloc(P.packed);
+    k_pack_patch<float><<<P.n, 256, 0, s>>>(P.ptr, P.inv_off, P.inv64, P.tile_off, P.pk32);
+  } else {
+    P.pk64.alloc(P.packed);
+    k_pack_patch<double><<<P.n, 256, 0, s>>>(P.ptr, P.inv_off, P.inv64, P.tile_off, P.pk64);
   }
+  MG_LAUNCH_CHECK();
+  MG_HIP(hipStreamSynchronize(s));
+  P.inv64.release();
 }
 
 // ---------------------------------------------------------------------------

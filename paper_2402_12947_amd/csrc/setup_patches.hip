@@ -222,19 +222,35 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
     acc += (int64_t)dofs[p].size() * (int64_t)dofs[p].size();
   }
   P.colour_first[ncol] = P.n;
-  std::vector<int32_t> cpatch, crow;
-  P.colour_chunk_first.assign(ncol + 1, 0);
+  std::vector<int32_t> ipatch, irow;
+  std::vector<int64_t> toff(P.n), yoff(P.n), zoff(P.n);
+  int64_t tacc = 0, yacc = 0, zacc = 0;
+  P.colour_item_first.assign(ncol + 1, 0);
   for (int col = 0; col < ncol; ++col) {
-    P.colour_chunk_first[col] = (int)cpatch.size();
-    for (int k = P.colour_first[col]; k < P.colour_first[col + 1]; ++k)
-      for (int i0 = 0; i0 < kptr[k + 1] - kptr[k]; i0 += 64) {
-        cpatch.push_back(k);
-        crow.push_back(i0);
+    P.colour_item_first[col] = (int)ipatch.size();
+    for (int k = P.colour_first[col]; k < P.colour_first[col + 1]; ++k) {
+      int64_t nb = (kptr[k + 1] - kptr[k] + PATCH_TILE - 1) / PATCH_TILE;
+      toff[k] = tacc;
+      yoff[k] = yacc;
+      zoff[k] = zacc;
+      tacc += nb * (nb + 1) / 2 * PATCH_TILE * PATCH_TILE;
+      yacc += nb * PATCH_TILE;
+      zacc += nb * (nb - 1) / 2 * PATCH_TILE;
+      for (int64_t I = 0; I < nb; ++I) {
+        ipatch.push_back(k);
+        irow.push_back((int32_t)I);
       }
+    }
   }
-  P.colour_chunk_first[ncol] = (int)cpatch.size();
-  upload(P.chunk_patch, cpatch.data(), cpatch.size(), s);
-  upload(P.chunk_row, crow.data(), crow.size(), s);
+  P.colour_item_first[ncol] = (int)ipatch.size();
+  P.packed = tacc;
+  P.ysize = yacc;
+  P.zsize = zacc;
+  upload(P.item_patch, ipatch.data(), ipatch.size(), s);
+  upload(P.item_row, irow.data(), irow.size(), s);
+  upload(P.tile_off, toff.data(), toff.size(), s);
+  upload(P.yoff, yoff.data(), yoff.size(), s);
+  upload(P.zoff, zoff.data(), zoff.size(), s);
   P.h_kptr = kptr;
   upload(P.ptr, kptr.data(), kptr.size(), s);
   upload(P.dofs_canon, kdofs.data(), kdofs.size(), s);

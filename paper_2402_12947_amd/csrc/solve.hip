@@ -131,93 +131,147 @@ template void cheb_step<float>(hipStream_t, const Sell &, const float *, const f
 // ---------------------------------------------------------------------------
 // local correction
 // ---------------------------------------------------------------------------
+// r = b - A u on the rows of one colour's patches: the patch rows of A are a
+// SELL matrix of their own (kernel order), streamed like the level operator.
 template <class T>
-__global__ void k_patch_residual(int64_t k0, int64_t k1, const int32_t *__restrict__ dofs,
-                                 const int64_t *__restrict__ sptr, const int32_t *__restrict__ col,
-                                 const T *__restrict__ val, const T *__restrict__ b, const T *__restrict__ u,
-                                 T *__restrict__ res) {
-  int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= k1) return;
-  int32_t pos = dofs[k];
-  int64_t sl = pos >> 6;
-  int lane = pos & 63;
-  int64_t base = sptr[sl];
-  int w = (int)((sptr[sl + 1] - base) >> 6);
-  T acc = 0;
-  for (int j = 0; j < w; ++j) acc += val[base + j * 64 + lane] * u[col[base + j * 64 + lane]];
-  res[k] = b[pos] - acc;
+__global__ __launch_bounds__(256) void k_patch_residual(int64_t k0, int64_t k1, const int64_t *__restrict__ sptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const T *__restrict__ val,
+                                                        const int32_t *__restrict__ dofs, const T *__restrict__ b,
+                                                        const T *__restrict__ u, T *__restrict__ res) {
+  int64_t k = (k0 & ~(int64_t)63) + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t sl = k >> 6;
+  if (k >= ((k1 + 63) & ~(int64_t)63)) return;
+  T acc = sell_row(sptr, col, val, u, sl, (int)(k & 63));
+  if (k >= k0 && k < k1) res[k] = b[dofs[k]] - acc;
 }
 
 template <class T>
-void patch_residual(hipStream_t s, const Sell &S, const Patches &pt, int colour, const T *b, const T *u, T *res) {
+void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, const T *u, T *res) {
   int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
   int64_t k0 = pt.h_kptr[p0], k1 = pt.h_kptr[p1];
   if (k1 <= k0) return;
-  int g = (int)((k1 - k0 + 255) / 256);
-  k_patch_residual<T><<<g, 256, 0, s>>>(k0, k1, pt.dofs, S.slice_ptr, S.col, sell_vals<T>(S), b, u, res);
+  int64_t span = ((k1 + 63) & ~(int64_t)63) - (k0 & ~(int64_t)63);
+  k_patch_residual<T><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(k0, k1, pt.rows.slice_ptr, pt.rows.col,
+                                                                      sell_vals<T>(pt.rows), pt.dofs, b, u, res);
   MG_LAUNCH_CHECK();
 }
-template void patch_residual<double>(hipStream_t, const Sell &, const Patches &, int, const double *,
-                                     const double *, double *);
-template void patch_residual<float>(hipStream_t, const Sell &, const Patches &, int, const float *, const float *,
-                                    float *);
+template void patch_residual<double>(hipStream_t, const Patches &, int, const double *, const double *, double *);
+template void patch_residual<float>(hipStream_t, const Patches &, int, const float *, const float *, float *);
 
-// One workgroup per 64-row chunk of a patch: e = A_d^-1 r on those rows, with
-// the four wavefronts splitting the inner dimension, then u[B_d] += e.  The
-// patch residual is staged in LDS when the largest patch fits in 64 KiB,
-// otherwise read from global memory (through L2).
-template <class T, bool STAGE>
-__global__ __launch_bounds__(256) void k_patch_apply(int c0, const int32_t *__restrict__ chunk_patch,
-                                                     const int32_t *__restrict__ chunk_row,
-                                                     const int32_t *__restrict__ ptr,
-                                                     const int32_t *__restrict__ dofs,
-                                                     const int64_t *__restrict__ off, const T *__restrict__ inv,
-                                                     const T *__restrict__ res, T *__restrict__ u) {
-  extern __shared__ unsigned char smem[];
-  T *red = reinterpret_cast<T *>(smem);  // [4][64]
-  int b = c0 + blockIdx.x;
-  int p = chunk_patch[b], i0 = chunk_row[b];
-  int k0 = ptr[p], n = ptr[p + 1] - k0;
+// Orders this wavefront's LDS accesses (writes before reads of other lanes).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// e_d = A_d^-1 r_d from the packed lower tiles of the inverse X (symmetric).
+// One wavefront per (patch, tile row I).  Lane (h, j) = (lane >> 5, lane & 31)
+// reads rows 2 s + h, s = 0..15, of each 32 x 32 tile, column j, so every
+// tile is read once, coalesced (the next tile is in flight meanwhile).  Tile
+// (I, J) gives
+//   the column product X_IJ^T r_I  (J < I; lane-private, stored per tile in pz),
+//   the row product    X_IJ r_J     (tile transposed through the wavefront's
+//                                    LDS area, lane (h, i) sums half a row),
+// and the row products of tile row I are summed in registers and stored in py.
+template <class T>
+__global__ __launch_bounds__(256) void k_patch_rows(int i0, int i1, const int32_t *__restrict__ item_patch,
+                                                    const int32_t *__restrict__ item_row,
+                                                    const int32_t *__restrict__ ptr,
+                                                    const int64_t *__restrict__ toff,
+                                                    const int64_t *__restrict__ yoff,
+                                                    const int64_t *__restrict__ zoff, const T *__restrict__ pk,
+                                                    const T *__restrict__ res, T *__restrict__ py,
+                                                    T *__restrict__ pz) {
+  constexpr int PT = PATCH_TILE;
+  __shared__ T tl[4][PT][PT + 1];
+  __shared__ T rl[4][PT];
+  const int wave = threadIdx.x >> 6;
+  const int item = i0 + (int)(blockIdx.x * 4 + wave);
+  if (item >= i1) return;
+  const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
+  T(*Ts)[PT + 1] = tl[wave];
+  T *Rs = rl[wave];
+  const int p = item_patch[item], I = item_row[item];
+  const int k0 = ptr[p], n = ptr[p + 1] - k0;
   const T *r = res + k0;
-  if (STAGE) {
-    T *rs = red + 256;  // [n]
-    for (int j = threadIdx.x; j < n; j += blockDim.x) rs[j] = res[k0 + j];
-    __syncthreads();
-    r = rs;
+  T rI[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    int i = I * PT + 2 * s + h;
+    rI[s] = i < n ? r[i] : (T)0;
   }
-  int w = threadIdx.x >> 6, lane = threadIdx.x & 63, i = i0 + lane;
-  int jlo = (w * n) >> 2, jhi = ((w + 1) * n) >> 2;
-  const T *M = inv + off[p];
-  T a0 = 0, a1 = 0;
-  if (i < n) {
-    int j = jlo;
-    for (; j + 1 < jhi; j += 2) {
-      a0 += M[(int64_t)j * n + i] * r[j];
-      a1 += M[(int64_t)(j + 1) * n + i] * r[j + 1];
+  const T *tile = pk + toff[p] + (int64_t)I * (I + 1) / 2 * PT * PT + h * PT + j;
+  T yrow = 0;
+  T v[16], nxt[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) nxt[s] = __builtin_nontemporal_load(tile + 2 * s * PT);
+  for (int J = 0; J <= I; ++J) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) v[s] = nxt[s];
+    tile += PT * PT;
+    if (J < I) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) nxt[s] = __builtin_nontemporal_load(tile + 2 * s * PT);
+      T cs = 0;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) cs += v[s] * rI[s];
+      cs += __shfl_xor(cs, 32);
+      if (h == 0) pz[zoff[p] + ((int64_t)I * (I - 1) / 2 + J) * PT + j] = cs;
     }
-    if (j < jhi) a0 += M[(int64_t)j * n + i] * r[j];
+    const int jj = J * PT + j;
+    if (h == 0) Rs[j] = jj < n ? r[jj] : (T)0;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) Ts[2 * s + h][j] = v[s];
+    wave_sync();
+    T acc = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc += Ts[j][16 * h + t] * Rs[16 * h + t];
+    yrow += acc + __shfl_xor(acc, 32);  // row j
+    wave_sync();
   }
-  red[threadIdx.x] = a0 + a1;
-  __syncthreads();
-  if (w == 0 && i < n) u[dofs[k0 + i]] += (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+  if (h == 0) py[yoff[p] + (int64_t)I * PT + j] = yrow;
+}
+
+// e_J = (row products of tile row J) + sum_{I > J} (column products of tile
+// (I, J)), in a fixed order; u[B_d] += e (patches of one colour share no DOF).
+template <class T>
+__global__ __launch_bounds__(256) void k_patch_gather(int i0, int i1, const int32_t *__restrict__ item_patch,
+                                                      const int32_t *__restrict__ item_row,
+                                                      const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ dofs,
+                                                      const int64_t *__restrict__ yoff,
+                                                      const int64_t *__restrict__ zoff, const T *__restrict__ py,
+                                                      const T *__restrict__ pz, T *__restrict__ u) {
+  constexpr int PT = PATCH_TILE;
+  const int item = i0 + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (item >= i1) return;
+  const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
+  const int p = item_patch[item], J = item_row[item];
+  const int k0 = ptr[p], n = ptr[p + 1] - k0, nb = (n + PT - 1) / PT;
+  T e = 0;
+  for (int I = J + 1 + h; I < nb; I += 2) e += pz[zoff[p] + ((int64_t)I * (I - 1) / 2 + J) * PT + j];
+  e += __shfl_xor(e, 32);
+  const int i = J * PT + j;
+  if (h == 0 && i < n) u[dofs[k0 + i]] += py[yoff[p] + (int64_t)J * PT + j] + e;
 }
 
 template <class T>
-void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *u) {
-  int c0 = pt.colour_chunk_first[colour], c1 = pt.colour_chunk_first[colour + 1];
-  if (c1 <= c0) return;
-  const T *inv = std::is_same<T, double>::value ? (const T *)pt.inv64.p : (const T *)pt.inv32.p;
-  size_t shm = (size_t)(pt.maxn + 256) * sizeof(T);
-  if (shm <= 65536)
-    k_patch_apply<T, true><<<c1 - c0, 256, shm, s>>>(c0, pt.chunk_patch, pt.chunk_row, pt.ptr, pt.dofs,
-                                                     pt.inv_off, inv, res, u);
-  else
-    k_patch_apply<T, false><<<c1 - c0, 256, 256 * sizeof(T), s>>>(c0, pt.chunk_patch, pt.chunk_row, pt.ptr,
-                                                                  pt.dofs, pt.inv_off, inv, res, u);
+void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u) {
+  int i0 = pt.colour_item_first[colour], i1 = pt.colour_item_first[colour + 1];
+  if (i1 <= i0) return;
+  const T *pk = std::is_same<T, double>::value ? (const T *)pt.pk64.p : (const T *)pt.pk32.p;
+  unsigned g = (unsigned)((i1 - i0 + 3) / 4);
+  k_patch_rows<T><<<g, 256, 0, s>>>(i0, i1, pt.item_patch, pt.item_row, pt.ptr, pt.tile_off, pt.yoff, pt.zoff, pk,
+                                    res, py, pz);
+  MG_LAUNCH_CHECK();
+  k_patch_gather<T><<<g, 256, 0, s>>>(i0, i1, pt.item_patch, pt.item_row, pt.ptr, pt.dofs, pt.yoff, pt.zoff, py,
+                                      pz, u);
   MG_LAUNCH_CHECK();
 }
-template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *);
-template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *);
+template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *, double *, double *);
+template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *, float *, float *);
 
 // ---------------------------------------------------------------------------
 // coarsest: y = M x with the dense symmetric inverse (FP64 arithmetic)

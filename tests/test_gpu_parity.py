@@ -20,21 +20,25 @@ from tests.parity_util import build_pair, from_dev, rel_err, sparse_close, to_de
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    # name: (workload, scale, degree, layers)
+    # name: (workload, scale, degree, layers[, patch policy])
     "square_p1_4k": ("square_p1_4k", 1, 1, 2),
     "square_p2": ("square_1025", 16, 2, 1),
     "square_p3": ("square_1025", 32, 3, 1),
     "cube_p1": ("cube_129", 8, 1, 1),
     "cube_p2": ("cube_129", 16, 2, 1),
+    # patch stress at 1/8 size: 54 separate flattened regions, patches of
+    # 27-1587 DOFs (one to fifty 32x32 tiles per side in the batched factorisation)
+    "cube_stress_p2": ("cube_129_stress", 8, 2, 0, "overlap"),
 }
 
 
 @functools.lru_cache(maxsize=None)
 def pair(name, precision="fp64"):
-    wl, scale, degree, layers = CASES[name]
+    wl, scale, degree, layers = CASES[name][:4]
+    policy = CASES[name][4] if len(CASES[name]) > 4 else "merge"
     meshes = meshgen.hierarchy(wl, seed=0, scale=scale)
     print(f"[case {name} {precision}] levels={[m['cells'].shape[0] for m in meshes]}", flush=True)
-    gpu, ora = build_pair(meshes, degree, layers=layers, precision=precision)
+    gpu, ora = build_pair(meshes, degree, layers=layers, precision=precision, policy=policy)
     return meshes, gpu, ora
 
 
@@ -117,7 +121,7 @@ def test_pcg_fp64(name):
     assert st["true_rel_residual"] < 10 * rtol
 
 
-@pytest.mark.parametrize("name", ["square_p1_4k", "square_p2", "cube_p2"])
+@pytest.mark.parametrize("name", ["square_p1_4k", "square_p2", "cube_p2", "cube_stress_p2"])
 def test_pcg_mixed_precision(name):
     meshes, gpu, ora = pair(name)
     _, gmix, _ = pair(name, "mixed")
@@ -135,7 +139,7 @@ def test_pcg_mixed_precision(name):
 
 def test_graph_replay_matches_eager():
     meshes, gpu, ora = pair("square_p2")
-    wl, scale, degree, layers = CASES["square_p2"]
+    wl, scale, degree, layers = CASES["square_p2"][:4]
     gg = build_pair(meshes, degree, layers=layers, use_graph=True, build_oracle=False)[0]
     n = ora.levels[0].A.shape[0]
     for rep in range(3):
