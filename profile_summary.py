@@ -9,6 +9,10 @@
       FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the largest-grid launches of
       <kernel>, each scaled by the factor that maps the same counter, read on a
       1 GiB read + 1 GiB write elementwise kernel, to its known byte count.
+
+  python profile_summary.py mfma <counter_collection.csv> <out.md> "<command>" "<title>"
+      FP64 matrix-core work per dispatch (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512
+      flops) over the dispatch duration, against the FP64 matrix peak.
 """
 import csv
 import hashlib
@@ -116,10 +120,37 @@ def counters(fetch_csv, write_csv, out_json, out_md, kernel, alg_bytes, fetch_cm
     print(json.dumps(d))
 
 
+PEAK_F64_TFLOPS = 78.6
+
+
+def mfma(path, out, cmd, title):
+    per = defaultdict(dict)
+    for r in csv.DictReader(open(path)):
+        key = (int(r["Dispatch_Id"]), short(r["Kernel_Name"]), int(r["Grid_Size"]))
+        per[key][r["Counter_Name"]] = float(r["Counter_Value"])
+        per[key]["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    L = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", "```", cmd, "```", "",
+         "| dispatch | kernel | workgroups | FP64 MFMA flops | ms | TFLOP/s | of FP64 matrix peak |",
+         "|---|---|---|---|---|---|---|"]
+    tf = tt = 0.0
+    for (did, name, grid), v in sorted(per.items()):
+        fl = v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512
+        ns = v["ns"]
+        tf += fl
+        tt += ns
+        L.append(f"| {did} | `{name}` | {grid // 256} | {fl:.3e} | {ns / 1e6:.1f} | {fl / ns / 1e3:.2f} | "
+                 f"{fl / ns / 1e3 / PEAK_F64_TFLOPS:.3f} |")
+    L += ["", f"Total: {tf:.3e} flops in {tt / 1e6:.1f} ms = {tf / tt / 1e3:.2f} TFLOP/s "
+              f"({tf / tt / 1e3 / PEAK_F64_TFLOPS:.3f} of the {PEAK_F64_TFLOPS} TFLOP/s FP64 matrix peak).", ""]
+    open(out, "w").write("\n".join(L) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(*sys.argv[2:])
     elif sys.argv[1] == "counters":
         counters(*sys.argv[2:])
+    elif sys.argv[1] == "mfma":
+        mfma(*sys.argv[2:])
     else:
         sys.exit(__doc__)
