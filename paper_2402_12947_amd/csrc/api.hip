@@ -65,15 +65,18 @@ void ensure_work(Ctx &c, Level &L) {
   if (L.patch.total > 0) {
     if (mixed) {
       L.res32.alloc(L.patch.total);
-      L.py32.alloc(L.patch.ysize);
-      L.pz32.alloc(std::max<int64_t>(1, L.patch.zsize));
+      L.py32.alloc(L.patch.inv.ysize);
+      L.pz32.alloc(std::max<int64_t>(1, L.patch.inv.zsize));
     } else {
       L.res64.alloc(L.patch.total);
-      L.py64.alloc(L.patch.ysize);
-      L.pz64.alloc(std::max<int64_t>(1, L.patch.zsize));
+      L.py64.alloc(L.patch.inv.ysize);
+      L.pz64.alloc(std::max<int64_t>(1, L.patch.inv.zsize));
     }
   }
-  if (L.coarsest) L.cpart.alloc(dense_part_size(L.nfree));
+  if (L.coarsest) {
+    L.cpy.alloc(L.cpk.ysize);
+    L.cpz.alloc(std::max<int64_t>(1, L.cpk.zsize));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -146,7 +149,7 @@ template <class T>
 static void vcycle_zero(Ctx &c, int l, const T *b, T *u) {
   Level &L = c.lv[l];
   if (L.coarsest) {
-    dense_symv<T>(c.stream, L.nfree, L.cinv, b, u, L.cpart);
+    coarse_apply<T>(c.stream, L, b, u);
     return;
   }
   fill<T>(c.stream, u, L.nfree, T(0));

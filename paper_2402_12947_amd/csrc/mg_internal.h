@@ -109,6 +109,29 @@ struct Csr {
   DBuf<double> val;
 };
 
+// Symmetric inverses of a set of systems (the patches of a level, or the
+// coarsest matrix) as the lower triangle of 32 x 32 tiles: tile (I, J), J <= I,
+// of system k at tile_off[k] + (I (I + 1) / 2 + J) * 1024, row-major inside the
+// tile, zero beyond the system size.  The apply runs over row items (system,
+// tile row I, chunk of at most PACK_CHUNK tiles), each writing the row
+// products of its chunk into one 32-entry slot of py and the transposed
+// products of its off-diagonal tiles into pz (per system, column J of tile row
+// I at zoff[k] + 32 (J nb - J (J + 1) / 2) + 32 (I - J - 1)), then over gather
+// items (system, tile row J) that add them up in a fixed order.
+constexpr int PATCH_TILE = 32;
+constexpr int PACK_CHUNK = 32;
+struct PackedInv {
+  int64_t packed = 0, ysize = 0, zsize = 0;
+  DBuf<int64_t> tile_off, zoff;                 // [systems]
+  DBuf<int32_t> r_sys, r_row, r_chunk, r_slot;  // row items
+  DBuf<int32_t> g_sys, g_row, g_slot;           // gather items (first slot of the row)
+  std::vector<int> colour_r_first, colour_g_first;  // [ncolour + 1]
+  DBuf<double> v64;
+  DBuf<float> v32;
+};
+void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const std::vector<int> &colour_first,
+                         PackedInv &P);
+
 // Patches of one level in kernel order (sorted by colour, then canonical id).
 struct Patches {
   int n = 0, ncolour = 0, maxn = 0;
@@ -121,18 +144,8 @@ struct Patches {
   DBuf<int32_t> dofs_canon;   // [total] canonical free ids (factorisation)
   DBuf<int64_t> inv_off;      // [n] offset of the full inverse (n_d^2 entries, setup only)
   DBuf<double> inv64;         // full inverses, row-major (setup only)
-  // Solve phase: the inverse of every patch as the lower triangle of 32 x 32
-  // tiles (tile (I, J), J <= I, at tile_off + (I (I + 1) / 2 + J) * 1024,
-  // row-major inside the tile, zero beyond n_d).  Work items are (patch, tile
-  // row); per patch the apply keeps the row products (yoff, PT entries per
-  // tile row) and the transposed products of the off-diagonal tiles (zoff, PT
-  // entries per tile below the diagonal).
-  int64_t packed = 0, ysize = 0, zsize = 0;
-  DBuf<int64_t> tile_off, yoff, zoff;   // [n]
-  DBuf<int32_t> item_patch, item_row;   // kernel order
-  std::vector<int> colour_item_first;   // [ncolour + 1]
-  DBuf<double> pk64;
-  DBuf<float> pk32;
+  // Solve phase: the patch inverses, packed
+  PackedInv inv;
   // rows of A at the patch DOFs (kernel order), columns in solve order
   Sell rows;
 };
@@ -174,14 +187,16 @@ struct Level {
   int lanczos_steps = 0, lanczos_steps_adj = 0;
   // coarsest: dense inverse
   bool coarsest = false;
-  DBuf<double> cinv;           // [nfree * nfree]
-  DBuf<double> cpart;          // partial sums of the dense product
+  DBuf<double> cinv;           // [nfree * nfree] (setup only)
+  PackedInv cpk;               // the coarsest inverse, packed (one system)
+  DBuf<int32_t> cptr;          // {0, nfree}
+  DBuf<double> cpy, cpz;       // its apply partial products
   // V-cycle work vectors, precision of the cycle
   DBuf<double> w64[6];
   DBuf<float> w32[6];
   DBuf<double> res64;          // patch residuals [patch.total]
   DBuf<float> res32;
-  DBuf<double> py64, pz64;     // patch apply partial products [patch.ysize], [patch.zsize]
+  DBuf<double> py64, pz64;     // patch apply partial products [inv.ysize], [inv.zsize]
   DBuf<float> py32, pz32;
   double setup_ms = 0;
 };
@@ -227,7 +242,6 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m);
 void factor_patches(Ctx &c, Level &L);
 void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad);
 void build_patch_rows(Ctx &c, Level &L, bool want32);
-constexpr int PATCH_TILE = 32;
 void factor_coarsest(Ctx &c, Level &L);
 void estimate_eigenvalues(Ctx &c, Level &L);
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);
@@ -255,9 +269,9 @@ template <class T>
 void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, const T *u, T *res);
 template <class T>
 void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u);
-
 template <class T>
-void dense_symv(hipStream_t s, int64_t n, const double *M, const T *x, T *y, double *part);
+void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u);
+
 
 template <class T>
 void fill(hipStream_t s, T *x, int64_t n, T v);
@@ -270,7 +284,6 @@ void gather_perm(hipStream_t s, const A *x, const int32_t *perm, B *y, int64_t n
 template <class A, class B>
 void scatter_perm(hipStream_t s, const A *x, const int32_t *perm, B *y, int64_t n);
 void add64(hipStream_t s, double *y, const double *x, int64_t n);
-int64_t dense_part_size(int64_t n);
 int spmv_dot_blocks(const Sell &S);
 void spmv_dot(hipStream_t s, const Sell &S, const double *p, double *q, double *part);
 

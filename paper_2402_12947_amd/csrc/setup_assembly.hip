@@ -479,9 +479,10 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
 }
 
 // Solve order of a level.  sigma >= 1 is used as given; sigma == 0 lets the
-// autotuner choose: when the unsorted layout pads by more than 2 %, both the
-// unsorted layout and rows sorted inside 1024-row windows are built and the one
-// whose Chebyshev-step kernel runs faster on this GPU is kept.
+// autotuner choose: when the unsorted layout pads by more than 2 %, rows sorted
+// inside windows of 128 and of 1024 rows are built as well and the layout whose
+// Chebyshev-step kernel runs fastest on this GPU is kept (short windows cut most
+// of the padding while neighbouring rows still gather neighbouring entries).
 void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
   if (sigma >= 1) {
     order_with(c, L, sigma, want32);
@@ -489,10 +490,17 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
   }
   order_with(c, L, 1, want32);
   if ((double)L.S.stored <= 1.02 * (double)L.A.nnz || L.nfree < 65536) return;
-  double t1 = time_cheb(c, L, want32);
-  order_with(c, L, 1024, want32);
-  double t2 = time_cheb(c, L, want32);
-  if (t1 <= t2) order_with(c, L, 1, want32);
+  int best = 1;
+  double tbest = time_cheb(c, L, want32);
+  for (int cand : {128, 1024}) {
+    order_with(c, L, cand, want32);
+    double t = time_cheb(c, L, want32);
+    if (t < tbest) {
+      tbest = t;
+      best = cand;
+    }
+  }
+  if (best != 1024) order_with(c, L, best, want32);
 }
 
 // ---------------------------------------------------------------------------

@@ -164,11 +164,11 @@ void factor_patches(Ctx &c, Level &L) {
   // lower 32 x 32 tiles of every inverse, in the precision of the cycle
   (void)total;
   if (c.opt.precision == MG_MIXED) {
-    P.pk32.alloc(P.packed);
-    k_pack_patch<float><<<P.n, 256, 0, s>>>(P.ptr, P.inv_off, P.inv64, P.tile_off, P.pk32);
+    P.inv.v32.alloc(P.inv.packed);
+    k_pack_patch<float><<<P.n, 256, 0, s>>>(P.ptr, P.inv_off, P.inv64, P.inv.tile_off, P.inv.v32);
   } else {
-    P.pk64.alloc(P.packed);
-    k_pack_patch<double><<<P.n, 256, 0, s>>>(P.ptr, P.inv_off, P.inv64, P.tile_off, P.pk64);
+    P.inv.v64.alloc(P.inv.packed);
+    k_pack_patch<double><<<P.n, 256, 0, s>>>(P.ptr, P.inv_off, P.inv64, P.inv.tile_off, P.inv.v64);
   }
   MG_LAUNCH_CHECK();
   MG_HIP(hipStreamSynchronize(s));
@@ -436,6 +436,18 @@ static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, in
   MG_HIP(hipStreamSynchronize(s));
 }
 
+// one workgroup per packed tile of a single n x n system
+__global__ __launch_bounds__(256) void k_pack_single(const double *X, int64_t n, double *pk) {
+  constexpr int PT = PATCH_TILE;
+  int I, J;
+  tri_index(blockIdx.x, I, J);
+  double *out = pk + (int64_t)blockIdx.x * PT * PT;
+  for (int e = threadIdx.x; e < PT * PT; e += blockDim.x) {
+    int64_t r = (int64_t)I * PT + e / PT, cc = (int64_t)J * PT + e % PT;
+    out[e] = (r < n && cc < n) ? X[r * n + cc] : 0.0;
+  }
+}
+
 void factor_coarsest(Ctx &c, Level &L) {
   hipStream_t s = c.stream;
   int64_t n = L.nfree;
@@ -460,6 +472,18 @@ void factor_coarsest(Ctx &c, Level &L) {
   MG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   if (hb != 2147483647) fail(MG_ERR_NOT_SPD, "coarsest operator: non-positive pivot at row %d", hb);
+  // packed lower tiles of the inverse (one system)
+  std::vector<int32_t> kptr = {0, (int32_t)n};
+  std::vector<int> cf = {0, 1};
+  build_packed_layout(s, kptr, cf, L.cpk);
+  upload(L.cptr, kptr.data(), kptr.size(), s);
+  L.cpk.v64.alloc(L.cpk.packed);
+  int64_t nbt = (n + PATCH_TILE - 1) / PATCH_TILE;
+  int64_t tiles = nbt * (nbt + 1) / 2;
+  k_pack_single<<<(unsigned)tiles, 256, 0, s>>>(L.cinv, n, L.cpk.v64);
+  MG_LAUNCH_CHECK();
+  MG_HIP(hipStreamSynchronize(s));
+  L.cinv.release();
 }
 
 }  // namespace mg

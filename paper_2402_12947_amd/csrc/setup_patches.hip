@@ -222,35 +222,7 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
     acc += (int64_t)dofs[p].size() * (int64_t)dofs[p].size();
   }
   P.colour_first[ncol] = P.n;
-  std::vector<int32_t> ipatch, irow;
-  std::vector<int64_t> toff(P.n), yoff(P.n), zoff(P.n);
-  int64_t tacc = 0, yacc = 0, zacc = 0;
-  P.colour_item_first.assign(ncol + 1, 0);
-  for (int col = 0; col < ncol; ++col) {
-    P.colour_item_first[col] = (int)ipatch.size();
-    for (int k = P.colour_first[col]; k < P.colour_first[col + 1]; ++k) {
-      int64_t nb = (kptr[k + 1] - kptr[k] + PATCH_TILE - 1) / PATCH_TILE;
-      toff[k] = tacc;
-      yoff[k] = yacc;
-      zoff[k] = zacc;
-      tacc += nb * (nb + 1) / 2 * PATCH_TILE * PATCH_TILE;
-      yacc += nb * PATCH_TILE;
-      zacc += nb * (nb - 1) / 2 * PATCH_TILE;
-      for (int64_t I = 0; I < nb; ++I) {
-        ipatch.push_back(k);
-        irow.push_back((int32_t)I);
-      }
-    }
-  }
-  P.colour_item_first[ncol] = (int)ipatch.size();
-  P.packed = tacc;
-  P.ysize = yacc;
-  P.zsize = zacc;
-  upload(P.item_patch, ipatch.data(), ipatch.size(), s);
-  upload(P.item_row, irow.data(), irow.size(), s);
-  upload(P.tile_off, toff.data(), toff.size(), s);
-  upload(P.yoff, yoff.data(), yoff.size(), s);
-  upload(P.zoff, zoff.data(), zoff.size(), s);
+  build_packed_layout(s, kptr, P.colour_first, P.inv);
   P.h_kptr = kptr;
   upload(P.ptr, kptr.data(), kptr.size(), s);
   upload(P.dofs_canon, kdofs.data(), kdofs.size(), s);
@@ -262,6 +234,56 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
 __global__ void k_map_dofs(const int32_t *canon, int64_t n, const int32_t *iperm, int32_t *pos) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) pos[k] = iperm[canon[k]];
+}
+
+// Item lists and offsets of a set of packed symmetric inverses; kptr[k]..kptr[k+1]
+// is the index range of system k, colour_first the system ranges per colour.
+void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const std::vector<int> &colour_first,
+                         PackedInv &P) {
+  const int ns = (int)kptr.size() - 1, ncol = (int)colour_first.size() - 1;
+  std::vector<int64_t> toff(ns), zoff(ns);
+  std::vector<int32_t> rs, rr, rc, rslot, gs, gr, gslot;
+  int64_t tacc = 0, zacc = 0;
+  int32_t slot = 0;
+  P.colour_r_first.assign(ncol + 1, 0);
+  P.colour_g_first.assign(ncol + 1, 0);
+  for (int col = 0; col < ncol; ++col) {
+    P.colour_r_first[col] = (int)rs.size();
+    P.colour_g_first[col] = (int)gs.size();
+    for (int k = colour_first[col]; k < colour_first[col + 1]; ++k) {
+      int64_t nb = (kptr[k + 1] - kptr[k] + PATCH_TILE - 1) / PATCH_TILE;
+      toff[k] = tacc;
+      zoff[k] = zacc;
+      tacc += nb * (nb + 1) / 2 * PATCH_TILE * PATCH_TILE;
+      zacc += nb * (nb - 1) / 2 * PATCH_TILE;
+      for (int64_t I = 0; I < nb; ++I) {
+        gs.push_back(k);
+        gr.push_back((int32_t)I);
+        gslot.push_back(slot);
+        for (int64_t c = 0; c * PACK_CHUNK <= I; ++c) {
+          rs.push_back(k);
+          rr.push_back((int32_t)I);
+          rc.push_back((int32_t)c);
+          rslot.push_back(slot++);
+        }
+      }
+    }
+  }
+  P.colour_r_first[ncol] = (int)rs.size();
+  P.colour_g_first[ncol] = (int)gs.size();
+  P.packed = tacc;
+  P.ysize = (int64_t)slot * PATCH_TILE;
+  P.zsize = zacc;
+  upload(P.tile_off, toff.data(), toff.size(), s);
+  upload(P.zoff, zoff.data(), zoff.size(), s);
+  upload(P.r_sys, rs.data(), rs.size(), s);
+  upload(P.r_row, rr.data(), rr.size(), s);
+  upload(P.r_chunk, rc.data(), rc.size(), s);
+  upload(P.r_slot, rslot.data(), rslot.size(), s);
+  upload(P.g_sys, gs.data(), gs.size(), s);
+  upload(P.g_row, gr.data(), gr.size(), s);
+  upload(P.g_slot, gslot.data(), gslot.size(), s);
+  MG_HIP(hipStreamSynchronize(s));
 }
 
 // patch DOFs in the level's solve order (after solve_order has set iperm)

@@ -166,162 +166,155 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// e_d = A_d^-1 r_d from the packed lower tiles of the inverse X (symmetric).
-// One wavefront per (patch, tile row I).  Lane (h, j) = (lane >> 5, lane & 31)
-// reads rows 2 s + h, s = 0..15, of each 32 x 32 tile, column j, so every
-// tile is read once, coalesced (the next tile is in flight meanwhile).  Tile
-// (I, J) gives
-//   the column product X_IJ^T r_I  (J < I; lane-private, stored per tile in pz),
-//   the row product    X_IJ r_J     (tile transposed through the wavefront's
-//                                    LDS area, lane (h, i) sums half a row),
-// and the row products of tile row I are summed in registers and stored in py.
-template <class T>
-__global__ __launch_bounds__(256) void k_patch_rows(int i0, int i1, const int32_t *__restrict__ item_patch,
-                                                    const int32_t *__restrict__ item_row,
-                                                    const int32_t *__restrict__ ptr,
-                                                    const int64_t *__restrict__ toff,
-                                                    const int64_t *__restrict__ yoff,
-                                                    const int64_t *__restrict__ zoff, const T *__restrict__ pk,
-                                                    const T *__restrict__ res, T *__restrict__ py,
-                                                    T *__restrict__ pz) {
+// e = X r with X symmetric, stored as packed lower 32 x 32 tiles (PackedInv).
+// Row items: one wavefront per (system k, tile row I, chunk of at most
+// PACK_CHUNK tiles).  Lane (h, j) = (lane >> 5, lane & 31) reads rows 2 s + h,
+// s = 0..15, column j of each tile, so every tile is read once, coalesced,
+// the next tile already in flight.  Tile (I, J) gives
+//   the column product X_IJ^T r_I  (J < I; lane-private, one 32-entry vector
+//                                   per tile in pz, column-major over tiles),
+//   the row product    X_IJ r_J     (the tile is transposed through the
+//                                   wavefront's LDS area, lane (h, i) sums half
+//                                   of row i),
+// and the row products of the chunk are summed in registers into one py slot.
+// TM is the storage and arithmetic type, TV the type of r.
+template <class TM, class TV>
+__global__ __launch_bounds__(256) void k_packed_rows(int i0, int i1, const int32_t *__restrict__ r_sys,
+                                                     const int32_t *__restrict__ r_row,
+                                                     const int32_t *__restrict__ r_chunk,
+                                                     const int32_t *__restrict__ r_slot,
+                                                     const int32_t *__restrict__ ptr,
+                                                     const int64_t *__restrict__ toff,
+                                                     const int64_t *__restrict__ zoff, const TM *__restrict__ pk,
+                                                     const TV *__restrict__ res, TM *__restrict__ py,
+                                                     TM *__restrict__ pz) {
   constexpr int PT = PATCH_TILE;
-  __shared__ T tl[4][PT][PT + 1];
-  __shared__ T rl[4][PT];
+  __shared__ TM tl[4][PT][PT + 1];
+  __shared__ TM rl[4][PT];
   const int wave = threadIdx.x >> 6;
   const int item = i0 + (int)(blockIdx.x * 4 + wave);
   if (item >= i1) return;
   const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
-  T(*Ts)[PT + 1] = tl[wave];
-  T *Rs = rl[wave];
-  const int p = item_patch[item], I = item_row[item];
-  const int k0 = ptr[p], n = ptr[p + 1] - k0;
-  const T *r = res + k0;
-  T rI[16];
+  TM(*Ts)[PT + 1] = tl[wave];
+  TM *Rs = rl[wave];
+  const int k = r_sys[item], I = r_row[item];
+  const int J0 = r_chunk[item] * PACK_CHUNK, J1 = min(I + 1, J0 + PACK_CHUNK);
+  const int k0 = ptr[k], n = ptr[k + 1] - k0, nb = (n + PT - 1) / PT;
+  const TV *r = res + k0;
+  TM rI[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     int i = I * PT + 2 * s + h;
-    rI[s] = i < n ? r[i] : (T)0;
+    rI[s] = i < n ? (TM)r[i] : (TM)0;
   }
-  const T *tile = pk + toff[p] + (int64_t)I * (I + 1) / 2 * PT * PT + h * PT + j;
-  T yrow = 0;
-  T v[16], nxt[16];
+  const TM *tile = pk + toff[k] + ((int64_t)I * (I + 1) / 2 + J0) * PT * PT + h * PT + j;
+  TM *zcol = pz + zoff[k] + (int64_t)(I - 1) * PT + j;  // + 32 (J nb - J (J + 1) / 2 - J)
+  TM yrow = 0;
+  TM v[16], nxt[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) nxt[s] = __builtin_nontemporal_load(tile + 2 * s * PT);
-  for (int J = 0; J <= I; ++J) {
+  for (int J = J0; J < J1; ++J) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) v[s] = nxt[s];
     tile += PT * PT;
-    if (J < I) {
+    if (J + 1 < J1) {
 #pragma unroll
       for (int s = 0; s < 16; ++s) nxt[s] = __builtin_nontemporal_load(tile + 2 * s * PT);
-      T cs = 0;
+    }
+    if (J < I) {
+      TM cs = 0;
 #pragma unroll
       for (int s = 0; s < 16; ++s) cs += v[s] * rI[s];
       cs += __shfl_xor(cs, 32);
-      if (h == 0) pz[zoff[p] + ((int64_t)I * (I - 1) / 2 + J) * PT + j] = cs;
+      if (h == 0) zcol[(int64_t)PT * ((int64_t)J * nb - (int64_t)J * (J + 1) / 2 - J)] = cs;
     }
     const int jj = J * PT + j;
-    if (h == 0) Rs[j] = jj < n ? r[jj] : (T)0;
+    if (h == 0) Rs[j] = jj < n ? (TM)r[jj] : (TM)0;
 #pragma unroll
     for (int s = 0; s < 16; ++s) Ts[2 * s + h][j] = v[s];
     wave_sync();
-    T acc = 0;
+    TM acc = 0;
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc += Ts[j][16 * h + t] * Rs[16 * h + t];
     yrow += acc + __shfl_xor(acc, 32);  // row j
     wave_sync();
   }
-  if (h == 0) py[yoff[p] + (int64_t)I * PT + j] = yrow;
+  if (h == 0) py[(int64_t)r_slot[item] * PT + j] = yrow;
 }
 
-// e_J = (row products of tile row J) + sum_{I > J} (column products of tile
-// (I, J)), in a fixed order; u[B_d] += e (patches of one colour share no DOF).
-template <class T>
-__global__ __launch_bounds__(256) void k_patch_gather(int i0, int i1, const int32_t *__restrict__ item_patch,
-                                                      const int32_t *__restrict__ item_row,
-                                                      const int32_t *__restrict__ ptr,
-                                                      const int32_t *__restrict__ dofs,
-                                                      const int64_t *__restrict__ yoff,
-                                                      const int64_t *__restrict__ zoff, const T *__restrict__ py,
-                                                      const T *__restrict__ pz, T *__restrict__ u) {
+// Gather items: e_J = (row products of the chunks of tile row J) + sum over
+// I > J of the column products of tile (I, J), in a fixed order; then
+// u[map(i)] += e (ADD; patches of one colour share no DOF) or u[i] = e (SET,
+// identity map).
+template <class TM, class TV, bool SET>
+__global__ __launch_bounds__(256) void k_packed_gather(int i0, int i1, const int32_t *__restrict__ g_sys,
+                                                       const int32_t *__restrict__ g_row,
+                                                       const int32_t *__restrict__ g_slot,
+                                                       const int32_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ map,
+                                                       const int64_t *__restrict__ zoff,
+                                                       const TM *__restrict__ py, const TM *__restrict__ pz,
+                                                       TV *__restrict__ u) {
   constexpr int PT = PATCH_TILE;
   const int item = i0 + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (item >= i1) return;
   const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
-  const int p = item_patch[item], J = item_row[item];
-  const int k0 = ptr[p], n = ptr[p + 1] - k0, nb = (n + PT - 1) / PT;
-  T e = 0;
-  for (int I = J + 1 + h; I < nb; I += 2) e += pz[zoff[p] + ((int64_t)I * (I - 1) / 2 + J) * PT + j];
+  const int k = g_sys[item], J = g_row[item];
+  const int k0 = ptr[k], n = ptr[k + 1] - k0, nb = (n + PT - 1) / PT;
+  const int nch = J / PACK_CHUNK + 1;
+  TM e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+  const TM *y = py + (int64_t)g_slot[item] * PT + j;
+  for (int c = h; c < nch; c += 2) e0 += y[(int64_t)c * PT];
+  const int cnt = nb - J - 1;  // tiles below the diagonal in tile column J
+  const TM *z = pz + zoff[k] + (int64_t)PT * ((int64_t)J * nb - (int64_t)J * (J + 1) / 2) + j;
+  int t = h;
+  for (; t + 6 < cnt; t += 8) {
+    e0 += z[(int64_t)t * PT];
+    e1 += z[(int64_t)(t + 2) * PT];
+    e2 += z[(int64_t)(t + 4) * PT];
+    e3 += z[(int64_t)(t + 6) * PT];
+  }
+  for (; t < cnt; t += 2) e0 += z[(int64_t)t * PT];
+  TM e = (e0 + e1) + (e2 + e3);
   e += __shfl_xor(e, 32);
   const int i = J * PT + j;
-  if (h == 0 && i < n) u[dofs[k0 + i]] += py[yoff[p] + (int64_t)J * PT + j] + e;
+  if (h == 0 && i < n) {
+    if (SET) u[i] = (TV)e;
+    else u[map[k0 + i]] += (TV)e;
+  }
+}
+
+template <class TM, class TV, bool SET>
+static void packed_apply(hipStream_t s, const PackedInv &P, const TM *pk, int colour, const int32_t *ptr,
+                         const int32_t *map, const TV *res, TM *py, TM *pz, TV *u) {
+  int r0 = P.colour_r_first[colour], r1 = P.colour_r_first[colour + 1];
+  int g0 = P.colour_g_first[colour], g1 = P.colour_g_first[colour + 1];
+  if (r1 <= r0) return;
+  k_packed_rows<TM, TV><<<(unsigned)((r1 - r0 + 3) / 4), 256, 0, s>>>(r0, r1, P.r_sys, P.r_row, P.r_chunk, P.r_slot,
+                                                                      ptr, P.tile_off, P.zoff, pk, res, py, pz);
+  MG_LAUNCH_CHECK();
+  k_packed_gather<TM, TV, SET><<<(unsigned)((g1 - g0 + 3) / 4), 256, 0, s>>>(g0, g1, P.g_sys, P.g_row, P.g_slot,
+                                                                             ptr, map, P.zoff, py, pz, u);
+  MG_LAUNCH_CHECK();
 }
 
 template <class T>
 void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u) {
-  int i0 = pt.colour_item_first[colour], i1 = pt.colour_item_first[colour + 1];
-  if (i1 <= i0) return;
-  const T *pk = std::is_same<T, double>::value ? (const T *)pt.pk64.p : (const T *)pt.pk32.p;
-  unsigned g = (unsigned)((i1 - i0 + 3) / 4);
-  k_patch_rows<T><<<g, 256, 0, s>>>(i0, i1, pt.item_patch, pt.item_row, pt.ptr, pt.tile_off, pt.yoff, pt.zoff, pk,
-                                    res, py, pz);
-  MG_LAUNCH_CHECK();
-  k_patch_gather<T><<<g, 256, 0, s>>>(i0, i1, pt.item_patch, pt.item_row, pt.ptr, pt.dofs, pt.yoff, pt.zoff, py,
-                                      pz, u);
-  MG_LAUNCH_CHECK();
+  const T *pk = std::is_same<T, double>::value ? (const T *)pt.inv.v64.p : (const T *)pt.inv.v32.p;
+  packed_apply<T, T, false>(s, pt.inv, pk, colour, pt.ptr, pt.dofs, res, py, pz, u);
 }
 template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *, double *, double *);
 template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *, float *, float *);
 
-// ---------------------------------------------------------------------------
-// coarsest: y = M x with the dense symmetric inverse (FP64 arithmetic)
-// ---------------------------------------------------------------------------
+// coarsest level: u = A^-1 b with the packed FP64 inverse (FP64 arithmetic)
 template <class T>
-__global__ __launch_bounds__(256) void k_dense_part(int64_t n, int64_t chunk, const double *__restrict__ M,
-                                                    const T *__restrict__ x, double *__restrict__ part) {
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = j0 + chunk < n ? j0 + chunk : n;
-  if (i >= n) return;
-  double a0 = 0, a1 = 0;
-  int64_t j = j0;
-  for (; j + 1 < j1; j += 2) {
-    a0 += M[j * n + i] * (double)x[j];
-    a1 += M[(j + 1) * n + i] * (double)x[j + 1];
-  }
-  if (j < j1) a0 += M[j * n + i] * (double)x[j];
-  part[(int64_t)blockIdx.y * n + i] = a0 + a1;
+void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u) {
+  packed_apply<double, T, true>(s, L.cpk, L.cpk.v64.p, 0, L.cptr, nullptr, b, L.cpy.p, L.cpz.p, u);
 }
-template <class T>
-__global__ void k_dense_finish(int64_t n, int nsplit, const double *__restrict__ part, T *__restrict__ y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0;
-  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
-  y[i] = (T)s;
-}
+template void coarse_apply<double>(hipStream_t, const Level &, const double *, double *);
+template void coarse_apply<float>(hipStream_t, const Level &, const float *, float *);
 
-static int dense_split(int64_t n) {
-  int64_t rows = (n + 255) / 256;
-  int64_t want = (2048 + rows - 1) / rows;
-  int64_t maxs = (n + 63) / 64;
-  int64_t sp = want < maxs ? want : maxs;
-  return (int)(sp < 1 ? 1 : sp);
-}
 
-template <class T>
-void dense_symv(hipStream_t s, int64_t n, const double *M, const T *x, T *y, double *part) {
-  int nsplit = dense_split(n);
-  int64_t chunk = (n + nsplit - 1) / nsplit;
-  dim3 g((unsigned)((n + 255) / 256), (unsigned)nsplit);
-  k_dense_part<T><<<g, 256, 0, s>>>(n, chunk, M, x, part);
-  MG_LAUNCH_CHECK();
-  k_dense_finish<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, nsplit, part, y);
-  MG_LAUNCH_CHECK();
-}
-template void dense_symv<double>(hipStream_t, int64_t, const double *, const double *, double *, double *);
-template void dense_symv<float>(hipStream_t, int64_t, const double *, const float *, float *, double *);
-
-int64_t dense_part_size(int64_t n) { return (int64_t)dense_split(n) * n; }
 
 // ---------------------------------------------------------------------------
 // vector kernels
