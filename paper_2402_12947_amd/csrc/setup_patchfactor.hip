@@ -11,9 +11,10 @@
 //   3. A^-1 = W^T W (lower tiles, mirrored).
 // Every tile product is a 32 x 32 x 32 FP64 product on the matrix cores
 // (v_mfma_f64_16x16x4: each wavefront owns one output tile, 2 x 2 blocks of
-// 16 x 16), with both operand tiles staged in the wavefront's own LDS area.
-// Tiles of one step are dealt to the four wavefronts in rounds; steps are
-// separated by workgroup barriers.  Patches are launched largest first so the
+// 16 x 16), its operands loaded straight from memory into the MFMA register
+// layout (all 32 loads of a tile in flight at once).  Tiles of one step are
+// dealt to the four wavefronts, which run independently; steps are separated
+// by workgroup barriers.  Only the diagonal tile and its inverse live in LDS.  Patches are launched largest first so the
 // long ones start early (longest-processing-time order).
 #include <cmath>
 
@@ -30,9 +31,6 @@ constexpr int PLD = PT + 1;  // LDS row stride (bank spread)
 struct PatchSmem {
   double Ld[PT][PLD];        // diagonal tile (factor, in place)
   double Li[PT][PLD];        // its inverse
-  double A[4][PT][PLD];      // per-wavefront operand tiles
-  double B[4][PT][PLD];
-  int fail;
 };
 
 __device__ inline void tri_rc(int t, int &i, int &j) {
@@ -44,28 +42,33 @@ __device__ inline void tri_rc(int t, int &i, int &j) {
   j = t - ii * (ii + 1) / 2;
 }
 
-// wavefront-cooperative copy of tile (rb, cb) of the n x n row-major matrix M
-// into S (transposed if asked), zeros outside the matrix
-__device__ inline void wave_load(const double *M, int n, int rb, int cb, bool trans, double (*S)[PLD], int lane) {
-  for (int t = lane; t < PT * PT; t += 64) {
-    int i = t / PT, j = t % PT;
-    int r = rb * PT + i, c = cb * PT + j;
-    double v = (r < n && c < n) ? M[(int64_t)r * n + c] : 0.0;
-    if (trans) S[j][i] = v; else S[i][j] = v;
-  }
+// MFMA operand registers of one 32 x 32 tile, read straight from the n x n
+// row-major matrix M: element (x, y) of the operand is M[r0 + x][c0 + y], or
+// M[r0 + y][c0 + x] when swap is set (zero outside the matrix).  For the A
+// operand lane l holds (x, y) = (16 blk + l % 16, 4 s + l / 16), for the B
+// operand (4 s + l / 16, 16 blk + l % 16); o[blk * 8 + s].
+template <bool ROLE_A>
+__device__ inline void fetch_ops(const double *M, int n, int r0, int c0, bool swap, double o[16], int lane) {
+  const int p = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int x = ROLE_A ? 16 * blk + p : 4 * s + q;
+      const int y = ROLE_A ? 4 * s + q : 16 * blk + p;
+      const int r = swap ? r0 + y : r0 + x, c = swap ? c0 + x : c0 + y;
+      o[blk * 8 + s] = (r < n && c < n) ? M[(int64_t)r * n + c] : 0.0;
+    }
 }
 
-// acc (a 32 x 32 tile as 2 x 2 MFMA blocks) += As * Bs
-__device__ inline void wave_mma(v4d acc[2][2], const double (*As)[PLD], const double (*Bs)[PLD], int lane) {
-  const int r = lane & 15, q = lane >> 4;
+// acc (a 32 x 32 tile as 2 x 2 MFMA blocks) += A B
+__device__ inline void mma_ops(v4d acc[2][2], const double a[16], const double b[16]) {
 #pragma unroll
-  for (int k0 = 0; k0 < PT; k0 += 4) {
-    double a0 = As[r][k0 + q], a1 = As[16 + r][k0 + q];
-    double b0 = Bs[k0 + q][r], b1 = Bs[k0 + q][16 + r];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  for (int s = 0; s < 8; ++s) {
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[8 + s], acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 + s], b[s], acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 + s], b[8 + s], acc[1][1], 0, 0, 0);
   }
 }
 
@@ -108,7 +111,6 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
     M[t] = 0.0;
     W[t] = 0.0;
   }
-  if (tid == 0) sm.fail = 0;
   __syncthreads();
   for (int i = wave; i < n; i += 4) {
     int32_t r = Bd[i];
@@ -168,49 +170,41 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
       M[(int64_t)(o + i) * n + o + j] = j <= i ? sm.Ld[i][j] : 0.0;
       W[(int64_t)(o + i) * n + o + j] = j <= i ? sm.Li[i][j] : 0.0;
     }
-    // panel: M[ib, kb] <- M[ib, kb] Li^T
+    // panel: M[ib, kb] <- M[ib, kb] Li^T (tiles dealt to the wavefronts; the
+    // operands come straight from memory, Li^T from LDS)
     const int rest = nb - kb - 1;
-    for (int t0 = 0; t0 < rest; t0 += 4) {
-      const int t = t0 + wave;
-      __syncthreads();
-      if (t < rest) {
-        wave_load(M, n, kb + 1 + t, kb, false, sm.A[wave], lane);
-        for (int e = lane; e < PT * PT; e += 64) sm.B[wave][e / PT][e % PT] = sm.Li[e % PT][e / PT];
-      }
-      __syncthreads();
-      if (t < rest) {
-        v4d acc[2][2];
-        zero_acc(acc);
-        wave_mma(acc, sm.A[wave], sm.B[wave], lane);
-        const int ro = (kb + 1 + t) * PT;
-        for_acc(acc, lane, [&](int i, int j, double v) {
-          if (ro + i < n && o + j < n) M[(int64_t)(ro + i) * n + o + j] = v;
-        });
-      }
+    for (int t = wave; t < rest; t += 4) {
+      const int ib = kb + 1 + t;
+      double a[16], b[16];
+      fetch_ops<true>(M, n, ib * PT, o, false, a, lane);
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) b[blk * 8 + s2] = sm.Li[16 * blk + (lane & 15)][4 * s2 + (lane >> 4)];
+      v4d acc[2][2];
+      zero_acc(acc);
+      mma_ops(acc, a, b);
+      for_acc(acc, lane, [&](int i, int j, double v) {
+        if (ib * PT + i < n && o + j < n) M[(int64_t)(ib * PT + i) * n + o + j] = v;
+      });
     }
     __syncthreads();
     // trailing lower triangle: M[ib, jb] -= M[ib, kb] M[jb, kb]^T
     const int ntr = rest * (rest + 1) / 2;
-    for (int t0 = 0; t0 < ntr; t0 += 4) {
-      const int t = t0 + wave;
+    for (int t = wave; t < ntr; t += 4) {
       int i = 0, j = 0;
-      if (t < ntr) tri_rc(t, i, j);
+      tri_rc(t, i, j);
       const int ib = kb + 1 + i, jb = kb + 1 + j;
-      __syncthreads();
-      if (t < ntr) {
-        wave_load(M, n, ib, kb, false, sm.A[wave], lane);
-        wave_load(M, n, jb, kb, true, sm.B[wave], lane);
-      }
-      __syncthreads();
-      if (t < ntr) {
-        v4d acc[2][2];
-        zero_acc(acc);
-        wave_mma(acc, sm.A[wave], sm.B[wave], lane);
-        for_acc(acc, lane, [&](int r, int c, double v) {
-          int gr = ib * PT + r, gc = jb * PT + c;
-          if (gr < n && gc < n) M[(int64_t)gr * n + gc] -= v;
-        });
-      }
+      double a[16], b[16];
+      fetch_ops<true>(M, n, ib * PT, o, false, a, lane);
+      fetch_ops<false>(M, n, jb * PT, o, true, b, lane);
+      v4d acc[2][2];
+      zero_acc(acc);
+      mma_ops(acc, a, b);
+      for_acc(acc, lane, [&](int r, int c, double v) {
+        int gr = ib * PT + r, gc = jb * PT + c;
+        if (gr < n && gc < n) M[(int64_t)gr * n + gc] -= v;
+      });
     }
     __syncthreads();
   }
@@ -218,85 +212,56 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
   // 2. W = L^-1: block row kb is finished by W[kb, jb] <- Li_kk W[kb, jb]
   // (jb < kb), then pushed into the rows below: W[ib, jb] -= L[ib, kb] W[kb, jb]
   for (int kb = 0; kb < nb; ++kb) {
-    for (int t0 = 0; t0 < kb; t0 += 4) {
-      const int jb = t0 + wave;
-      __syncthreads();
-      if (jb < kb) {
-        wave_load(W, n, kb, kb, false, sm.A[wave], lane);
-        wave_load(W, n, kb, jb, false, sm.B[wave], lane);
-      }
-      __syncthreads();
-      if (jb < kb) {
-        v4d acc[2][2];
-        zero_acc(acc);
-        wave_mma(acc, sm.A[wave], sm.B[wave], lane);
-        for_acc(acc, lane, [&](int r, int c, double v) {
-          int gr = kb * PT + r, gc = jb * PT + c;
-          if (gr < n && gc < n) W[(int64_t)gr * n + gc] = v;
-        });
-      }
+    for (int jb = wave; jb < kb; jb += 4) {
+      double a[16], b[16];
+      fetch_ops<true>(W, n, kb * PT, kb * PT, false, a, lane);
+      fetch_ops<false>(W, n, kb * PT, jb * PT, false, b, lane);
+      v4d acc[2][2];
+      zero_acc(acc);
+      mma_ops(acc, a, b);
+      for_acc(acc, lane, [&](int r, int c, double v) {
+        int gr = kb * PT + r, gc = jb * PT + c;
+        if (gr < n && gc < n) W[(int64_t)gr * n + gc] = v;
+      });
     }
     __syncthreads();
     const int below = nb - kb - 1, nt = below * (kb + 1);
-    for (int t0 = 0; t0 < nt; t0 += 4) {
-      const int t = t0 + wave;
+    for (int t = wave; t < nt; t += 4) {
       const int ib = kb + 1 + t / (kb + 1), jb = t % (kb + 1);
-      __syncthreads();
-      if (t < nt) {
-        wave_load(M, n, ib, kb, false, sm.A[wave], lane);
-        wave_load(W, n, kb, jb, false, sm.B[wave], lane);
-      }
-      __syncthreads();
-      if (t < nt) {
-        v4d acc[2][2];
-        zero_acc(acc);
-        wave_mma(acc, sm.A[wave], sm.B[wave], lane);
-        for_acc(acc, lane, [&](int r, int c, double v) {
-          int gr = ib * PT + r, gc = jb * PT + c;
-          if (gr < n && gc < n) W[(int64_t)gr * n + gc] -= v;
-        });
-      }
+      double a[16], b[16];
+      fetch_ops<true>(M, n, ib * PT, kb * PT, false, a, lane);
+      fetch_ops<false>(W, n, kb * PT, jb * PT, false, b, lane);
+      v4d acc[2][2];
+      zero_acc(acc);
+      mma_ops(acc, a, b);
+      for_acc(acc, lane, [&](int r, int c, double v) {
+        int gr = ib * PT + r, gc = jb * PT + c;
+        if (gr < n && gc < n) W[(int64_t)gr * n + gc] -= v;
+      });
     }
     __syncthreads();
   }
 
   // 3. X = W^T W: X[ib, jb] = sum_{k >= ib} W[k, ib]^T W[k, jb], jb <= ib, mirrored
   const int nx = nb * (nb + 1) / 2;
-  for (int t0 = 0; t0 < nx; t0 += 4) {
-    const int t = t0 + wave;
+  for (int t = wave; t < nx; t += 4) {
     int ib = 0, jb = 0;
-    if (t < nx) tri_rc(t, ib, jb);
+    tri_rc(t, ib, jb);
     v4d acc[2][2];
     zero_acc(acc);
-    // every wavefront runs the same number of k rounds (barriers stay uniform)
-    int kmax = 0;
-    for (int w = 0; w < 4; ++w) {
-      int tw = t0 + w, iw = 0, jw = 0;
-      if (tw < nx) {
-        tri_rc(tw, iw, jw);
-        kmax = max(kmax, nb - iw);
+    for (int k = ib; k < nb; ++k) {
+      double a[16], b[16];
+      fetch_ops<true>(W, n, k * PT, ib * PT, true, a, lane);
+      fetch_ops<false>(W, n, k * PT, jb * PT, false, b, lane);
+      mma_ops(acc, a, b);
+    }
+    for_acc(acc, lane, [&](int r, int c, double v) {
+      int gr = ib * PT + r, gc = jb * PT + c;
+      if (gr < n && gc < n && (ib != jb || r >= c)) {  // diagonal tiles: lower half, mirrored
+        X[(int64_t)gr * n + gc] = v;
+        X[(int64_t)gc * n + gr] = v;
       }
-    }
-    for (int kk = 0; kk < kmax; ++kk) {
-      const int k = ib + kk;
-      const bool on = t < nx && k < nb;
-      __syncthreads();
-      if (on) {
-        wave_load(W, n, k, ib, true, sm.A[wave], lane);
-        wave_load(W, n, k, jb, false, sm.B[wave], lane);
-      }
-      __syncthreads();
-      if (on) wave_mma(acc, sm.A[wave], sm.B[wave], lane);
-    }
-    if (t < nx) {
-      for_acc(acc, lane, [&](int r, int c, double v) {
-        int gr = ib * PT + r, gc = jb * PT + c;
-        if (gr < n && gc < n && (ib != jb || r >= c)) {  // diagonal tiles: lower half, mirrored
-          X[(int64_t)gr * n + gc] = v;
-          X[(int64_t)gc * n + gr] = v;
-        }
-      });
-    }
+    });
   }
 }
 
@@ -306,7 +271,11 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
 void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad) {
   Patches &P = L.patch;
   hipStream_t s = c.stream;
-  constexpr int64_t SCRATCH_CAP = (int64_t)1 << 29;  // 4 GiB of FP64
+  // scratch per launch: a quarter of the free device memory, 1-48 GiB
+  size_t free_b = 0, total_b = 0;
+  MG_HIP(hipMemGetInfo(&free_b, &total_b));
+  const int64_t SCRATCH_CAP =
+      std::min<int64_t>((int64_t)6 << 30, std::max<int64_t>((int64_t)1 << 27, (int64_t)(free_b / 4 / 8)));
   std::vector<int32_t> order;
   for (int k = 0; k < P.n; ++k) (P.h_kptr[k + 1] - P.h_kptr[k] <= batch_max ? order : rest).push_back(k);
   auto size = [&](int32_t k) { return (int64_t)(P.h_kptr[k + 1] - P.h_kptr[k]); };
