@@ -119,6 +119,7 @@ typedef struct {
   int64_t sell_stored;      /* stored SELL entries incl. padding               */
   int32_t is_coarsest;
   double setup_ms;          /* setup time spent on this level                  */
+  int64_t sell_nnz16;       /* nonzeros stored with 16-bit column indices      */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */

@@ -53,7 +53,8 @@ class MgLevelInfo(C.Structure):
                 ("sum_patch_dofs", C.c_int64), ("gamma_min", C.c_double), ("lambda_max", C.c_double),
                 ("lambda_adj", C.c_double), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
                 ("lanczos_steps", C.c_int32), ("lanczos_steps_adj", C.c_int32), ("sell_sigma", C.c_int32),
-                ("sell_stored", C.c_int64), ("is_coarsest", C.c_int32), ("setup_ms", C.c_double)]
+                ("sell_stored", C.c_int64), ("is_coarsest", C.c_int32), ("setup_ms", C.c_double),
+                ("sell_nnz16", C.c_int64)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:

@@ -620,6 +620,7 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->lanczos_steps_adj = L.lanczos_steps_adj;
   o->sell_sigma = L.S.sigma;
   o->sell_stored = L.S.stored;
+  o->sell_nnz16 = L.S.nnz16;
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;
   return MG_OK;
@@ -689,8 +690,10 @@ mg_status mg_cheb_algorithmic_bytes(const mg_ctx *h, double *bytes) {
   if (!h || !bytes) return MG_ERR_ARG;
   const Level &L = h->impl.lv[0];
   if (L.coarsest) return MG_ERR_ARG;
-  double nnz = (double)L.A.nnz, n = (double)L.nfree;
-  *bytes = h->impl.opt.precision == MG_MIXED ? 8.0 * nnz + 24.0 * n : 12.0 * nnz + 48.0 * n;
+  // values once, column indices once (2 bytes in 16-bit slices), x, b, D^-1, d
+  // read, d and x' written
+  double n16 = (double)L.S.nnz16, n32 = (double)(L.S.nnz - L.S.nnz16), n = (double)L.nfree;
+  *bytes = h->impl.opt.precision == MG_MIXED ? 6.0 * n16 + 8.0 * n32 + 24.0 * n : 10.0 * n16 + 12.0 * n32 + 48.0 * n;
   return MG_OK;
 }
 

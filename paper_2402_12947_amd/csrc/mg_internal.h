@@ -100,6 +100,12 @@ struct Sell {
   DBuf<int32_t> col;        // [stored]
   DBuf<double> v64;         // [stored] (FP64 copy)
   DBuf<float> v32;          // [stored] (FP32 copy, mixed precision)
+  // 16-bit columns: a slice whose columns fit two windows of 32768 stores
+  // column c as c - base0 (below 0x8000) or 0x8000 | (c - base1); cbase holds
+  // (base0, base1) per slice, base0 = -1 for slices kept at 32 bits
+  DBuf<uint16_t> col16;     // [stored]
+  DBuf<int32_t> cbase;      // [2 * nslices]
+  int64_t nnz = 0, nnz16 = 0;  // entries, entries in 16-bit slices
 };
 
 struct Csr {

@@ -326,6 +326,60 @@ __global__ void k_sell_fill(const int64_t *rowptr, const int32_t *ccol, const do
   }
 }
 
+__device__ inline int wave_min_i(int v) {
+  for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m));
+  return v;
+}
+
+// One wavefront per slice: find two windows of 32768 columns covering every
+// column of the slice; if they exist, store the 16-bit form and the bases.
+__global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const int64_t *sptr, const int32_t *col,
+                                                       const int64_t *rp, int64_t nrows, uint16_t *col16,
+                                                       int32_t *cbase, unsigned long long *nnz16) {
+  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (sl >= nslices) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t base = sptr[sl];
+  const int w = (int)((sptr[sl + 1] - base) / SELL_C);
+  const int32_t *cp = col + base + lane;
+  int mn = 2147483647;
+  for (int j = 0; j < w; ++j) mn = min(mn, cp[(int64_t)j * SELL_C]);
+  mn = wave_min_i(mn);
+  int mn1 = 2147483647;
+  for (int j = 0; j < w; ++j) {
+    int c = cp[(int64_t)j * SELL_C];
+    if (c - mn >= 32768) mn1 = min(mn1, c);
+  }
+  mn1 = wave_min_i(mn1);
+  int bad = 0;
+  for (int j = 0; j < w; ++j) {
+    int c = cp[(int64_t)j * SELL_C];
+    if (c - mn >= 32768 && c - mn1 >= 32768) bad = 1;
+  }
+  bad = -wave_min_i(-bad);
+  if (bad) {
+    if (lane == 0) {
+      cbase[2 * sl] = -1;
+      cbase[2 * sl + 1] = -1;
+    }
+    return;
+  }
+  const int b1 = mn1 == 2147483647 ? mn : mn1;
+  uint16_t *op = col16 + base + lane;
+  for (int j = 0; j < w; ++j) {
+    int c = cp[(int64_t)j * SELL_C];
+    op[(int64_t)j * SELL_C] = c - mn < 32768 ? (uint16_t)(c - mn) : (uint16_t)(0x8000 | (c - b1));
+  }
+  const int64_t r = sl * SELL_C + lane;
+  unsigned long long len = r < nrows ? (unsigned long long)(rp[r + 1] - rp[r]) : 0ull;
+  for (int m = 32; m >= 1; m >>= 1) len += __shfl_xor(len, m);
+  if (lane == 0) {
+    cbase[2 * sl] = mn;
+    cbase[2 * sl + 1] = b1;
+    atomicAdd(nnz16, len);
+  }
+}
+
 // SELL-C layout of A with its rows in their given order (row = position); the
 // solve order (solve_order) is applied to A beforehand.
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
@@ -352,7 +406,21 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
   k_sell_fill<<<grid_for(npos, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, S.perm, S.slice_ptr, npos, S.col, S.v64,
                                                  want32 ? S.v32.p : nullptr);
   MG_LAUNCH_CHECK();
+  S.nnz = A.nnz;
+  S.col16.alloc(S.stored);
+  S.cbase.alloc(2 * S.nslices);
+  DBuf<unsigned long long> cnt;
+  cnt.alloc(1);
+  MG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+  if (S.nslices > 0) {
+    k_compress_cols<<<(unsigned)((S.nslices + 3) / 4), 256, 0, s>>>(S.nslices, S.slice_ptr, S.col, A.rowptr,
+                                                                    A.nrows, S.col16, S.cbase, cnt);
+    MG_LAUNCH_CHECK();
+  }
+  unsigned long long h16 = 0;
+  MG_HIP(hipMemcpyAsync(&h16, cnt.p, sizeof(h16), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
+  S.nnz16 = (int64_t)h16;
 }
 
 // ---------------------------------------------------------------------------

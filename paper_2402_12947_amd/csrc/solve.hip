@@ -19,15 +19,22 @@
 
 namespace mg {
 
-// Row `lane` of slice `sl`: the matrix entries are streamed once per product,
-// so they are loaded non-temporally and leave the cache to the gathered vector.
-template <class T>
-__device__ inline T sell_row(const int64_t *__restrict__ sptr, const int32_t *__restrict__ col,
-                             const T *__restrict__ val, const T *__restrict__ x, int64_t sl, int lane) {
-  int64_t base = sptr[sl];
-  int w = (int)((sptr[sl + 1] - base) >> 6);
-  const int32_t *cp = col + base + lane;
-  const T *vp = val + base + lane;
+// Column arrays of a SELL matrix as the solve kernels read them.
+struct SellCols {
+  const int64_t *sptr;
+  const int32_t *col;
+  const uint16_t *col16;
+  const int32_t *cbase;
+};
+static inline SellCols cols_of(const Sell &S) { return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p}; }
+
+// Row `lane` of slice `sl` (sl is the same for the whole wavefront): the matrix
+// entries are streamed once per product, so they are loaded non-temporally and
+// leave the cache to the gathered vector; slices whose columns fit two windows
+// of 32768 read 16-bit columns.
+template <class T, class C, class F>
+__device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
+                             F decode) {
   constexpr int U = 8;  // eight independent gathers in flight per lane
   T a[U];
 #pragma unroll
@@ -38,28 +45,43 @@ __device__ inline T sell_row(const int64_t *__restrict__ sptr, const int32_t *__
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      c[u] = __builtin_nontemporal_load(cp + (j + u) * 64);
+      c[u] = decode(__builtin_nontemporal_load(cp + (j + u) * 64));
       v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) a[u] += v[u] * x[c[u]];
   }
-  for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[__builtin_nontemporal_load(cp + j * 64)];
+  for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[decode(__builtin_nontemporal_load(cp + j * 64))];
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+template <class T>
+__device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
+                             int lane) {
+  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
+  const int64_t base = S.sptr[s32];
+  const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
+  const T *vp = val + base + lane;
+  const int b0 = S.cbase[2 * s32];
+  if (b0 >= 0) {
+    const int bh = S.cbase[2 * s32 + 1] - 0x8000;
+    return sell_dot(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
+  }
+  return sell_dot(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; });
 }
 
 // Unknowns are numbered in the operator's row order (solve order), so the row
 // of a SELL position is the position itself; positions past nrows are padding.
 template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nrows, const int64_t *__restrict__ sptr,
-                                                   const int32_t *__restrict__ col, const T *__restrict__ val,
+__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nrows, SellCols cols,
+                                                   const T *__restrict__ val,
                                                    const T *__restrict__ x, T *__restrict__ y,
                                                    const T *__restrict__ b) {
   int64_t blk = blockIdx.x;
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
-  T acc = sell_row(sptr, col, val, x, sl, (int)(pos & 63));
+  T acc = sell_row(cols, val, x, sl, (int)(pos & 63));
   if (pos >= nrows) return;
   if (MODE == SPMV_SET) y[pos] = acc;
   else if (MODE == SPMV_ADD) y[pos] += acc;
@@ -81,11 +103,11 @@ void sell_spmv(hipStream_t s, const Sell &S, const T *x, T *y, int mode, const T
   const T *v = sell_vals<T>(S);
   unsigned g = sell_grid(S);
   if (mode == SPMV_SET)
-    k_sell_spmv<T, SPMV_SET><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, x, y, b);
+    k_sell_spmv<T, SPMV_SET><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
   else if (mode == SPMV_ADD)
-    k_sell_spmv<T, SPMV_ADD><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, x, y, b);
+    k_sell_spmv<T, SPMV_ADD><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
   else
-    k_sell_spmv<T, SPMV_RESID><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, x, y, b);
+    k_sell_spmv<T, SPMV_RESID><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
   MG_LAUNCH_CHECK();
 }
 template void sell_spmv<double>(hipStream_t, const Sell &, const double *, double *, int, const double *);
@@ -95,8 +117,8 @@ template void sell_spmv<float>(hipStream_t, const Sell &, const float *, float *
 // Chebyshev-Jacobi step
 // ---------------------------------------------------------------------------
 template <class T, int FIRST>
-__global__ __launch_bounds__(256) void k_cheb(int64_t nslices, int64_t nrows, const int64_t *__restrict__ sptr,
-                                              const int32_t *__restrict__ col, const T *__restrict__ val,
+__global__ __launch_bounds__(256) void k_cheb(int64_t nslices, int64_t nrows, SellCols cols,
+                                              const T *__restrict__ val,
                                               const T *__restrict__ dinv, const T *__restrict__ b,
                                               const T *__restrict__ x, T *__restrict__ xout, T *__restrict__ d,
                                               T c_d, T c_r) {
@@ -104,7 +126,7 @@ __global__ __launch_bounds__(256) void k_cheb(int64_t nslices, int64_t nrows, co
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
-  T acc = sell_row(sptr, col, val, x, sl, (int)(pos & 63));
+  T acc = sell_row(cols, val, x, sl, (int)(pos & 63));
   if (pos >= nrows) return;
   T r = dinv[pos] * (b[pos] - acc);
   T dn = FIRST ? c_r * r : c_d * d[pos] + c_r * r;
@@ -118,9 +140,9 @@ void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T 
   const T *v = sell_vals<T>(S);
   unsigned g = sell_grid(S);
   if (first)
-    k_cheb<T, 1><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+    k_cheb<T, 1><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
   else
-    k_cheb<T, 0><<<g, 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+    k_cheb<T, 0><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
   MG_LAUNCH_CHECK();
 }
 template void cheb_step<double>(hipStream_t, const Sell &, const double *, const double *, const double *, double *,
@@ -134,15 +156,14 @@ template void cheb_step<float>(hipStream_t, const Sell &, const float *, const f
 // r = b - A u on the rows of one colour's patches: the patch rows of A are a
 // SELL matrix of their own (kernel order), streamed like the level operator.
 template <class T>
-__global__ __launch_bounds__(256) void k_patch_residual(int64_t k0, int64_t k1, const int64_t *__restrict__ sptr,
-                                                        const int32_t *__restrict__ col,
+__global__ __launch_bounds__(256) void k_patch_residual(int64_t k0, int64_t k1, SellCols cols,
                                                         const T *__restrict__ val,
                                                         const int32_t *__restrict__ dofs, const T *__restrict__ b,
                                                         const T *__restrict__ u, T *__restrict__ res) {
   int64_t k = (k0 & ~(int64_t)63) + (int64_t)blockIdx.x * 256 + threadIdx.x;
   int64_t sl = k >> 6;
   if (k >= ((k1 + 63) & ~(int64_t)63)) return;
-  T acc = sell_row(sptr, col, val, u, sl, (int)(k & 63));
+  T acc = sell_row(cols, val, u, sl, (int)(k & 63));
   if (k >= k0 && k < k1) res[k] = b[dofs[k]] - acc;
 }
 
@@ -152,7 +173,7 @@ void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, co
   int64_t k0 = pt.h_kptr[p0], k1 = pt.h_kptr[p1];
   if (k1 <= k0) return;
   int64_t span = ((k1 + 63) & ~(int64_t)63) - (k0 & ~(int64_t)63);
-  k_patch_residual<T><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(k0, k1, pt.rows.slice_ptr, pt.rows.col,
+  k_patch_residual<T><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(k0, k1, cols_of(pt.rows),
                                                                       sell_vals<T>(pt.rows), pt.dofs, b, u, res);
   MG_LAUNCH_CHECK();
 }
@@ -489,8 +510,8 @@ void cg_update_p(hipStream_t s, double *p, const double *z, const double *scal, 
 }
 
 // q = A p (FP64 SELL) with partial sums of p.q
-__global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, int64_t nrows, const int64_t *__restrict__ sptr,
-                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+__global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, int64_t nrows, SellCols cols,
+                                                  const double *__restrict__ val,
                                                   const double *__restrict__ p, double *__restrict__ q,
                                                   double *__restrict__ part) {
   int64_t blk = blockIdx.x;
@@ -498,7 +519,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, int64_t nrows
   int64_t sl = pos >> 6;
   double contrib = 0;
   if (sl < nslices) {
-    double acc = sell_row(sptr, col, val, p, sl, (int)(pos & 63));
+    double acc = sell_row(cols, val, p, sl, (int)(pos & 63));
     if (pos < nrows) {
       q[pos] = acc;
       contrib = acc * p[pos];
@@ -509,7 +530,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(int64_t nslices, int64_t nrows
 }
 int spmv_dot_blocks(const Sell &S) { return (int)sell_grid(S); }
 void spmv_dot(hipStream_t s, const Sell &S, const double *p, double *q, double *part) {
-  k_spmv_dot<<<sell_grid(S), 256, 0, s>>>(S.nslices, S.nrows, S.slice_ptr, S.col, S.v64, p, q, part);
+  k_spmv_dot<<<sell_grid(S), 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), S.v64, p, q, part);
   MG_LAUNCH_CHECK();
 }
 
