@@ -156,6 +156,10 @@ void mg_default_options(mg_options *opt);
  * eigenvalues and, on the coarsest level, a dense Cholesky factorisation.
  * levels[0] is the finest mesh.  On success *out owns all device memory it
  * allocated until mg_destroy.  On failure *out = NULL and nothing leaks.
+ * Limits: a local-correction patch of more than 16384 DOFs, a coarsest level
+ * of more than 60000 unknowns or a Galerkin row of more than 3072 nonzeros
+ * fail with MG_ERR_LIMIT.  With MG_SETUP_LOG=1 in the environment every
+ * finished setup phase is reported on stderr.
  * Errors: MG_ERR_ARG, MG_ERR_MESH, MG_ERR_LOCATE, MG_ERR_NOT_SPD, MG_ERR_HIP,
  * MG_ERR_OOM, MG_ERR_LIMIT. */
 mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_threshold,
