@@ -100,11 +100,16 @@ struct Sell {
   DBuf<int32_t> col;        // [stored]
   DBuf<double> v64;         // [stored] (FP64 copy)
   DBuf<float> v32;          // [stored] (FP32 copy, mixed precision)
-  // 16-bit columns: a slice whose columns fit two windows of 32768 stores
-  // column c as c - base0 (below 0x8000) or 0x8000 | (c - base1); cbase holds
-  // (base0, base1) per slice, base0 = -1 for slices kept at 32 bits
+  // 16-bit columns.  Per slice cbase = (base0, base1):
+  //   base0 >= 0: two windows of 32768, column c stored as c - base0 (below
+  //               0x8000) or 0x8000 | (c - base1);
+  //   base0 = -2: up to 8 windows of 8192 starting at ctab[16 s + w], stored as
+  //               (w << 13) | (c - ctab[16 s + w]);
+  //   base0 = -3: up to 16 windows of 4096, (w << 12) | (c - ctab[16 s + w]);
+  //   base0 = -1: 32-bit columns.
   DBuf<uint16_t> col16;     // [stored]
   DBuf<int32_t> cbase;      // [2 * nslices]
+  DBuf<int32_t> ctab;       // [16 * nslices]
   int64_t nnz = 0, nnz16 = 0;  // entries, entries in 16-bit slices
 };
 

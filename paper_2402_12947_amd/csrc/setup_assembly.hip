@@ -331,53 +331,86 @@ __device__ inline int wave_min_i(int v) {
   return v;
 }
 
-// One wavefront per slice: find two windows of 32768 columns covering every
-// column of the slice; if they exist, store the 16-bit form and the bases.
+// Greedy cover of the slice's columns by at most W windows of 2^bits columns,
+// each starting at the smallest column not yet covered (optimal for intervals).
+// Returns the number of windows, or 0 if W are not enough.
+template <int W>
+__device__ int cover_windows(const int32_t *cp, int w, int bits, int *bases) {
+  int cnt = 0;
+  long long end = -1;  // columns below end are covered
+  while (true) {
+    int m = 2147483647;
+    for (int j = 0; j < w; ++j) {
+      int c = cp[(int64_t)j * SELL_C];
+      if ((long long)c >= end) m = min(m, c);
+    }
+    m = wave_min_i(m);
+    if (m == 2147483647) return cnt;
+    if (cnt == W) return 0;
+    bases[cnt++] = m;
+    end = (long long)m + (1ll << bits);
+  }
+}
+
+// One wavefront per slice: choose the narrowest 16-bit form that covers every
+// column of the slice (two windows of 32768, else eight of 8192, else sixteen
+// of 4096) and write it, or keep the slice at 32 bits.
 __global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const int64_t *sptr, const int32_t *col,
                                                        const int64_t *rp, int64_t nrows, uint16_t *col16,
-                                                       int32_t *cbase, unsigned long long *nnz16) {
+                                                       int32_t *cbase, int32_t *ctab, unsigned long long *nnz16) {
   const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (sl >= nslices) return;
   const int lane = threadIdx.x & 63;
   const int64_t base = sptr[sl];
   const int w = (int)((sptr[sl + 1] - base) / SELL_C);
   const int32_t *cp = col + base + lane;
-  int mn = 2147483647;
-  for (int j = 0; j < w; ++j) mn = min(mn, cp[(int64_t)j * SELL_C]);
-  mn = wave_min_i(mn);
-  int mn1 = 2147483647;
-  for (int j = 0; j < w; ++j) {
-    int c = cp[(int64_t)j * SELL_C];
-    if (c - mn >= 32768) mn1 = min(mn1, c);
-  }
-  mn1 = wave_min_i(mn1);
-  int bad = 0;
-  for (int j = 0; j < w; ++j) {
-    int c = cp[(int64_t)j * SELL_C];
-    if (c - mn >= 32768 && c - mn1 >= 32768) bad = 1;
-  }
-  bad = -wave_min_i(-bad);
-  if (bad) {
-    if (lane == 0) {
-      cbase[2 * sl] = -1;
-      cbase[2 * sl + 1] = -1;
-    }
-    return;
-  }
-  const int b1 = mn1 == 2147483647 ? mn : mn1;
   uint16_t *op = col16 + base + lane;
-  for (int j = 0; j < w; ++j) {
-    int c = cp[(int64_t)j * SELL_C];
-    op[(int64_t)j * SELL_C] = c - mn < 32768 ? (uint16_t)(c - mn) : (uint16_t)(0x8000 | (c - b1));
+  int bases[16];
+  int mode;
+  int nb = cover_windows<2>(cp, w, 15, bases);
+  if (nb > 0) {
+    const int b0 = bases[0], b1 = nb > 1 ? bases[1] : bases[0];
+    for (int j = 0; j < w; ++j) {
+      int c = cp[(int64_t)j * SELL_C];
+      op[(int64_t)j * SELL_C] = c - b0 < 32768 ? (uint16_t)(c - b0) : (uint16_t)(0x8000 | (c - b1));
+    }
+    if (lane == 0) {
+      cbase[2 * sl] = b0;
+      cbase[2 * sl + 1] = b1;
+    }
+    mode = 2;
+  } else {
+    int bits = 13;
+    nb = cover_windows<8>(cp, w, 13, bases);
+    if (nb == 0) {
+      bits = 12;
+      nb = cover_windows<16>(cp, w, 12, bases);
+    }
+    if (nb == 0) {
+      if (lane == 0) {
+        cbase[2 * sl] = -1;
+        cbase[2 * sl + 1] = -1;
+      }
+      return;
+    }
+    for (int j = 0; j < w; ++j) {
+      int c = cp[(int64_t)j * SELL_C];
+      int k = 0;
+      while (k + 1 < nb && c >= bases[k + 1]) ++k;
+      op[(int64_t)j * SELL_C] = (uint16_t)((k << bits) | (c - bases[k]));
+    }
+    if (lane < 16) ctab[16 * sl + lane] = lane < nb ? bases[lane] : 0;
+    if (lane == 0) {
+      cbase[2 * sl] = bits == 13 ? -2 : -3;
+      cbase[2 * sl + 1] = 0;
+    }
+    mode = bits;
   }
+  (void)mode;
   const int64_t r = sl * SELL_C + lane;
   unsigned long long len = r < nrows ? (unsigned long long)(rp[r + 1] - rp[r]) : 0ull;
   for (int m = 32; m >= 1; m >>= 1) len += __shfl_xor(len, m);
-  if (lane == 0) {
-    cbase[2 * sl] = mn;
-    cbase[2 * sl + 1] = b1;
-    atomicAdd(nnz16, len);
-  }
+  if (lane == 0) atomicAdd(nnz16, len);
 }
 
 // SELL-C layout of A with its rows in their given order (row = position); the
@@ -409,12 +442,13 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
   S.nnz = A.nnz;
   S.col16.alloc(S.stored);
   S.cbase.alloc(2 * S.nslices);
+  S.ctab.alloc(16 * S.nslices);
   DBuf<unsigned long long> cnt;
   cnt.alloc(1);
   MG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
   if (S.nslices > 0) {
     k_compress_cols<<<(unsigned)((S.nslices + 3) / 4), 256, 0, s>>>(S.nslices, S.slice_ptr, S.col, A.rowptr,
-                                                                    A.nrows, S.col16, S.cbase, cnt);
+                                                                    A.nrows, S.col16, S.cbase, S.ctab, cnt);
     MG_LAUNCH_CHECK();
   }
   unsigned long long h16 = 0;

@@ -25,8 +25,11 @@ struct SellCols {
   const int32_t *col;
   const uint16_t *col16;
   const int32_t *cbase;
+  const int32_t *ctab;
 };
-static inline SellCols cols_of(const Sell &S) { return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p}; }
+static inline SellCols cols_of(const Sell &S) {
+  return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p, S.ctab.p};
+}
 
 // Row `lane` of slice `sl` (sl is the same for the whole wavefront): the matrix
 // entries are streamed once per product, so they are loaded non-temporally and
@@ -66,6 +69,14 @@ __device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const
   if (b0 >= 0) {
     const int bh = S.cbase[2 * s32 + 1] - 0x8000;
     return sell_dot(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
+  }
+  if (b0 < -1) {
+    // window bases in lanes 0..15, picked per entry by a cross-lane read
+    const int tb = S.ctab[16 * (int64_t)s32 + (lane & 15)];
+    const int shift = b0 == -2 ? 13 : 12;
+    const int mask = (1 << shift) - 1;
+    return sell_dot(S.col16 + base + lane, vp, x, w,
+                    [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); });
   }
   return sell_dot(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; });
 }

@@ -29,6 +29,9 @@ CASES = {
     # patch stress at 1/8 size: 54 separate flattened regions, patches of
     # 27-1587 DOFs (one to fifty 32x32 tiles per side in the batched factorisation)
     "cube_stress_p2": ("cube_129_stress", 8, 2, 0, "overlap"),
+    # 1/8 of the 1025^2 P3 square: most level-0 slices need the eight-window
+    # form of the 16-bit column indices
+    "square_p3_s8": ("square_1025", 8, 3, 1),
 }
 
 
