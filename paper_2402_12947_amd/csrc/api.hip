@@ -115,14 +115,18 @@ static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt) {
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   T *d = LV<T>::w(L, W_D);
+  // step flags: 1 = first step (no previous direction), 2 = last step (the
+  // direction is not stored)
+  const int k = c.opt.cheb_degree;
   time_begin(c, l);
-  cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, 1, 0.0, 1.0 / theta);
+  cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, k == 1 ? 3 : 1, 0.0, 1.0 / theta);
   time_end(c, l);
   std::swap(u, alt);
-  for (int j = 1; j < c.opt.cheb_degree; ++j) {
+  for (int j = 1; j < k; ++j) {
     double rho_new = 1.0 / (2.0 * sigma - rho);
     time_begin(c, l);
-    cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, 0, rho_new * rho, 2.0 * rho_new / delta);
+    cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, j == k - 1 ? 2 : 0, rho_new * rho,
+                 2.0 * rho_new / delta);
     time_end(c, l);
     std::swap(u, alt);
     rho = rho_new;
@@ -690,10 +694,16 @@ mg_status mg_cheb_algorithmic_bytes(const mg_ctx *h, double *bytes) {
   if (!h || !bytes) return MG_ERR_ARG;
   const Level &L = h->impl.lv[0];
   if (L.coarsest) return MG_ERR_ARG;
-  // values once, column indices once (2 bytes in 16-bit slices), x, b, D^-1, d
-  // read, d and x' written
+  // average over the k steps of one Chebyshev polynomial: values and column
+  // indices once (2-byte indices in 16-bit slices); x, b, D^-1 read and x'
+  // written by every step, the direction d written by all but the last step
+  // and read by all but the first
+  const int k = h->impl.opt.cheb_degree;
+  const double vecs = 4.0 + 2.0 * (k - 1) / k;
+  const bool mixed = h->impl.opt.precision == MG_MIXED;
+  const double vb = mixed ? 4.0 : 8.0;
   double n16 = (double)L.S.nnz16, n32 = (double)(L.S.nnz - L.S.nnz16), n = (double)L.nfree;
-  *bytes = h->impl.opt.precision == MG_MIXED ? 6.0 * n16 + 8.0 * n32 + 24.0 * n : 10.0 * n16 + 12.0 * n32 + 48.0 * n;
+  *bytes = (vb + 2.0) * n16 + (vb + 4.0) * n32 + vb * vecs * n;
   return MG_OK;
 }
 

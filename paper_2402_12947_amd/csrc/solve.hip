@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void k_cheb(int64_t nslices, int64_t nrows, Se
   T acc = sell_row(cols, val, x, sl, (int)(pos & 63));
   if (pos >= nrows) return;
   T r = dinv[pos] * (b[pos] - acc);
-  T dn = FIRST ? c_r * r : c_d * d[pos] + c_r * r;
-  d[pos] = dn;
+  T dn = (FIRST & 1) ? c_r * r : c_d * d[pos] + c_r * r;
+  if (!(FIRST & 2)) d[pos] = dn;  // the last step of a polynomial needs no direction
   xout[pos] = x[pos] + dn;
 }
 
@@ -150,10 +150,12 @@ void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T 
                double c_d, double c_r) {
   const T *v = sell_vals<T>(S);
   unsigned g = sell_grid(S);
-  if (first)
-    k_cheb<T, 1><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
-  else
-    k_cheb<T, 0><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+  switch (first) {
+    case 1: k_cheb<T, 1><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r); break;
+    case 2: k_cheb<T, 2><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r); break;
+    case 3: k_cheb<T, 3><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r); break;
+    default: k_cheb<T, 0><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, (T)c_d, (T)c_r);
+  }
   MG_LAUNCH_CHECK();
 }
 template void cheb_step<double>(hipStream_t, const Sell &, const double *, const double *, const double *, double *,

@@ -175,3 +175,19 @@ def test_error_paths_on_gpu():
     z = to_dev(np.zeros(n))
     st = gpu.pcg(to_dev(np.zeros(n)), z, 1e-8, 10)
     assert st["converged"] and st["iterations"] == 0 and float(z.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_chebyshev_degree(k):
+    """Chebyshev polynomials of degree 1 and 3 (first, middle and last steps)."""
+    meshes = meshgen.hierarchy("square_p1_4k", seed=0)
+    gpu, ora = build_pair(meshes, 1, layers=2, k=k)
+    n = ora.levels[0].A.shape[0]
+    b, u0 = meshgen.random_rhs(n, 7), meshgen.random_rhs(n, 8)
+    u = to_dev(u0)
+    gpu.smooth(0, to_dev(b), u, 1)
+    assert rel_err(from_dev(u), ora.smooth(0, b, u0.copy(), 1)) < 1e-10
+    u = to_dev(u0)
+    gpu.vcycle(to_dev(b), u)
+    assert rel_err(from_dev(u), ora.vcycle(b, u0.copy())) < 1e-10
+    gpu.close()
