@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include "devutil.h"
+#include "mfma_tile.h"
 
 namespace mg {
 
@@ -241,33 +242,6 @@ __global__ __launch_bounds__(64) void k_chol_panel(double *A, int64_t n, int kb)
   for (int t = threadIdx.x; t < mr * m; t += blockDim.x) A[(ro + t / m) * n + o + t % m] = R[t / m][t % m];
 }
 
-// 16x16 threads, each owning a 4x4 block of the 64x64 output tile:
-// acc[a][b] += sum_k As[ty*4+a][k] * Bs[k][tx*4+b]
-__device__ inline void tile_mac(double acc[4][4], double (*As)[TB + 1], double (*Bs)[TB + 1]) {
-  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-#pragma unroll 4
-  for (int k = 0; k < TB; ++k) {
-    double a[4], b[4];
-    for (int q = 0; q < 4; ++q) {
-      a[q] = As[ty * 4 + q][k];
-      b[q] = Bs[k][tx * 4 + q];
-    }
-    for (int p = 0; p < 4; ++p)
-      for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
-  }
-}
-
-// load tile (row block rb, col block cb) of M (n x n) into S, transposed or not,
-// zero outside the matrix
-__device__ inline void load_tile(const double *M, int64_t n, int rb, int cb, bool trans, double (*S)[TB + 1]) {
-  for (int t = threadIdx.x; t < TB * TB; t += blockDim.x) {
-    int i = t / TB, j = t % TB;
-    int64_t r = (int64_t)rb * TB + i, cc = (int64_t)cb * TB + j;
-    double v = (r < n && cc < n) ? M[r * n + cc] : 0.0;
-    if (trans) S[j][i] = v; else S[i][j] = v;
-  }
-}
-
 __device__ inline void tri_index(int64_t t, int &i, int &j) {
   // t -> (i, j) with 0 <= j <= i, t = i (i + 1) / 2 + j
   int64_t ii = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -277,24 +251,28 @@ __device__ inline void tri_index(int64_t t, int &i, int &j) {
   j = (int)(t - ii * (ii + 1) / 2);
 }
 
+// The 64 x 64 tile products below run on the FP64 matrix cores: one workgroup
+// per output tile, wavefront w owns the 32 x 32 quadrant (w >> 1, w & 1) and
+// reads its operands straight into registers (mfma_tile.h).
+
 // trailing update: A[ib, jb] -= L[ib, kb] L[jb, kb]^T for kb < jb <= ib
 __global__ __launch_bounds__(256) void k_chol_update(double *A, int64_t n, int kb) {
-  __shared__ double As[TB][TB + 1];
-  __shared__ double Bs[TB][TB + 1];
   int i, j;
   tri_index(blockIdx.x, i, j);
-  int ib = kb + 1 + i, jb = kb + 1 + j;
-  load_tile(A, n, ib, kb, false, As);
-  load_tile(A, n, jb, kb, true, Bs);
-  __syncthreads();
-  double acc[4][4] = {};
-  tile_mac(acc, As, Bs);
-  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) {
-      int64_t r = (int64_t)ib * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
-      if (r < n && cc < n) A[r * n + cc] -= acc[p][q];
-    }
+  const int ib = kb + 1 + i, jb = kb + 1 + j;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, qr = wave >> 1, qc = wave & 1;
+  v4d acc[2][2];
+  zero_acc(acc);
+  for (int kc = 0; kc < 2; ++kc) {
+    double a[16], b[16];
+    fetch_ops<true>(A, (int)n, ib * TB + 32 * qr, kb * TB + 32 * kc, false, a, lane);
+    fetch_ops<false>(A, (int)n, jb * TB + 32 * qc, kb * TB + 32 * kc, true, b, lane);
+    mma_ops(acc, a, b);
+  }
+  for_acc(acc, lane, [&](int r, int c, double v) {
+    int64_t gr = (int64_t)ib * TB + 32 * qr + r, gc = (int64_t)jb * TB + 32 * qc + c;
+    if (gr < n && gc < n) A[gr * n + gc] -= v;
+  });
 }
 
 // W[jb, jb] = L[jb, jb]^-1 (one workgroup of 64 threads per diagonal tile)
@@ -323,37 +301,39 @@ __global__ __launch_bounds__(64) void k_trtri_diag(const double *Lm, double *W, 
 // Y[ib, jb] -= L[ib, kb] Y[kb, jb] for ib > kb, jb <= kb.  Every tile of a step
 // is independent, so each step is one wide launch.
 __global__ __launch_bounds__(256) void k_trsm_rows(const double *Dinv, double *Y, int64_t n, int kb) {
-  __shared__ double As[TB][TB + 1];
-  __shared__ double Bs[TB][TB + 1];
-  int jb = blockIdx.x;  // 0..kb
-  load_tile(Dinv, n, kb, kb, false, As);
-  load_tile(Y, n, kb, jb, false, Bs);
-  __syncthreads();
-  double acc[4][4] = {};
-  tile_mac(acc, As, Bs);
-  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) {
-      int64_t r = (int64_t)kb * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
-      if (r < n && cc < n) Y[r * n + cc] = acc[p][q];
-    }
+  const int jb = blockIdx.x;  // 0..kb
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, qr = wave >> 1, qc = wave & 1;
+  double a[2][16], b[2][16];
+  for (int kc = 0; kc < 2; ++kc) {
+    fetch_ops<true>(Dinv, (int)n, kb * TB + 32 * qr, kb * TB + 32 * kc, false, a[kc], lane);
+    fetch_ops<false>(Y, (int)n, kb * TB + 32 * kc, jb * TB + 32 * qc, false, b[kc], lane);
+  }
+  __syncthreads();  // the tile is overwritten in place: all reads first
+  v4d acc[2][2];
+  zero_acc(acc);
+  mma_ops(acc, a[0], b[0]);
+  mma_ops(acc, a[1], b[1]);
+  for_acc(acc, lane, [&](int r, int c, double v) {
+    int64_t gr = (int64_t)kb * TB + 32 * qr + r, gc = (int64_t)jb * TB + 32 * qc + c;
+    if (gr < n && gc < n) Y[gr * n + gc] = v;
+  });
 }
 
 __global__ __launch_bounds__(256) void k_trsm_update(const double *Lm, double *Y, int64_t n, int kb) {
-  __shared__ double As[TB][TB + 1];
-  __shared__ double Bs[TB][TB + 1];
-  int ib = kb + 1 + blockIdx.x / (kb + 1), jb = blockIdx.x % (kb + 1);
-  load_tile(Lm, n, ib, kb, false, As);
-  load_tile(Y, n, kb, jb, false, Bs);
-  __syncthreads();
-  double acc[4][4] = {};
-  tile_mac(acc, As, Bs);
-  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) {
-      int64_t r = (int64_t)ib * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
-      if (r < n && cc < n) Y[r * n + cc] -= acc[p][q];
-    }
+  const int ib = kb + 1 + blockIdx.x / (kb + 1), jb = blockIdx.x % (kb + 1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, qr = wave >> 1, qc = wave & 1;
+  v4d acc[2][2];
+  zero_acc(acc);
+  for (int kc = 0; kc < 2; ++kc) {
+    double a[16], b[16];
+    fetch_ops<true>(Lm, (int)n, ib * TB + 32 * qr, kb * TB + 32 * kc, false, a, lane);
+    fetch_ops<false>(Y, (int)n, kb * TB + 32 * kc, jb * TB + 32 * qc, false, b, lane);
+    mma_ops(acc, a, b);
+  }
+  for_acc(acc, lane, [&](int r, int c, double v) {
+    int64_t gr = (int64_t)ib * TB + 32 * qr + r, gc = (int64_t)jb * TB + 32 * qc + c;
+    if (gr < n && gc < n) Y[gr * n + gc] -= v;
+  });
 }
 
 __global__ void k_identity(double *Y, int64_t n) {
@@ -363,27 +343,26 @@ __global__ void k_identity(double *Y, int64_t n) {
 
 // X[ib, jb] = sum_{k>=ib} W[k, ib]^T W[k, jb] for jb <= ib; mirrored to X[jb, ib]
 __global__ __launch_bounds__(256) void k_lauum(const double *W, double *X, int64_t n, int nb) {
-  __shared__ double As[TB][TB + 1];
-  __shared__ double Bs[TB][TB + 1];
   int ib, jb;
   tri_index(blockIdx.x, ib, jb);
-  double acc[4][4] = {};
-  for (int k = ib; k < nb; ++k) {
-    __syncthreads();
-    load_tile(W, n, k, ib, true, As);
-    load_tile(W, n, k, jb, false, Bs);
-    __syncthreads();
-    tile_mac(acc, As, Bs);
-  }
-  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  for (int p = 0; p < 4; ++p)
-    for (int q = 0; q < 4; ++q) {
-      int64_t r = (int64_t)ib * TB + ty * 4 + p, cc = (int64_t)jb * TB + tx * 4 + q;
-      if (r < n && cc < n) {
-        X[r * n + cc] = acc[p][q];
-        X[cc * n + r] = acc[p][q];
-      }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, qr = wave >> 1, qc = wave & 1;
+  v4d acc[2][2];
+  zero_acc(acc);
+  for (int k = ib; k < nb; ++k)
+    for (int kc = 0; kc < 2; ++kc) {
+      double a[16], b[16];
+      fetch_ops<true>(W, (int)n, k * TB + 32 * kc, ib * TB + 32 * qr, true, a, lane);
+      fetch_ops<false>(W, (int)n, k * TB + 32 * kc, jb * TB + 32 * qc, false, b, lane);
+      mma_ops(acc, a, b);
     }
+  for_acc(acc, lane, [&](int r, int c, double v) {
+    const int lr = 32 * qr + r, lc = 32 * qc + c;
+    int64_t gr = (int64_t)ib * TB + lr, gc = (int64_t)jb * TB + lc;
+    if (gr < n && gc < n && (ib != jb || lr >= lc)) {  // diagonal tiles: lower half, mirrored
+      X[gr * n + gc] = v;
+      X[gc * n + gr] = v;
+    }
+  });
 }
 
 __global__ __launch_bounds__(256) void k_single_inverse(const int64_t *rp, const int32_t *col, const double *val,

@@ -19,12 +19,12 @@
 #include <cmath>
 
 #include "devutil.h"
+#include "mfma_tile.h"
 
 namespace mg {
 
 namespace {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int PT = 32;       // tile edge
 constexpr int PLD = PT + 1;  // LDS row stride (bank spread)
 
@@ -40,51 +40,6 @@ __device__ inline void tri_rc(int t, int &i, int &j) {
   while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
   i = ii;
   j = t - ii * (ii + 1) / 2;
-}
-
-// MFMA operand registers of one 32 x 32 tile, read straight from the n x n
-// row-major matrix M: element (x, y) of the operand is M[r0 + x][c0 + y], or
-// M[r0 + y][c0 + x] when swap is set (zero outside the matrix).  For the A
-// operand lane l holds (x, y) = (16 blk + l % 16, 4 s + l / 16), for the B
-// operand (4 s + l / 16, 16 blk + l % 16); o[blk * 8 + s].
-template <bool ROLE_A>
-__device__ inline void fetch_ops(const double *M, int n, int r0, int c0, bool swap, double o[16], int lane) {
-  const int p = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int blk = 0; blk < 2; ++blk)
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int x = ROLE_A ? 16 * blk + p : 4 * s + q;
-      const int y = ROLE_A ? 4 * s + q : 16 * blk + p;
-      const int r = swap ? r0 + y : r0 + x, c = swap ? c0 + x : c0 + y;
-      o[blk * 8 + s] = (r < n && c < n) ? M[(int64_t)r * n + c] : 0.0;
-    }
-}
-
-// acc (a 32 x 32 tile as 2 x 2 MFMA blocks) += A B
-__device__ inline void mma_ops(v4d acc[2][2], const double a[16], const double b[16]) {
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[8 + s], acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 + s], b[s], acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 + s], b[8 + s], acc[1][1], 0, 0, 0);
-  }
-}
-
-__device__ inline void zero_acc(v4d acc[2][2]) {
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-}
-
-// element (i, j) of the tile held by this lane: in each 16 x 16 block the lane
-// owns column (lane & 15) and rows (lane >> 4) + 4 e, e = 0..3 (the f64 MFMA
-// result layout, checked on the device)
-template <class F>
-__device__ inline void for_acc(v4d acc[2][2], int lane, F f) {
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int e = 0; e < 4; ++e) f(16 * a + (lane >> 4) + 4 * e, 16 * b + (lane & 15), acc[a][b][e]);
 }
 
 }  // namespace
