@@ -148,6 +148,48 @@ def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", budget_s=1
                       f"iterations {its[0]}"}
 
 
+def run_study(scale=4):
+    """The paper's Poisson study (Sec. 6.1) on the GPU: multigrid as a stationary
+    solver and as a CG preconditioner, plain Chebyshev vs global-local
+    smoother, on the reference mesh (no degraded cells), degraded cells on the
+    finest level, on every level (Case A) and on the coarse levels only
+    (Case B).  One JSON line per (workload, case, smoother)."""
+    import torch
+
+    import meshgen
+    from paper_2402_12947_amd import MgError, Solver
+    for recipe, degree in (("square_1025", 2), ("cube_129", 2)):
+        for case in ("ref", "fine", "A", "B"):
+            meshes = meshgen.hierarchy(recipe, seed=0, scale=scale, case=case)
+            ref_x = None
+            for smoother in ("global_local", "plain"):
+                local = smoother == "global_local"
+                rec = {"study": f"{recipe}/{scale} P{degree}", "case": case, "smoother": smoother}
+                try:
+                    s = Solver(meshes, degree=degree, tau=0.1, layers=1, local_correction=local, adjusted_eig=local)
+                except MgError as e:
+                    rec["error"] = str(e)
+                    print(json.dumps(rec), flush=True)
+                    continue
+                n = s.n_free(0)
+                b = torch.as_tensor(_rhs(n, 77)).cuda()
+                if ref_x is None:  # the solution, from the global-local PCG to rtol 1e-13
+                    ref_x = torch.zeros(n, dtype=torch.float64, device="cuda")
+                    s.pcg(b, ref_x, 1e-13, 500)
+                u = torch.zeros(n, dtype=torch.float64, device="cuda")
+                st12 = s.mg_solve(b, u, 1e-300, 12)
+                err12 = float(torch.linalg.norm(u - ref_x) / torch.linalg.norm(ref_x))
+                st = s.mg_solve(b, torch.zeros_like(u), 1e-8, 300)
+                pc = s.pcg(b, torch.zeros_like(u), 1e-8, 500)
+                rec.update({"dofs": n, "flagged_level0": s.level_info(0)["n_flagged"],
+                            "mg_cycles_to_1e-8": st["iterations"] if st["converged"] else None,
+                            "mg_rel_error_after_12_cycles": err12,
+                            "mg_residual_after_12_cycles": st12["rel_residual"],
+                            "pcg_iterations_to_1e-8": pc["iterations"] if pc["converged"] else None})
+                print(json.dumps(rec), flush=True)
+                s.close()
+
+
 def run_batch(name, steps, warmup):
     """Many-instance solve: every instance's hierarchy in mixed precision with
     graph-captured V-cycles, all instances solved together by
@@ -231,6 +273,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the V-cycle from a hipGraph")
     ap.add_argument("--sigma", type=int, default=0, help="SELL sorting window (0 = library's choice)")
+    ap.add_argument("--study", action="store_true",
+                    help="instead of the benchmark line: the stationary-solver / preconditioner study of "
+                         "plain vs global-local smoothing on the reference mesh and Cases A and B")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -241,6 +286,9 @@ def main():
     import torch
     import meshgen
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.study:
+        run_study()
+        return
     if args.workload in BATCH_WORKLOADS:
         print(json.dumps(run_batch(args.workload, args.steps, args.warmup)), flush=True)
         return

@@ -182,6 +182,16 @@ mg_status mg_vcycle(mg_ctx *c, const double *b, double *u);
 mg_status mg_pcg_solve(mg_ctx *c, const double *b, double *u, double rtol, int32_t maxit,
                        mg_solve_stats *st);
 
+/* Multigrid as a stationary solver (Sec. 2, Algorithm alg:mg repeated; the
+ * Poisson experiments of Sec. 6.1): from u = 0, u <- Vcycle(A_0, b, u) until
+ * ||b - A u||_2 <= rtol ||b||_2 (the residual recomputed after every cycle) or
+ * maxit cycles.  st (may be NULL): iterations = cycles, history = relative
+ * residual after each cycle.  Returns MG_NOT_CONVERGED if maxit cycles were
+ * not enough (u holds the last iterate), MG_ERR_BREAKDOWN on a non-finite
+ * residual. */
+mg_status mg_vcycle_solve(mg_ctx *c, const double *b, double *u, double rtol, int32_t maxit,
+                          mg_solve_stats *st);
+
 /* Many-instance solve (the serving pattern of independent problems): solves
  * the n_inst x nrhs systems A_i u_(i,r) = b_(i,r) of the contexts cs[i] together
  * with the same method and stopping rule as mg_pcg_solve.  b[i * nrhs + r] and

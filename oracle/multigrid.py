@@ -159,5 +159,24 @@ class Hierarchy:
             rho = rho_new
         return x, it, False, hist
 
+    def mg_solve(self, b: np.ndarray, rtol: float, maxit: int, x0: np.ndarray | None = None):
+        """Multigrid as a stationary solver (Sec. 2, Algorithm alg:mg applied
+        repeatedly; the paper's Poisson experiments of Sec. 6.1): one V-cycle
+        per iteration from the current iterate, stopping when
+        ||b - A x|| <= rtol ||b|| or after maxit cycles.
+        Returns (x, cycles, converged, history of ||r||/||b||)."""
+        A = self.levels[0].A
+        x = np.zeros_like(b) if x0 is None else x0.copy()
+        bnorm = float(np.linalg.norm(b))
+        if bnorm == 0.0:
+            return np.zeros_like(b), 0, True, [0.0]
+        hist = [float(np.linalg.norm(b - A @ x)) / bnorm]
+        it = 0
+        while hist[-1] > rtol and it < maxit:
+            x = self.vcycle(b, x)
+            it += 1
+            hist.append(float(np.linalg.norm(b - A @ x)) / bnorm)
+        return x, it, hist[-1] <= rtol, hist
+
     def rhs_from_nodal(self, f_nodal: np.ndarray) -> np.ndarray:
         return self.levels[0].Mf @ f_nodal

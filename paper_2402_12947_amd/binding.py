@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mg_smooth": (C.c_int, [P, C.c_int32, P, P, C.c_int32]),
         "mg_vcycle": (C.c_int, [P, P, P]),
         "mg_pcg_solve": (C.c_int, [P, P, P, C.c_double, C.c_int32, C.POINTER(MgSolveStats)]),
+        "mg_vcycle_solve": (C.c_int, [P, P, P, C.c_double, C.c_int32, C.POINTER(MgSolveStats)]),
         "mg_rhs_from_nodal": (C.c_int, [P, P, P]),
         "mg_pcg_solve_batch": (C.c_int, [C.POINTER(P), C.c_int32, C.c_int32, C.POINTER(P), C.POINTER(P),
                                          C.c_double, C.c_int32, C.POINTER(MgSolveStats), C.POINTER(C.c_double)]),
@@ -248,6 +249,17 @@ class Solver:
         return {"status": code, "iterations": st.iterations, "converged": bool(st.converged),
                 "rel_residual": st.rel_residual, "true_rel_residual": st.true_rel_residual,
                 "solve_ms": st.solve_ms, "history": list(st.history[:st.n_history])}
+
+    def mg_solve(self, b, u, rtol: float = 1e-8, maxit: int = 100) -> dict:
+        """Multigrid as a stationary solver: V-cycles from u = 0 until the
+        relative residual is at most rtol (mg_vcycle_solve)."""
+        _sync()
+        st = MgSolveStats()
+        code = self._check(lib().mg_vcycle_solve(self._h, _ptr(b), _ptr(u), rtol, maxit, C.byref(st)),
+                           allow=(MG_OK, MG_NOT_CONVERGED))
+        return {"status": code, "iterations": st.iterations, "converged": bool(st.converged),
+                "rel_residual": st.rel_residual, "solve_ms": st.solve_ms,
+                "history": list(st.history[:st.n_history])}
 
     def rhs_from_nodal(self, f, b):
         _sync()

@@ -541,6 +541,72 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
   MG_API_END(cp)
 }
 
+mg_status mg_vcycle_solve(mg_ctx *h, const double *b, double *u, double rtol, int32_t maxit, mg_solve_stats *st) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || !b || !u) fail(MG_ERR_ARG, "NULL argument");
+  Ctx &c = h->impl;
+  if (b == u) fail(MG_ERR_ARG, "b must not alias u");
+  if (maxit < 0 || !(rtol >= 0)) fail(MG_ERR_ARG, "bad rtol or maxit");
+  Level &L0 = c.lv[0];
+  const int64_t n = L0.nfree;
+  hipStream_t s = c.stream;
+  if (st) std::memset(st, 0, sizeof(*st));
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } guard{e0, e1};
+  MG_HIP(hipEventRecord(e0, s));
+  double *scal = c.scal.p;
+  double *x = c.xpos.p;
+  fill<double>(s, x, n, 0.0);
+  gather_perm<double, double>(s, b, L0.perm, c.bpos, n);
+  copy64(s, c.bpos, c.r, n);
+  dot_to(c, c.bpos, c.bpos, n, scal + 7);
+  const double bnorm = std::sqrt(read_scalar(c, scal + 7));
+  std::vector<double> hist{bnorm > 0 ? 1.0 : 0.0};
+  int it = 0;
+  double rel = bnorm > 0 ? 1.0 : 0.0;
+  bool converged = rel <= rtol, bad = false;
+  // x <- x + B (b - A x): one V-cycle per iteration (the cycle is affine in
+  // its initial guess), then the residual of the new iterate
+  while (!converged && it < maxit) {
+    precondition(c);
+    add64(s, x, c.z, n);
+    sell_spmv<double>(s, L0.S, x, c.r, SPMV_RESID, c.bpos);
+    dot_to(c, c.r, c.r, n, scal + 7);
+    const double rr = read_scalar(c, scal + 7);
+    ++it;
+    if (!std::isfinite(rr)) {
+      bad = true;
+      break;
+    }
+    rel = std::sqrt(rr) / bnorm;
+    hist.push_back(rel);
+    converged = rel <= rtol;
+  }
+  scatter_perm<double, double>(s, x, L0.perm, u, n);
+  MG_HIP(hipEventRecord(e1, s));
+  MG_HIP(hipEventSynchronize(e1));
+  float tms = 0;
+  MG_HIP(hipEventElapsedTime(&tms, e0, e1));
+  if (st) {
+    st->iterations = it;
+    st->converged = converged ? 1 : 0;
+    st->rel_residual = rel;
+    st->true_rel_residual = rel;  // the recomputed residual is the true one
+    st->solve_ms = tms;
+    st->n_history = (int32_t)std::min<size_t>(hist.size(), MG_MAX_HISTORY);
+    for (int k = 0; k < st->n_history; ++k) st->history[k] = hist[k];
+  }
+  if (bad) fail(MG_ERR_BREAKDOWN, "non-finite residual after cycle %d", it);
+  return converged ? MG_OK : MG_NOT_CONVERGED;
+  MG_API_END(cp)
+}
+
 mg_status mg_pcg_solve_batch(mg_ctx *const *cs, int32_t n_inst, int32_t nrhs, const double *const *b,
                              double *const *u, double rtol, int32_t maxit, mg_solve_stats *st, double *wall_ms) {
   if (!cs || !b || !u || n_inst < 0 || nrhs < 0) {

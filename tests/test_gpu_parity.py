@@ -191,3 +191,21 @@ def test_chebyshev_degree(k):
     gpu.vcycle(to_dev(b), u)
     assert rel_err(from_dev(u), ora.vcycle(b, u0.copy())) < 1e-10
     gpu.close()
+
+
+@pytest.mark.parametrize("name", ["square_p1_4k", "square_p2", "cube_p2"])
+def test_stationary_multigrid(name):
+    """mg_vcycle_solve: twelve V-cycles from zero equal the oracle's iterate, and
+    the number of cycles to rtol 1e-8 matches within one."""
+    meshes, gpu, ora = pair(name)
+    n = ora.levels[0].A.shape[0]
+    b = meshgen.random_rhs(n, 9)
+    x_o, it_o, _, hist_o = ora.mg_solve(b, 1e-300, 12)
+    u = to_dev(np.zeros(n))
+    st = gpu.mg_solve(to_dev(b), u, 1e-300, 12)
+    assert st["iterations"] == 12 and not st["converged"]
+    assert rel_err(from_dev(u), x_o) < 1e-9
+    assert np.allclose(st["history"], hist_o, rtol=1e-6, atol=1e-12)
+    _, it_o, conv_o, _ = ora.mg_solve(b, 1e-8, 200)
+    st = gpu.mg_solve(to_dev(b), to_dev(np.zeros(n)), 1e-8, 200)
+    assert conv_o and st["converged"] and abs(st["iterations"] - it_o) <= 1

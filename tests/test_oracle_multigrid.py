@@ -62,6 +62,31 @@ def test_vcycle_with_nonzero_initial_guess_is_affine():
     assert np.allclose(H.vcycle(b, u), u + B @ (b - A @ u), atol=1e-10)
 
 
+def test_stationary_solver_is_the_iteration_of_the_dense_operator():
+    """x_(k+1) = x_k + B (b - A x_k) with the brute-force B: after k cycles the
+    error is (I - B A)^k e_0, and the residual history is that of the dense
+    iteration."""
+    H = _tiny_hierarchy(sides=(8, 4))
+    A = H.levels[0].A
+    n = A.shape[0]
+    b = np.random.default_rng(3).normal(size=n)
+    B = _dense_B(H, 0)
+    x, it, conv, hist = H.mg_solve(b, 1e-300, 6)
+    assert it == 6 and not conv and len(hist) == 7
+    xs = np.zeros(n)
+    for k in range(6):
+        xs = xs + B @ (b - A @ xs)
+        assert abs(hist[k + 1] - np.linalg.norm(b - A @ xs) / np.linalg.norm(b)) < 1e-9
+    assert np.allclose(x, xs, atol=1e-9 * np.abs(xs).max())
+    u = np.linalg.solve(A.toarray(), b)
+    E = np.eye(n) - B @ A.toarray()
+    assert np.allclose(u - x, np.linalg.matrix_power(E, 6) @ u, atol=1e-9 * np.abs(u).max())
+    # convergence to the direct solution; zero right-hand side
+    x, it, conv, _ = H.mg_solve(b, 1e-10, 100)
+    assert conv and np.linalg.norm(x - u) <= 1e-8 * np.linalg.norm(u)
+    assert H.mg_solve(np.zeros(n), 1e-8, 10)[1] == 0
+
+
 def test_galerkin_coarse_operator_in_hierarchy():
     H = _tiny_hierarchy(sides=(8, 4))
     l0, l1 = H.levels
