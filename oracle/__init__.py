@@ -26,7 +26,8 @@ from .fem import DofMap, assemble, assemble_full, element_matrices, local_basis,
 from .multigrid import Hierarchy, Options
 from .patches import MERGE, OVERLAP, colour, patches
 from .quality import radius_ratio
-from .smoothers import LocalCorrection, chebyshev, lanczos_lmax, sandwich, splitmix64, start_vector
+from .smoothers import (LocalCorrection, SymmetricGaussSeidel, chebyshev, lanczos_lmax, matrix_colouring, sandwich,
+                        splitmix64, start_vector)
 from .transfer import LocateError, barycentric, galerkin, locate, prolongation
 
 __all__ = [
@@ -34,5 +35,5 @@ __all__ = [
     "reference_tensors", "Hierarchy", "Options", "MERGE", "OVERLAP", "colour",
     "patches", "radius_ratio", "LocalCorrection", "chebyshev", "lanczos_lmax",
     "sandwich", "splitmix64", "start_vector", "LocateError", "barycentric",
-    "galerkin", "locate", "prolongation",
+    "galerkin", "locate", "prolongation", "SymmetricGaussSeidel", "matrix_colouring",
 ]

@@ -31,7 +31,7 @@ import scipy.sparse as sp
 from .fem import DofMap, assemble
 from .patches import MERGE, colour, patches
 from .quality import radius_ratio
-from .smoothers import LocalCorrection, lanczos_lmax, sandwich
+from .smoothers import LocalCorrection, SymmetricGaussSeidel, lanczos_lmax, matrix_colouring, sandwich
 from .transfer import galerkin, prolongation
 
 
@@ -46,6 +46,7 @@ class Options:
     patch_policy: int = MERGE
     eig_tol: float = 1e-8
     eig_maxit: int = 200
+    global_smoother: str = "chebyshev"   # or "sgs" (multicolour symmetric Gauss-Seidel)
 
 
 @dataclass
@@ -62,6 +63,7 @@ class Level:
     lo: float = 0.0
     hi: float = 0.0
     local: LocalCorrection | None = None
+    sgs: SymmetricGaussSeidel | None = None   # global smoother when opts.global_smoother == "sgs"
     P: sp.csr_matrix | None = None            # to the next coarser level
     locate_cell: np.ndarray | None = None     # coarse cell of each free DOF node
     chol: tuple | None = None                 # coarsest only
@@ -107,13 +109,15 @@ class Hierarchy:
                 lev.lam_adj = lev.lam
             lev.hi = lev.lam_adj if (use_local and opts.adjusted_eig) else lev.lam
             lev.lo = opts.cheb_lo_frac * lev.hi
+            if opts.global_smoother == "sgs":
+                lev.sgs = SymmetricGaussSeidel(lev.A, matrix_colouring(lev.A))
 
     # -- the method --------------------------------------------------------
     def smooth(self, l: int, b: np.ndarray, u: np.ndarray, nu: int) -> np.ndarray:
         lev = self.levels[l]
         for _ in range(nu):
             u = sandwich(lev.A, lev.dinv, b, u, lev.local, self.opts.cheb_degree,
-                         lev.lo, lev.hi)
+                         lev.lo, lev.hi, lev.sgs)
         return u
 
     def vcycle(self, b: np.ndarray, u: np.ndarray | None = None, l: int = 0) -> np.ndarray:

@@ -31,6 +31,17 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
   the combined smoother symmetric.  With one colour (disjoint subdomains, as in
   the paper) this is exactly the paper's S_c.
 * Combined smoother (Sec. 4.2): u <- S_c, then S_g, then S_c.
+* Symmetric Gauss-Seidel as S_g (the global smoother of most of the paper's
+  Poisson experiments, Sec. 3.2 and Sec. 6.1; one forward and one backward
+  sweep per application).  Here the multicolour form: the rows are coloured
+  greedily in row order (each row takes the smallest colour not used by a
+  lower-numbered neighbour in the matrix graph); a forward sweep updates the
+  colours in ascending order, all rows of a colour at once from the current
+  iterate, u_i += (b_i - (A u)_i) / a_ii, the backward sweep in descending
+  order.  Rows of one colour are not coupled, so a forward sweep is exactly
+  sequential Gauss-Seidel in colour-major row order (lexicographic SGS in the
+  original numbering visits the rows in another order, so iteration counts
+  differ from the paper's).
 """
 from __future__ import annotations
 
@@ -143,11 +154,51 @@ class LocalCorrection:
         return u
 
 
-def sandwich(A, dinv, b, u, local: LocalCorrection | None, k, lo, hi):
-    """One application of the combined smoother S_c -> S_g -> S_c."""
+def matrix_colouring(A: sp.csr_matrix) -> np.ndarray:
+    """Greedy colouring of the matrix graph in row order: row i takes the
+    smallest colour not used by any neighbour j < i (a_ij != 0)."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    col = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        nbr = A.indices[A.indptr[i]:A.indptr[i + 1]]
+        used = set(col[nbr[nbr < i]].tolist())
+        c = 0
+        while c in used:
+            c += 1
+        col[i] = c
+    return col
+
+
+class SymmetricGaussSeidel:
+    """Multicolour symmetric Gauss-Seidel sweep (one forward, one backward)."""
+
+    def __init__(self, A: sp.csr_matrix, colours: np.ndarray):
+        A = sp.csr_matrix(A)
+        self.colours = colours
+        self.rows = [np.flatnonzero(colours == c) for c in range(int(colours.max()) + 1)]
+        self.blocks = [A[r] for r in self.rows]
+        self.dinv = 1.0 / A.diagonal()
+
+    def _colour(self, c, b, u):
+        r = self.rows[c]
+        u[r] += self.dinv[r] * (b[r] - self.blocks[c] @ u)
+
+    def apply(self, b, u):
+        u = u.copy()
+        for c in range(len(self.rows)):
+            self._colour(c, b, u)
+        for c in reversed(range(len(self.rows))):
+            self._colour(c, b, u)
+        return u
+
+
+def sandwich(A, dinv, b, u, local: LocalCorrection | None, k, lo, hi, sgs: SymmetricGaussSeidel | None = None):
+    """One application of the combined smoother S_c -> S_g -> S_c; S_g is the
+    Chebyshev-Jacobi polynomial, or the symmetric Gauss-Seidel sweep if given."""
     if local is not None and local.n_colours:
         u = local.apply(A, b, u, descending=False)
-    u = chebyshev(A, dinv, b, u, k, lo, hi)
+    u = sgs.apply(b, u) if sgs is not None else chebyshev(A, dinv, b, u, k, lo, hi)
     if local is not None and local.n_colours:
         u = local.apply(A, b, u, descending=True)
     return u

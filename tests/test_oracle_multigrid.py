@@ -148,3 +148,35 @@ def test_global_local_recovers_reference_iterations():
         its[name] = it
     assert abs(its["gl"] - its["ref"]) <= 1
     assert its["plain"] >= its["gl"] + 4
+
+
+def test_sgs_vcycle_equals_brute_force_operator():
+    """Symmetric Gauss-Seidel as S_g: the cycle is the dense multigrid operator
+    built from the smoother's own dense matrix, and symmetric positive definite."""
+    meshes = [meshgen.square_mesh(8, 0, n_single=2, single_depth=1e-3), meshgen.square_mesh(4, 10)]
+    H = Hierarchy(meshes, tau=0.1, layers=1, opts=Options(degree=1, global_smoother="sgs"))
+    n = H.levels[0].A.shape[0]
+    V = np.stack([H.vcycle(e) for e in np.eye(n)], axis=1)
+    B = _dense_B(H, 0)
+    assert np.allclose(V, B, atol=1e-9 * np.abs(B).max())
+    assert np.allclose(V, V.T, atol=1e-9 * np.abs(V).max())
+    assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+
+
+def test_sgs_global_local_recovers_reference_cycles():
+    """Sec. 3.2 / Sec. 6.1 with symmetric Gauss-Seidel as the global smoother
+    (multigrid as a stationary solver, as in the paper): the local correction
+    restores the reference mesh's cycle count, the plain smoother does not."""
+    low = meshgen.hierarchy("square_p1_4k", seed=0)
+    ref = meshgen.hierarchy("square_p1_4k", seed=0, case="ref")
+    cyc = {}
+    for name, meshes, local in (("gl", low, True), ("plain", low, False), ("ref", ref, True)):
+        H = Hierarchy(meshes, tau=0.1, layers=2,
+                      opts=Options(degree=1, local_correction=local, adjusted_eig=local, global_smoother="sgs",
+                                   nu=1))
+        b = meshgen.random_rhs(H.levels[0].A.shape[0], 1)
+        _, it, conv, _ = H.mg_solve(b, 1e-8, 300)
+        assert conv
+        cyc[name] = it
+    assert cyc["gl"] <= cyc["ref"] + 2
+    assert cyc["plain"] >= 2 * cyc["gl"]

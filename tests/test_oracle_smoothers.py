@@ -191,3 +191,67 @@ def test_smoother_error_localises_at_low_quality_cells():
     for _ in range(5):
         v = sandwich(A, dinv, b, v, L, 2, lam / 10, lam)
     assert np.abs(v[inside]).max() < 0.05 * np.abs(u[inside]).max()
+
+
+# --- symmetric Gauss-Seidel as the global smoother --------------------------
+
+def _sgs_problem(degree=2):
+    m = meshgen.square_mesh(6, 3, n_single=2, single_depth=1e-3)
+    _, A, _ = oracle.assemble(m, degree)
+    return A.tocsr()
+
+
+def test_matrix_colouring_is_proper_and_greedy():
+    A = _sgs_problem()
+    col = oracle.matrix_colouring(A)
+    C = A.tocoo()
+    off = C.row != C.col
+    assert np.all(col[C.row[off]] != col[C.col[off]])          # proper
+    deg = np.diff(A.indptr) - 1
+    assert col.max() <= deg.max()                               # at most max degree + 1 colours
+    for i in range(A.shape[0]):                                 # greedy: no smaller colour was free
+        nbr = A.indices[A.indptr[i]:A.indptr[i + 1]]
+        lower = set(col[nbr[nbr < i]].tolist())
+        assert all(c in lower for c in range(col[i]))
+
+
+def test_forward_colour_sweep_is_sequential_gauss_seidel():
+    """A forward sweep equals Gauss-Seidel in colour-major row order, computed
+    here by a sparse triangular solve: u' = u + (D + L)^-1 (b - A u) with L the
+    strictly lower part of the symmetrically permuted matrix."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    A = _sgs_problem()
+    n = A.shape[0]
+    col = oracle.matrix_colouring(A)
+    S = oracle.SymmetricGaussSeidel(A, col)
+    rng = np.random.default_rng(4)
+    b, u = rng.normal(size=n), rng.normal(size=n)
+    fwd = u.copy()
+    for c in range(len(S.rows)):
+        S._colour(c, b, fwd)
+    perm = np.argsort(col, kind="stable")
+    Ap = A[perm][:, perm]
+    DL = sp.tril(Ap, format="csr")
+    r = (b - A @ u)[perm]
+    want = u.copy()
+    want[perm] += spla.spsolve_triangular(DL, r, lower=True)
+    assert np.allclose(fwd, want, atol=1e-12 * np.abs(want).max())
+    # the backward sweep is the transposed (upper) solve in the same order
+    full = S.apply(b, u)
+    DU = sp.triu(Ap, format="csr")
+    r2 = (b - A @ want)[perm]
+    want2 = want.copy()
+    want2[perm] += spla.spsolve_triangular(DU, r2, lower=False)
+    assert np.allclose(full, want2, atol=1e-12 * np.abs(want2).max())
+
+
+def test_sgs_smoother_is_symmetric_and_convergent():
+    A = _sgs_problem()
+    n = A.shape[0]
+    S = oracle.SymmetricGaussSeidel(A, oracle.matrix_colouring(A))
+    M = np.stack([S.apply(e, np.zeros(n)) for e in np.eye(n)], axis=1)   # u = M b from u = 0
+    assert np.allclose(M, M.T, atol=1e-12 * np.abs(M).max())
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+    E = np.eye(n) - M @ A.toarray()
+    assert np.max(np.abs(np.linalg.eigvals(E))) < 1.0
