@@ -73,14 +73,15 @@ def log(msg):
 
 
 def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local=True, timing=False,
-            use_graph=False, seed0=1000, sigma=0, policy="merge"):
+            use_graph=False, seed0=1000, sigma=0, policy="merge", smoother="chebyshev"):
     import torch
 
     from paper_2402_12947_amd import Solver
     log(f"setup precision={precision} local={local}")
     t0 = time.perf_counter()
     s = Solver(meshes, degree=degree, tau=0.1, layers=layers, precision=precision,
-               local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma, policy=policy)
+               local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma, policy=policy,
+               global_smoother=smoother)
     setup_s = time.perf_counter() - t0
     n = s.n_free(0)
     log(f"setup done in {setup_s:.2f} s, {n} DOFs; solving")
@@ -103,7 +104,7 @@ def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local
            "converged": all(x["converged"] for x in stats),
            "true_rel_residual": max(x["true_rel_residual"] for x in stats),
            "levels": [s.level_info(l) for l in range(s.n_levels)]}
-    if timing:
+    if timing and smoother == "chebyshev":
         launches, total_ms = s.kernel_time()
         out["cheb_launches"] = launches
         out["cheb_avg_ms"] = total_ms / max(launches, 1)
@@ -273,6 +274,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the V-cycle from a hipGraph")
     ap.add_argument("--sigma", type=int, default=0, help="SELL sorting window (0 = library's choice)")
+    ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "sgs"],
+                    help="global smoother S_g of every arm (the roofline entry needs chebyshev)")
     ap.add_argument("--study", action="store_true",
                     help="instead of the benchmark line: the stationary-solver / preconditioner study of "
                          "plain vs global-local smoothing on the reference mesh and Cases A and B")
@@ -296,27 +299,32 @@ def main():
     meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
     arms = args.arms.split(",")
     main_arm = run_arm(meshes, degree, layers, rtol, args.steps, args.warmup, precision=args.precision,
-                       local=True, timing=True, use_graph=args.graph, sigma=args.sigma, policy=policy)
+                       local=True, timing=True, use_graph=args.graph, sigma=args.sigma, policy=policy,
+                       smoother=args.smoother)
     n = main_arm["n"]
     value = n * args.steps / main_arm["elapsed_s"]
     extra = {}
     if "plain" in arms:
-        p = run_arm(meshes, degree, layers, rtol, max(1, args.steps // 2), 1, precision="fp64", local=False)
+        p = run_arm(meshes, degree, layers, rtol, max(1, args.steps // 2), 1, precision="fp64", local=False,
+                    smoother=args.smoother)
         extra["plain_fp64"] = {"dofs_per_s": p["n"] * len(p["iterations"]) / p["elapsed_s"],
                                "iterations": p["iterations"][0], "setup_s": round(p["setup_s"], 3),
                                "true_rel_residual": p["true_rel_residual"]}
     if "mixed" in arms and args.precision == "fp64":
-        mx = run_arm(meshes, degree, layers, rtol, args.steps, 1, precision="mixed", local=True, policy=policy)
+        mx = run_arm(meshes, degree, layers, rtol, args.steps, 1, precision="mixed", local=True, policy=policy,
+                     smoother=args.smoother)
         extra["global_local_mixed"] = {"dofs_per_s": mx["n"] * len(mx["iterations"]) / mx["elapsed_s"],
                                        "iterations": mx["iterations"][0], "setup_s": round(mx["setup_s"], 3),
                                        "true_rel_residual": mx["true_rel_residual"]}
-    avg_ms = main_arm["cheb_avg_ms"]
-    achieved = main_arm["cheb_bytes"] / (avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(args.workload, args.precision)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": CHEB_KERNEL, "avg_launch_ms": round(avg_ms, 5),
-                "algorithmic_bytes_per_launch": main_arm["cheb_bytes"], "launches": main_arm["cheb_launches"]}
+    roofline = None
+    if args.smoother == "chebyshev":
+        avg_ms = main_arm["cheb_avg_ms"]
+        achieved = main_arm["cheb_bytes"] / (avg_ms * 1e-3) / 1e9
+        traffic = read_traffic(args.workload, args.precision)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                    "kernel": CHEB_KERNEL, "avg_launch_ms": round(avg_ms, 5),
+                    "algorithmic_bytes_per_launch": main_arm["cheb_bytes"], "launches": main_arm["cheb_launches"]}
     line = {
         "metric": "DOFs solved/sec to rtol 1e-8 (MG-PCG, global-local smoother)",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -325,7 +333,9 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32-in-f64",
         "data": "synthetic (seeded meshes and right-hand sides)",
         "config": {"workload": args.workload, "dofs": n, "levels": len(meshes), "rtol": rtol,
-                   "smoother": "S_c -> Chebyshev-Jacobi(2) -> S_c, V(2,2), adjusted lambda_max",
+                   "smoother": ("S_c -> Chebyshev-Jacobi(2) -> S_c, V(2,2), adjusted lambda_max"
+                                if args.smoother == "chebyshev" else
+                                "S_c -> multicolour symmetric Gauss-Seidel -> S_c, V(2,2)"),
                    "precision": args.precision, "patch_layers": layers, "patch_policy": policy,
                    "iterations": main_arm["iterations"][0],
                    "setup_s": round(main_arm["setup_s"], 3),

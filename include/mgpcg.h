@@ -59,6 +59,7 @@ typedef enum {
 
 enum { MG_FP64 = 0, MG_MIXED = 1 };
 enum { MG_PATCH_MERGE = 0, MG_PATCH_OVERLAP = 1 };
+enum { MG_SMOOTHER_CHEBYSHEV = 0, MG_SMOOTHER_SGS = 1 };
 
 /* One level of the hierarchy: an independent simplicial mesh of the domain. */
 typedef struct {
@@ -90,6 +91,13 @@ typedef struct {
   int32_t sell_sigma;       /* SELL row-sorting window: 0 = autotune, 1 = off,
                                else a multiple of 64                          */
   void *stream;             /* hipStream_t to run on; NULL = library-owned     */
+  int32_t global_smoother;  /* S_g: MG_SMOOTHER_CHEBYSHEV (Chebyshev-Jacobi,
+                               the default) or MG_SMOOTHER_SGS: one forward and
+                               one backward multicolour Gauss-Seidel sweep
+                               (Sec. 3.2, Sec. 6.1); the rows are coloured
+                               greedily in canonical order, each row taking the
+                               smallest colour unused by its lower-numbered
+                               neighbours; no eigenvalue estimate is made      */
 } mg_options;
 
 typedef struct {
@@ -139,12 +147,16 @@ enum {
   MG_ARR_P_COLS = 12,      /* int32   [n_free * width] (row-major, -1 = none)   */
   MG_ARR_P_VALS = 13,      /* double  [n_free * width]                          */
   MG_ARR_CELL_DOFS = 14,   /* int32   [n_cells * n_local] canonical DOF ids     */
-  MG_ARR_P_WIDTH = 15      /* int32   [1] coarse DOFs per cell (ELL width)      */
+  MG_ARR_P_WIDTH = 15,     /* int32   [1] coarse DOFs per cell (ELL width)      */
+  MG_ARR_SGS_COLOUR = 16   /* int32   [n_free] Gauss-Seidel colour of each
+                              unknown (MG_SMOOTHER_SGS, levels above the
+                              coarsest)                                       */
 };
 
 /* Fills *opt with: degree 1, MG_FP64, nu 2, cheb_degree 2, cheb_lo_frac 0.1,
  * local_correction 1, adjusted_eig 1, MG_PATCH_MERGE, eig_tol 1e-8,
- * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL. */
+ * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
+ * global_smoother MG_SMOOTHER_CHEBYSHEV. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

@@ -35,7 +35,8 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
   Poisson experiments, Sec. 3.2 and Sec. 6.1; one forward and one backward
   sweep per application).  Here the multicolour form: the rows are coloured
   greedily in row order (each row takes the smallest colour not used by a
-  lower-numbered neighbour in the matrix graph); a forward sweep updates the
+  lower-numbered neighbour in the matrix graph, |a_ij| > 1e-12 sqrt(a_ii a_jj));
+  a forward sweep updates the
   colours in ascending order, all rows of a colour at once from the current
   iterate, u_i += (b_i - (A u)_i) / a_ii, the backward sweep in descending
   order.  Rows of one colour are not coupled, so a forward sweep is exactly
@@ -154,15 +155,24 @@ class LocalCorrection:
         return u
 
 
+COUPLING_EPS = 1e-12
+
+
 def matrix_colouring(A: sp.csr_matrix) -> np.ndarray:
     """Greedy colouring of the matrix graph in row order: row i takes the
-    smallest colour not used by any neighbour j < i (a_ij != 0)."""
+    smallest colour not used by any neighbour j < i.  Rows i and j are
+    neighbours if |a_ij| > 1e-12 sqrt(a_ii a_jj): a Galerkin product can hold
+    entries that cancel to zero or to rounding noise, which are not couplings
+    (and whose presence depends on the summation order)."""
     A = sp.csr_matrix(A)
     n = A.shape[0]
+    d = np.sqrt(np.abs(A.diagonal()))
     col = np.full(n, -1, dtype=np.int64)
     for i in range(n):
         nbr = A.indices[A.indptr[i]:A.indptr[i + 1]]
-        used = set(col[nbr[nbr < i]].tolist())
+        val = A.data[A.indptr[i]:A.indptr[i + 1]]
+        keep = (nbr < i) & (np.abs(val) > COUPLING_EPS * d[i] * d[nbr])
+        used = set(col[nbr[keep]].tolist())
         c = 0
         while c in used:
             c += 1

@@ -23,7 +23,7 @@ MAX_HISTORY = 1024
 
 ARR = {"quality": 1, "flags": 2, "patch_ptr": 3, "patch_dofs": 4, "patch_colour": 5, "locate": 6,
        "free_dofs": 7, "dof_nodes": 8, "a_rowptr": 9, "a_cols": 10, "a_vals": 11, "p_cols": 12,
-       "p_vals": 13, "cell_dofs": 14, "p_width": 15}
+       "p_vals": 13, "cell_dofs": 14, "p_width": 15, "sgs_colour": 16}
 
 
 class MgMesh(C.Structure):
@@ -37,7 +37,8 @@ class MgOptions(C.Structure):
                 ("cheb_degree", C.c_int32), ("cheb_lo_frac", C.c_double),
                 ("local_correction", C.c_int32), ("adjusted_eig", C.c_int32),
                 ("patch_policy", C.c_int32), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32),
-                ("use_graph", C.c_int32), ("sell_sigma", C.c_int32), ("stream", C.c_void_p)]
+                ("use_graph", C.c_int32), ("sell_sigma", C.c_int32), ("stream", C.c_void_p),
+                ("global_smoother", C.c_int32)]
 
 
 class MgSolveStats(C.Structure):
@@ -138,7 +139,8 @@ class Solver:
     def __init__(self, meshes: list, degree: int = 1, tau: float = 0.1, layers: int = 1,
                  precision: str = "fp64", nu: int = 2, cheb_degree: int = 2, cheb_lo_frac: float = 0.1,
                  local_correction: bool = True, adjusted_eig: bool = True, policy: str = "merge",
-                 eig_tol: float = 1e-8, eig_maxit: int = 200, use_graph: bool = False, sell_sigma: int = 0):
+                 eig_tol: float = 1e-8, eig_maxit: int = 200, use_graph: bool = False, sell_sigma: int = 0,
+                 global_smoother: str = "chebyshev"):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -154,6 +156,9 @@ class Solver:
         opt.eig_maxit = eig_maxit
         opt.use_graph = int(bool(use_graph))
         opt.sell_sigma = sell_sigma
+        if global_smoother not in ("chebyshev", "sgs"):
+            raise ValueError("global_smoother must be 'chebyshev' or 'sgs'")
+        opt.global_smoother = 1 if global_smoother == "sgs" else 0
         keep: list = []
         arr = (MgMesh * len(meshes))(*[_mesh_struct(m, keep) for m in meshes])
         h = C.c_void_p()
@@ -201,6 +206,7 @@ class Solver:
             "quality": (np.float64, n), "flags": (np.uint8, n),
             "patch_ptr": (np.int32, info["n_patches"] + 1), "patch_dofs": (np.int32, info["sum_patch_dofs"]),
             "patch_colour": (np.int32, info["n_patches"]), "locate": (np.int32, nf),
+            "sgs_colour": (np.int32, nf),
             "free_dofs": (np.int32, nf), "dof_nodes": (np.float64, info["n_dofs"] * self.dim),
             "a_rowptr": (np.int64, nf + 1), "a_cols": (np.int32, info["nnz"]), "a_vals": (np.float64, info["nnz"]),
             "p_cols": (np.int32, nf * int(pw[0])), "p_vals": (np.float64, nf * int(pw[0])),

@@ -133,6 +133,15 @@ static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt) {
   }
 }
 
+// symmetric Gauss-Seidel as S_g: colours ascending, then descending, in place
+template <class T>
+static void sgs_sweeps(Ctx &c, int l, const T *b, T *u) {
+  Level &L = c.lv[l];
+  const int nc = (int)L.sgs.size();
+  for (int k = 0; k < nc; ++k) sgs_colour_sweep<T>(c.stream, L.sgs[k], L.sgs_pos[k], LV<T>::dinv(L), b, u);
+  for (int k = nc - 1; k >= 0; --k) sgs_colour_sweep<T>(c.stream, L.sgs[k], L.sgs_pos[k], LV<T>::dinv(L), b, u);
+}
+
 // u <- S^nu (b, u): nu applications of S_c -> S_g -> S_c (paper Sec. 4.2)
 template <class T>
 static void smooth(Ctx &c, int l, const T *b, T *u, int nu) {
@@ -142,7 +151,8 @@ static void smooth(Ctx &c, int l, const T *b, T *u, int nu) {
   if (u == alt) alt = LV<T>::w(L, W_T);
   for (int s = 0; s < nu; ++s) {
     if (local) local_correction<T>(c, L, b, cur, false);
-    chebyshev<T>(c, l, b, cur, alt);
+    if (c.opt.global_smoother == MG_SMOOTHER_SGS) sgs_sweeps<T>(c, l, b, cur);
+    else chebyshev<T>(c, l, b, cur, alt);
     if (local) local_correction<T>(c, L, b, cur, true);
   }
   if (cur != u) convert<T, T>(c.stream, cur, u, L.nfree);
@@ -262,6 +272,7 @@ void mg_default_options(mg_options *o) {
   o->eig_maxit = 200;
   o->use_graph = 0;
   o->sell_sigma = 0;
+  o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
   o->stream = nullptr;
 }
 
@@ -305,6 +316,8 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.precision != MG_FP64 && o.precision != MG_MIXED) fail(MG_ERR_ARG, "bad precision");
     if (o.nu < 0 || o.cheb_degree < 1 || !(o.cheb_lo_frac >= 0 && o.cheb_lo_frac < 1) || o.eig_maxit < 1)
       fail(MG_ERR_ARG, "bad smoother options");
+    if (o.global_smoother != MG_SMOOTHER_CHEBYSHEV && o.global_smoother != MG_SMOOTHER_SGS)
+      fail(MG_ERR_ARG, "global_smoother must be MG_SMOOTHER_CHEBYSHEV or MG_SMOOTHER_SGS");
     if (o.sell_sigma < 0 || (o.sell_sigma > 1 && o.sell_sigma % SELL_C))
       fail(MG_ERR_ARG, "sell_sigma must be 0, 1 or a multiple of 64");
     for (int l = 0; l < n_levels; ++l) validate_mesh(levels[l], dim, l);
@@ -358,6 +371,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       solve_order(c, L, L.coarsest ? 1 : c.opt.sell_sigma, mixed && !L.coarsest);
       permute_patches(c, L);
       if (!L.coarsest) build_patch_rows(c, L, mixed);
+      if (!L.coarsest && o.global_smoother == MG_SMOOTHER_SGS) build_sgs(c, L, mixed);
       L.setup_ms += ms(t0, now());
       phase("solve order", l);
     }
@@ -370,8 +384,10 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
         L.Rc = Csr();
         factor_patches(c, L);
         phase("patch factorisation", l);
-        estimate_eigenvalues(c, L);
-        phase("eigenvalue estimates", l);
+        if (o.global_smoother == MG_SMOOTHER_CHEBYSHEV) {  // Gauss-Seidel needs no spectral bound
+          estimate_eigenvalues(c, L);
+          phase("eigenvalue estimates", l);
+        }
       } else {
         factor_coarsest(c, L);
         phase("coarsest factorisation", l);
@@ -721,6 +737,10 @@ mg_status mg_get_array(const mg_ctx *h, int32_t level, int32_t what, void *out) 
     case MG_ARR_P_VALS: copy_out(s, L.pval.p, L.coarsest ? 0 : L.nfree * L.pw, out); break;
     case MG_ARR_CELL_DOFS: copy_out(s, L.cell_dofs.p, L.nc * L.nloc, out); break;
     case MG_ARR_P_WIDTH: *(int32_t *)out = L.pw; break;
+    case MG_ARR_SGS_COLOUR:
+      if (!L.sgs_colour.p) fail(MG_ERR_ARG, "no Gauss-Seidel colouring on this level");
+      copy_out(s, L.sgs_colour.p, L.nfree, out);
+      break;
     default: fail(MG_ERR_ARG, "unknown array %d", what);
   }
   return MG_OK;

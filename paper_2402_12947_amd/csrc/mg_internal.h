@@ -193,6 +193,12 @@ struct Level {
   Sell P, R;                   // y += P x_c ; y = R r
   // local correction
   Patches patch;
+  // multicolour symmetric Gauss-Seidel (global smoother option): the rows of
+  // each colour as a SELL matrix (columns in solve order) and their solve-order
+  // positions; the colour of every unknown in canonical order (export)
+  std::vector<Sell> sgs;
+  std::vector<DBuf<int32_t>> sgs_pos;
+  DBuf<int32_t> sgs_colour;
   // Chebyshev
   double lam = 0, lam_adj = 0, lo = 0, hi = 0;
   int lanczos_steps = 0, lanczos_steps_adj = 0;
@@ -253,6 +259,7 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m);
 void factor_patches(Ctx &c, Level &L);
 void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad);
 void build_patch_rows(Ctx &c, Level &L, bool want32);
+void build_sgs(Ctx &c, Level &L, bool want32);
 void factor_coarsest(Ctx &c, Level &L);
 void estimate_eigenvalues(Ctx &c, Level &L);
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);
@@ -282,6 +289,8 @@ template <class T>
 void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u);
 template <class T>
 void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u);
+template <class T>
+void sgs_colour_sweep(hipStream_t s, const Sell &S, const int32_t *pos, const T *dinv, const T *b, T *u);
 
 
 template <class T>

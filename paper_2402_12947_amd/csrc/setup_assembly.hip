@@ -14,6 +14,8 @@
 #include <cmath>
 
 #include "basis.h"
+#include <algorithm>
+
 #include "devutil.h"
 #include "geom.h"
 
@@ -540,6 +542,66 @@ void build_patch_rows(Ctx &c, Level &L, bool want32) {
   permute_csr(c, L.A, P.dofs_canon, P.total, L.iperm, L.nfree, B);
   build_sell(c, B, P.rows, 1, want32);
   P.rows.perm.release();
+}
+
+// Multicolour symmetric Gauss-Seidel: greedy colouring of the matrix graph in
+// canonical row order (row i takes the smallest colour not used by a coupled
+// neighbour j < i), then the rows of every colour, in solve order, as a SELL
+// matrix whose columns are solve-order positions.
+void build_sgs(Ctx &c, Level &L, bool want32) {
+  hipStream_t s = c.stream;
+  const int64_t n = L.nfree;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> col, ip;
+  std::vector<double> val;
+  download(rp, L.A.rowptr.p, (size_t)n + 1, s);
+  download(col, L.A.col.p, (size_t)L.A.nnz, s);
+  download(val, L.A.val.p, (size_t)L.A.nnz, s);
+  download(ip, L.iperm.p, (size_t)n, s);
+  // rows i and j are coupled if |a_ij| > 1e-12 sqrt(a_ii a_jj): Galerkin entries
+  // that cancel to zero or to rounding noise are not couplings
+  std::vector<double> dsq((size_t)n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (col[k] == i) dsq[i] = std::sqrt(std::fabs(val[k]));
+  std::vector<int32_t> colour((size_t)n, -1);
+  std::vector<int64_t> mark;  // mark[k] == i: colour k is taken by a lower neighbour of row i
+  int ncol = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      int32_t j = col[k];
+      if (j < i && std::fabs(val[k]) > 1e-12 * dsq[i] * dsq[j]) {
+        size_t cj = (size_t)colour[j];
+        if (cj >= mark.size()) mark.resize(cj + 1, -1);
+        mark[cj] = i;
+      }
+    }
+    int k = 0;
+    while ((size_t)k < mark.size() && mark[k] == i) ++k;
+    colour[i] = k;
+    ncol = std::max(ncol, k + 1);
+  }
+  upload(L.sgs_colour, colour.data(), colour.size(), s);
+  std::vector<std::vector<int32_t>> rows(ncol);
+  for (int64_t i = 0; i < n; ++i) rows[colour[i]].push_back((int32_t)i);
+  L.sgs.clear();
+  L.sgs_pos.clear();
+  L.sgs.resize(ncol);
+  L.sgs_pos.resize(ncol);
+  for (int k = 0; k < ncol; ++k) {
+    auto &r = rows[k];
+    std::sort(r.begin(), r.end(), [&](int32_t a, int32_t b) { return ip[a] < ip[b]; });
+    std::vector<int32_t> pos(r.size());
+    for (size_t t = 0; t < r.size(); ++t) pos[t] = ip[r[t]];
+    DBuf<int32_t> dr;
+    upload(dr, r.data(), r.size(), s);
+    Csr B;
+    permute_csr(c, L.A, dr, (int64_t)r.size(), L.iperm, n, B);
+    build_sell(c, B, L.sgs[k], 1, want32);
+    L.sgs[k].perm.release();
+    upload(L.sgs_pos[k], pos.data(), pos.size(), s);
+  }
+  MG_HIP(hipStreamSynchronize(s));
 }
 
 // average time of the level's Chebyshev-step kernel in its current layout

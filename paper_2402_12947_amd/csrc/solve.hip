@@ -35,10 +35,10 @@ static inline SellCols cols_of(const Sell &S) {
 // entries are streamed once per product, so they are loaded non-temporally and
 // leave the cache to the gathered vector; slices whose columns fit two windows
 // of 32768 read 16-bit columns.
-template <class T, class C, class F>
+template <int U, class T, class C, class F>
 __device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
                              F decode) {
-  constexpr int U = 8;  // eight independent gathers in flight per lane
+  // U independent gathers in flight per lane
   T a[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) a[u] = 0;
@@ -55,12 +55,15 @@ __device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp,
     for (int u = 0; u < U; ++u) a[u] += v[u] * x[c[u]];
   }
   for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[decode(__builtin_nontemporal_load(cp + j * 64))];
-  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  T s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  if (U == 16) s += ((a[8] + a[9]) + (a[10] + a[11])) + ((a[12] + a[13]) + (a[14] + a[15]));
+  return s;
 }
 
-template <class T>
+template <class T, int U = 8>
 __device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
                              int lane) {
+  static_assert(U == 8 || U == 16, "8 or 16 gathers in flight");
   const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
   const int64_t base = S.sptr[s32];
   const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
@@ -68,17 +71,17 @@ __device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const
   const int b0 = S.cbase[2 * s32];
   if (b0 >= 0) {
     const int bh = S.cbase[2 * s32 + 1] - 0x8000;
-    return sell_dot(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
+    return sell_dot<U>(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
   }
   if (b0 < -1) {
     // window bases in lanes 0..15, picked per entry by a cross-lane read
     const int tb = S.ctab[16 * (int64_t)s32 + (lane & 15)];
     const int shift = b0 == -2 ? 13 : 12;
     const int mask = (1 << shift) - 1;
-    return sell_dot(S.col16 + base + lane, vp, x, w,
-                    [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); });
+    return sell_dot<U>(S.col16 + base + lane, vp, x, w,
+                       [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); });
   }
-  return sell_dot(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; });
+  return sell_dot<U>(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; });
 }
 
 // Unknowns are numbered in the operator's row order (solve order), so the row
@@ -162,6 +165,34 @@ template void cheb_step<double>(hipStream_t, const Sell &, const double *, const
                                 double *, int, double, double);
 template void cheb_step<float>(hipStream_t, const Sell &, const float *, const float *, const float *, float *,
                                float *, int, double, double);
+
+// One colour of a multicolour Gauss-Seidel sweep: u_r += D^-1_r (b_r - (A u)_r)
+// for the rows r of the colour (pos maps SELL rows to solve-order unknowns).
+// Rows of one colour are not coupled, so the update in place is race-free.
+template <class T>
+__global__ __launch_bounds__(256) void k_sgs_colour(int64_t nslices, int64_t nrows, SellCols cols,
+                                                    const T *__restrict__ val, const int32_t *__restrict__ pos,
+                                                    const T *__restrict__ dinv, const T *__restrict__ b,
+                                                    T *__restrict__ u) {
+  int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t sl = k >> 6;
+  if (sl >= nslices) return;
+  T acc = sell_row(cols, val, u, sl, (int)(k & 63));
+  if (k >= nrows) return;
+  const int32_t r = pos[k];
+  u[r] += dinv[r] * (b[r] - acc);
+}
+
+template <class T>
+void sgs_colour_sweep(hipStream_t s, const Sell &S, const int32_t *pos, const T *dinv, const T *b, T *u) {
+  if (S.nslices == 0) return;
+  k_sgs_colour<T><<<sell_grid(S), 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), sell_vals<T>(S), pos, dinv, b, u);
+  MG_LAUNCH_CHECK();
+}
+template void sgs_colour_sweep<double>(hipStream_t, const Sell &, const int32_t *, const double *, const double *,
+                                       double *);
+template void sgs_colour_sweep<float>(hipStream_t, const Sell &, const int32_t *, const float *, const float *,
+                                      float *);
 
 // ---------------------------------------------------------------------------
 // local correction

@@ -7,18 +7,20 @@ import oracle
 
 
 def build_pair(meshes, degree, tau=0.1, layers=1, precision="fp64", local=True, adjusted=True,
-               policy="merge", use_graph=False, nu=2, k=2, eig_maxit=200, build_oracle=True):
+               policy="merge", use_graph=False, nu=2, k=2, eig_maxit=200, build_oracle=True,
+               smoother="chebyshev"):
     from paper_2402_12947_amd import Solver
     gpu = Solver(meshes, degree=degree, tau=tau, layers=layers, precision=precision,
                  local_correction=local, adjusted_eig=adjusted, policy=policy, use_graph=use_graph,
-                 nu=nu, cheb_degree=k, eig_maxit=eig_maxit)
+                 nu=nu, cheb_degree=k, eig_maxit=eig_maxit, global_smoother=smoother)
     ora = None
     if build_oracle:
         ora = oracle.Hierarchy(meshes, tau=tau, layers=layers,
                                opts=oracle.Options(degree=degree, nu=nu, cheb_degree=k, local_correction=local,
                                                    adjusted_eig=adjusted,
                                                    patch_policy=oracle.OVERLAP if policy == "overlap"
-                                                   else oracle.MERGE, eig_maxit=eig_maxit))
+                                                   else oracle.MERGE, eig_maxit=eig_maxit,
+                                                   global_smoother=smoother))
     return gpu, ora
 
 
