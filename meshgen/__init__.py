@@ -25,7 +25,7 @@ import numpy as np
 
 __all__ = [
     "square_mesh", "cube_mesh", "hierarchy", "random_rhs", "CONFIGS",
-    "orientation", "instance_batch", "stress_cube_mesh",
+    "orientation", "instance_batch", "stress_cube_mesh", "lattice_mesh",
 ]
 
 
@@ -353,6 +353,67 @@ def stress_cube_mesh(n: int, seed: int, jitter: float = 0.15, flat: float = 0.01
             "dirichlet_vertex": _dirichlet_3d(coords, dirichlet)}
 
 
+def lattice_mesh(n: int, seed: int, jitter: float = 0.15, slivers: int = 0, depth=(1e-4, 3e-3)) -> dict:
+    """Kuhn tetrahedralisation of the truss-like lattice [0,6]^3 minus the three
+    tunnels a x b^2, b x a x b, b^2 x a with a = [0, 6], b = [1, 5] (the twelve
+    edges of the cube as bars of unit cross-section), on a grid of n intervals
+    per side (n a multiple of 6, so the tunnel walls are grid planes).
+
+    Vertex jitter leaves every coordinate that lies on a plane 0, 1, 5 or 6
+    unchanged, so the boundary is the same for every level; degraded cells
+    (`slivers`, as in cube_mesh) use vertices off those planes.  Dirichlet
+    vertices: the face x = 0.
+    """
+    if n % 6:
+        raise ValueError("lattice_mesh needs n divisible by 6")
+    rng = np.random.default_rng(seed)
+    coords, cells, _ = _cube_grid(n, rng, 0.0)
+    coords *= 6.0
+    h = 6.0 / n
+    on_plane = np.zeros(coords.shape, dtype=bool)
+    for v in (0.0, 1.0, 5.0, 6.0):
+        on_plane |= np.abs(coords - v) < 1e-9
+    disp = rng.uniform(-jitter * h, jitter * h, size=coords.shape)
+    disp[on_plane] = 0.0
+    coords = coords + disp
+    cen = coords[cells].mean(axis=1)
+    inb = (cen > 1.0) & (cen < 5.0)
+    hole = (inb[:, 1] & inb[:, 2]) | (inb[:, 0] & inb[:, 2]) | (inb[:, 0] & inb[:, 1])
+    cells = cells[~hole]
+    used = np.unique(cells)
+    remap = np.full(coords.shape[0], -1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    coords = np.ascontiguousarray(coords[used])
+    on_plane = on_plane[used]
+    cells = remap[cells].astype(np.int32)
+    if slivers > 0:
+        free = ~on_plane.any(axis=1)
+        # _degrade picks candidates near each centre on the structured grid; here
+        # the vertex set is compacted, so candidates are the free vertices
+        # nearest to each centre
+        ptr, cell_of = _vertex_cells(coords.shape[0], cells)
+        cand_all = np.flatnonzero(free)
+        centres = coords[rng.choice(cand_all, size=min(slivers, cand_all.size), replace=False)]
+        used_v = np.zeros(coords.shape[0], dtype=bool)
+        for centre in centres:
+            dist = np.linalg.norm(coords[cand_all] - centre, axis=1)
+            for v in cand_all[np.argsort(dist, kind="stable")[:8]]:
+                if used_v[v]:
+                    continue
+                inc = cell_of[ptr[v]:ptr[v + 1]]
+                cell = inc[rng.integers(0, inc.size)]
+                d = float(np.exp(rng.uniform(np.log(depth[0]), np.log(depth[1]))))
+                old = coords[v].copy()
+                coords[v] = _displace_towards_facet(coords, cells, v, cell, d, rng)
+                if np.all(orientation(coords, cells[inc]) > 0):
+                    used_v[np.unique(cells[inc])] = True
+                    break
+                coords[v] = old
+    assert np.all(orientation(coords, cells) > 0)
+    dv = (np.abs(coords[:, 0]) < 1e-12).astype(np.uint8)
+    return {"dim": 3, "coords": coords, "cells": np.ascontiguousarray(cells), "dirichlet_vertex": dv}
+
+
 # ----------------------------------------------------------------------------
 # workload hierarchies
 # ----------------------------------------------------------------------------
@@ -381,6 +442,10 @@ CONFIGS = {
     # degraded cells.
     "cube_129_stress": dict(kind="cube_stress", sides=[128, 64, 32, 16, 8], jitter=0.15,
                             dirichlet=("x0", "x1")),
+    # elasticity: the lattice [0,6]^3 minus three orthogonal tunnels, four levels
+    # of 8, 4, 2 and 1 grid cells per unit (the bars are one unit thick), 400
+    # degraded cells on the finest level, clamped at x = 0
+    "lattice": dict(kind="lattice", sides=[48, 24, 12, 6], jitter=0.15, slivers=[400, 60, 8, 1]),
 }
 
 
@@ -409,6 +474,12 @@ def hierarchy(name: str, seed: int = 0, scale: int = 1, case: str = "fine") -> l
                                    n_single=nsingle,
                                    single_depth=cfg.get("single_depth", 1e-3),
                                    dirichlet=cfg["dirichlet"]))
+        elif cfg["kind"] == "lattice":
+            m = max(6, (n // 6) * 6)
+            ns = (cfg["slivers"][lvl] // (scale ** 3)) if degrade else 0
+            if degrade and cfg["slivers"][lvl] > 0:
+                ns = max(1, ns)
+            out.append(lattice_mesh(m, lseed, jitter=cfg["jitter"], slivers=ns))
         elif cfg["kind"] == "cube_stress":
             if degrade:
                 out.append(stress_cube_mesh(n, lseed, jitter=cfg["jitter"], dirichlet=cfg["dirichlet"]))

@@ -29,11 +29,12 @@ from .quality import radius_ratio
 from .smoothers import (LocalCorrection, SymmetricGaussSeidel, chebyshev, lanczos_lmax, matrix_colouring, sandwich,
                         splitmix64, start_vector)
 from .transfer import LocateError, barycentric, galerkin, locate, prolongation
+from . import elasticity
 
 __all__ = [
     "DofMap", "assemble", "assemble_full", "element_matrices", "local_basis",
     "reference_tensors", "Hierarchy", "Options", "MERGE", "OVERLAP", "colour",
     "patches", "radius_ratio", "LocalCorrection", "chebyshev", "lanczos_lmax",
     "sandwich", "splitmix64", "start_vector", "LocateError", "barycentric",
-    "galerkin", "locate", "prolongation", "SymmetricGaussSeidel", "matrix_colouring",
+    "galerkin", "locate", "prolongation", "SymmetricGaussSeidel", "matrix_colouring", "elasticity",
 ]

@@ -31,6 +31,7 @@ import scipy.sparse as sp
 from .fem import DofMap, assemble
 from .patches import MERGE, colour, patches
 from .quality import radius_ratio
+from . import elasticity
 from .smoothers import LocalCorrection, SymmetricGaussSeidel, lanczos_lmax, matrix_colouring, sandwich
 from .transfer import galerkin, prolongation
 
@@ -47,6 +48,9 @@ class Options:
     eig_tol: float = 1e-8
     eig_maxit: int = 200
     global_smoother: str = "chebyshev"   # or "sgs" (multicolour symmetric Gauss-Seidel)
+    problem: str = "poisson"             # or "elasticity" (Sec. 6.2)
+    young: float = 6.9e10
+    poisson_ratio: float = 0.33
 
 
 @dataclass
@@ -79,18 +83,27 @@ class Hierarchy:
         nlev = len(meshes)
         dms = [DofMap(m, opts.degree) for m in meshes]
         A = None
+        elastic = opts.problem == "elasticity"
+        ncomp = meshes[0]["coords"].shape[1] if elastic else 1
         for l, (mesh, dm) in enumerate(zip(meshes, dms)):
             Mf = None
             if l == 0:
-                _, A, Mf = assemble(mesh, opts.degree)
+                if elastic:
+                    _, A = elasticity.assemble(mesh, opts.degree, opts.young, opts.poisson_ratio)
+                else:
+                    _, A, Mf = assemble(mesh, opts.degree)
             gamma = radius_ratio(mesh["coords"], mesh["cells"])
             pc, pd = patches(dm.cells, dm.coords.shape[0], gamma, tau, layers,
                              opts.patch_policy, dm.cell_dofs, dm.free_index)
+            if elastic:  # every component of the patch's scalar DOFs
+                pd = [elasticity.vector_ids(B, ncomp) for B in pd]
             cols = colour(pd)
             lev = Level(dofmap=dm, A=A, dinv=1.0 / A.diagonal(), gamma=gamma,
                         patch_cells=pc, patch_dofs=pd, colours=cols, Mf=Mf)
             if l < nlev - 1:
                 lev.P, lev.locate_cell = prolongation(dm, dms[l + 1])
+                if elastic:  # each component interpolated on its own: P (x) I
+                    lev.P = sp.kron(lev.P, sp.identity(ncomp), format="csr")
                 A = galerkin(A, lev.P)
             self.levels.append(lev)
         for l, lev in enumerate(self.levels):
@@ -183,4 +196,6 @@ class Hierarchy:
         return x, it, hist[-1] <= rtol, hist
 
     def rhs_from_nodal(self, f_nodal: np.ndarray) -> np.ndarray:
+        if self.levels[0].Mf is None:
+            raise ValueError("b = M f_hat is defined for the Poisson problem only")
         return self.levels[0].Mf @ f_nodal
