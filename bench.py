@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    # name: (meshgen recipe, degree, scale, layers, rtol, patch policy)
+    # name: (meshgen recipe, degree, scale, layers, rtol, patch policy[, problem])
     "square_1025_p2": ("square_1025", 2, 1, 1, 1e-8, "merge"),
     "square_1025_p3": ("square_1025", 3, 1, 1, 1e-8, "merge"),
     "cube_129_p1": ("cube_129", 1, 1, 1, 1e-8, "merge"),
@@ -40,6 +40,10 @@ WORKLOADS = {
     # patch stress: ~20k separate flattened regions, the regions themselves
     # are the subdomains (no extension layer), ~40 % of the DOFs in patches
     "cube_129_stress_p2": ("cube_129_stress", 2, 1, 0, 1e-8, "overlap"),
+    # linear elasticity on the truss-like lattice (vector P1 / P2, E = 6.9e10,
+    # nu = 0.33, clamped at x = 0), four levels
+    "lattice_96_p1": ("lattice_96", 1, 1, 1, 1e-8, "merge", "elasticity"),
+    "lattice_96_p2": ("lattice_96", 2, 1, 1, 1e-8, "merge", "elasticity"),
 }
 # many-instance workload: 32 unit-cube problems of 50k-3M DOFs, 4 right-hand sides each
 BATCH_WORKLOADS = {"cube_batch_32x4": (32, 4, 1), "cube_batch_small": (4, 2, 4)}
@@ -73,7 +77,7 @@ def log(msg):
 
 
 def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local=True, timing=False,
-            use_graph=False, seed0=1000, sigma=0, policy="merge", smoother="chebyshev"):
+            use_graph=False, seed0=1000, sigma=0, policy="merge", smoother="chebyshev", problem="poisson"):
     import torch
 
     from paper_2402_12947_amd import Solver
@@ -81,7 +85,7 @@ def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local
     t0 = time.perf_counter()
     s = Solver(meshes, degree=degree, tau=0.1, layers=layers, precision=precision,
                local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma, policy=policy,
-               global_smoother=smoother)
+               global_smoother=smoother, problem=problem)
     setup_s = time.perf_counter() - t0
     n = s.n_free(0)
     log(f"setup done in {setup_s:.2f} s, {n} DOFs; solving")
@@ -119,7 +123,7 @@ def _rhs(n, seed):
     return meshgen.random_rhs(n, seed)
 
 
-def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", budget_s=12.0):
+def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", problem="poisson", budget_s=12.0):
     import meshgen
     import oracle
     try:
@@ -130,7 +134,7 @@ def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", budget_s=1
     meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
     H = oracle.Hierarchy(meshes, tau=0.1, layers=layers,
                          opts=oracle.Options(degree=degree, patch_policy=oracle.OVERLAP if policy == "overlap"
-                                             else oracle.MERGE))
+                                             else oracle.MERGE, problem=problem))
     n = H.levels[0].A.shape[0]
     solved, t0 = 0, time.perf_counter()
     its = []
@@ -295,24 +299,25 @@ def main():
     if args.workload in BATCH_WORKLOADS:
         print(json.dumps(run_batch(args.workload, args.steps, args.warmup)), flush=True)
         return
-    recipe, degree, scale, layers, rtol, policy = WORKLOADS[args.workload]
+    recipe, degree, scale, layers, rtol, policy = WORKLOADS[args.workload][:6]
+    problem = WORKLOADS[args.workload][6] if len(WORKLOADS[args.workload]) > 6 else "poisson"
     meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
     arms = args.arms.split(",")
     main_arm = run_arm(meshes, degree, layers, rtol, args.steps, args.warmup, precision=args.precision,
                        local=True, timing=True, use_graph=args.graph, sigma=args.sigma, policy=policy,
-                       smoother=args.smoother)
+                       smoother=args.smoother, problem=problem)
     n = main_arm["n"]
     value = n * args.steps / main_arm["elapsed_s"]
     extra = {}
     if "plain" in arms:
         p = run_arm(meshes, degree, layers, rtol, max(1, args.steps // 2), 1, precision="fp64", local=False,
-                    smoother=args.smoother)
+                    smoother=args.smoother, problem=problem)
         extra["plain_fp64"] = {"dofs_per_s": p["n"] * len(p["iterations"]) / p["elapsed_s"],
                                "iterations": p["iterations"][0], "setup_s": round(p["setup_s"], 3),
                                "true_rel_residual": p["true_rel_residual"]}
     if "mixed" in arms and args.precision == "fp64":
         mx = run_arm(meshes, degree, layers, rtol, args.steps, 1, precision="mixed", local=True, policy=policy,
-                     smoother=args.smoother)
+                     smoother=args.smoother, problem=problem)
         extra["global_local_mixed"] = {"dofs_per_s": mx["n"] * len(mx["iterations"]) / mx["elapsed_s"],
                                        "iterations": mx["iterations"][0], "setup_s": round(mx["setup_s"], 3),
                                        "true_rel_residual": mx["true_rel_residual"]}
@@ -336,7 +341,8 @@ def main():
                    "smoother": ("S_c -> Chebyshev-Jacobi(2) -> S_c, V(2,2), adjusted lambda_max"
                                 if args.smoother == "chebyshev" else
                                 "S_c -> multicolour symmetric Gauss-Seidel -> S_c, V(2,2)"),
-                   "precision": args.precision, "patch_layers": layers, "patch_policy": policy,
+                   "problem": problem, "precision": args.precision, "patch_layers": layers,
+                   "patch_policy": policy,
                    "iterations": main_arm["iterations"][0],
                    "setup_s": round(main_arm["setup_s"], 3),
                    "true_rel_residual": main_arm["true_rel_residual"],
@@ -364,7 +370,7 @@ def main():
         line["copy_calibration_bytes"] = {"kernel": "elementwise MulFunctor", "read": src.numel() * 8,
                                           "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8, policy)
+        line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8, policy, problem)
     print(json.dumps(line), flush=True)
 
 

@@ -60,6 +60,7 @@ typedef enum {
 enum { MG_FP64 = 0, MG_MIXED = 1 };
 enum { MG_PATCH_MERGE = 0, MG_PATCH_OVERLAP = 1 };
 enum { MG_SMOOTHER_CHEBYSHEV = 0, MG_SMOOTHER_SGS = 1 };
+enum { MG_PROBLEM_POISSON = 0, MG_PROBLEM_ELASTICITY = 1 };
 
 /* One level of the hierarchy: an independent simplicial mesh of the domain. */
 typedef struct {
@@ -98,6 +99,14 @@ typedef struct {
                                greedily in canonical order, each row taking the
                                smallest colour unused by its lower-numbered
                                neighbours; no eigenvalue estimate is made      */
+  int32_t problem;          /* MG_PROBLEM_POISSON: -lap u = f (Sec. 6.1), or
+                               MG_PROBLEM_ELASTICITY: -div sigma(u) = f with
+                               sigma = 2 mu eps(u) + lambda tr(eps(u)) I
+                               (Sec. 6.2), vector Lagrange elements, unknown
+                               (scalar DOF s, component c) = s * dim + c, all
+                               components of a Dirichlet DOF clamped          */
+  double young;             /* E (elasticity; paper: 6.9e10)                   */
+  double poisson_ratio;     /* nu (elasticity; paper: 0.33), 0 <= nu < 0.5     */
 } mg_options;
 
 typedef struct {
@@ -128,6 +137,8 @@ typedef struct {
   int32_t is_coarsest;
   double setup_ms;          /* setup time spent on this level                  */
   int64_t sell_nnz16;       /* nonzeros stored with 16-bit column indices      */
+  int32_t n_components;     /* unknowns per DOF node (1; dim for elasticity):
+                               n_free = n_components * free DOF nodes          */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -139,7 +150,8 @@ enum {
   MG_ARR_PATCH_COLOUR = 5, /* int32   [n_patches]                               */
   MG_ARR_LOCATE = 6,       /* int32   [n_free] coarse cell of each free DOF node
                               (levels above the coarsest)                     */
-  MG_ARR_FREE_DOFS = 7,    /* int32   [n_free] canonical DOF id of each unknown */
+  MG_ARR_FREE_DOFS = 7,    /* int32   [n_free / n_components] canonical DOF id
+                              of each free DOF node (LOCATE likewise)        */
   MG_ARR_DOF_NODES = 8,    /* double  [n_dofs * dim] node coordinates          */
   MG_ARR_A_ROWPTR = 9,     /* int64   [n_free + 1]                              */
   MG_ARR_A_COLS = 10,      /* int32   [nnz]                                     */
@@ -156,7 +168,8 @@ enum {
 /* Fills *opt with: degree 1, MG_FP64, nu 2, cheb_degree 2, cheb_lo_frac 0.1,
  * local_correction 1, adjusted_eig 1, MG_PATCH_MERGE, eig_tol 1e-8,
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
- * global_smoother MG_SMOOTHER_CHEBYSHEV. */
+ * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
+ * young 6.9e10, poisson_ratio 0.33. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

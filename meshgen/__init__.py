@@ -446,6 +446,8 @@ CONFIGS = {
     # of 8, 4, 2 and 1 grid cells per unit (the bars are one unit thick), 400
     # degraded cells on the finest level, clamped at x = 0
     "lattice": dict(kind="lattice", sides=[48, 24, 12, 6], jitter=0.15, slivers=[400, 60, 8, 1]),
+    # the same lattice at twice the resolution (16, 8, 4, 2 cells per unit)
+    "lattice_96": dict(kind="lattice", sides=[96, 48, 24, 12], jitter=0.15, slivers=[400, 60, 8, 1]),
 }
 
 

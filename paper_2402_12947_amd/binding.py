@@ -38,7 +38,8 @@ class MgOptions(C.Structure):
                 ("local_correction", C.c_int32), ("adjusted_eig", C.c_int32),
                 ("patch_policy", C.c_int32), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32),
                 ("use_graph", C.c_int32), ("sell_sigma", C.c_int32), ("stream", C.c_void_p),
-                ("global_smoother", C.c_int32)]
+                ("global_smoother", C.c_int32), ("problem", C.c_int32), ("young", C.c_double),
+                ("poisson_ratio", C.c_double)]
 
 
 class MgSolveStats(C.Structure):
@@ -55,7 +56,7 @@ class MgLevelInfo(C.Structure):
                 ("lambda_adj", C.c_double), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
                 ("lanczos_steps", C.c_int32), ("lanczos_steps_adj", C.c_int32), ("sell_sigma", C.c_int32),
                 ("sell_stored", C.c_int64), ("is_coarsest", C.c_int32), ("setup_ms", C.c_double),
-                ("sell_nnz16", C.c_int64)]
+                ("sell_nnz16", C.c_int64), ("n_components", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -140,7 +141,8 @@ class Solver:
                  precision: str = "fp64", nu: int = 2, cheb_degree: int = 2, cheb_lo_frac: float = 0.1,
                  local_correction: bool = True, adjusted_eig: bool = True, policy: str = "merge",
                  eig_tol: float = 1e-8, eig_maxit: int = 200, use_graph: bool = False, sell_sigma: int = 0,
-                 global_smoother: str = "chebyshev"):
+                 global_smoother: str = "chebyshev", problem: str = "poisson", young: float = 6.9e10,
+                 poisson_ratio: float = 0.33):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -159,6 +161,11 @@ class Solver:
         if global_smoother not in ("chebyshev", "sgs"):
             raise ValueError("global_smoother must be 'chebyshev' or 'sgs'")
         opt.global_smoother = 1 if global_smoother == "sgs" else 0
+        if problem not in ("poisson", "elasticity"):
+            raise ValueError("problem must be 'poisson' or 'elasticity'")
+        opt.problem = 1 if problem == "elasticity" else 0
+        opt.young = young
+        opt.poisson_ratio = poisson_ratio
         keep: list = []
         arr = (MgMesh * len(meshes))(*[_mesh_struct(m, keep) for m in meshes])
         h = C.c_void_p()
@@ -202,12 +209,13 @@ class Solver:
         if what in ("p_cols", "p_vals"):
             self._check(lib().mg_get_array(self._h, level, ARR["p_width"], pw.ctypes.data))
         n, nf = info["n_cells"], info["n_free"]
+        nodes = nf // max(1, info["n_components"])   # free DOF nodes
         spec = {
             "quality": (np.float64, n), "flags": (np.uint8, n),
             "patch_ptr": (np.int32, info["n_patches"] + 1), "patch_dofs": (np.int32, info["sum_patch_dofs"]),
-            "patch_colour": (np.int32, info["n_patches"]), "locate": (np.int32, nf),
+            "patch_colour": (np.int32, info["n_patches"]), "locate": (np.int32, nodes),
             "sgs_colour": (np.int32, nf),
-            "free_dofs": (np.int32, nf), "dof_nodes": (np.float64, info["n_dofs"] * self.dim),
+            "free_dofs": (np.int32, nodes), "dof_nodes": (np.float64, info["n_dofs"] * self.dim),
             "a_rowptr": (np.int64, nf + 1), "a_cols": (np.int32, info["nnz"]), "a_vals": (np.float64, info["nnz"]),
             "p_cols": (np.int32, nf * int(pw[0])), "p_vals": (np.float64, nf * int(pw[0])),
             "cell_dofs": (np.int32, n * nloc),

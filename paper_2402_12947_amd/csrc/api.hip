@@ -273,6 +273,9 @@ void mg_default_options(mg_options *o) {
   o->use_graph = 0;
   o->sell_sigma = 0;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
+  o->problem = MG_PROBLEM_POISSON;
+  o->young = 6.9e10;
+  o->poisson_ratio = 0.33;
   o->stream = nullptr;
 }
 
@@ -316,6 +319,10 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.precision != MG_FP64 && o.precision != MG_MIXED) fail(MG_ERR_ARG, "bad precision");
     if (o.nu < 0 || o.cheb_degree < 1 || !(o.cheb_lo_frac >= 0 && o.cheb_lo_frac < 1) || o.eig_maxit < 1)
       fail(MG_ERR_ARG, "bad smoother options");
+    if (o.problem != MG_PROBLEM_POISSON && o.problem != MG_PROBLEM_ELASTICITY)
+      fail(MG_ERR_ARG, "problem must be MG_PROBLEM_POISSON or MG_PROBLEM_ELASTICITY");
+    if (o.problem == MG_PROBLEM_ELASTICITY && !(o.young > 0 && o.poisson_ratio >= 0 && o.poisson_ratio < 0.5))
+      fail(MG_ERR_ARG, "elasticity needs young > 0 and 0 <= poisson_ratio < 0.5");
     if (o.global_smoother != MG_SMOOTHER_CHEBYSHEV && o.global_smoother != MG_SMOOTHER_SGS)
       fail(MG_ERR_ARG, "global_smoother must be MG_SMOOTHER_CHEBYSHEV or MG_SMOOTHER_SGS");
     if (o.sell_sigma < 0 || (o.sell_sigma > 1 && o.sell_sigma % SELL_C))
@@ -352,6 +359,10 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       L.degree = o.degree;
       L.coarsest = (l == n_levels - 1);
       build_dofmap(c, L, levels[l]);
+      if (o.problem == MG_PROBLEM_ELASTICITY) {  // dim unknowns per DOF node
+        L.ncomp = dim;
+        L.nfree = L.nfree_s * dim;
+      }
       compute_quality(c, L);
       if (!L.coarsest) build_patches(c, L, levels[l]);
       if (l == 0) assemble_fine(c, L);
@@ -671,6 +682,7 @@ mg_status mg_rhs_from_nodal(mg_ctx *h, const double *f, double *b) {
   MG_API_BEGIN
   if (!h || !f || !b) fail(MG_ERR_ARG, "NULL argument");
   Ctx &c = h->impl;
+  if (c.opt.problem != MG_PROBLEM_POISSON) fail(MG_ERR_ARG, "b = M f_hat is provided for the Poisson problem only");
   if (c.M.nrows == 0) {
     assemble_mass(c, c.lv[0]);
     build_sell(c, c.M, c.Ms, 1, false);
@@ -707,6 +719,7 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->sell_sigma = L.S.sigma;
   o->sell_stored = L.S.stored;
   o->sell_nnz16 = L.S.nnz16;
+  o->n_components = L.ncomp;
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;
   return MG_OK;
@@ -727,8 +740,8 @@ mg_status mg_get_array(const mg_ctx *h, int32_t level, int32_t what, void *out) 
     case MG_ARR_PATCH_PTR: std::memcpy(out, L.patch.h_ptr.data(), L.patch.h_ptr.size() * 4); break;
     case MG_ARR_PATCH_DOFS: std::memcpy(out, L.patch.h_dofs.data(), L.patch.h_dofs.size() * 4); break;
     case MG_ARR_PATCH_COLOUR: std::memcpy(out, L.patch.h_colour.data(), L.patch.h_colour.size() * 4); break;
-    case MG_ARR_LOCATE: copy_out(s, L.locate.p, L.coarsest ? 0 : L.nfree, out); break;
-    case MG_ARR_FREE_DOFS: copy_out(s, L.free_dofs.p, L.nfree, out); break;
+    case MG_ARR_LOCATE: copy_out(s, L.locate.p, L.coarsest ? 0 : L.nfree_s, out); break;
+    case MG_ARR_FREE_DOFS: copy_out(s, L.free_dofs.p, L.nfree_s, out); break;
     case MG_ARR_DOF_NODES: copy_out(s, L.nodes.p, L.ndofs * L.dim, out); break;
     case MG_ARR_A_ROWPTR: copy_out(s, L.A.rowptr.p, L.nfree + 1, out); break;
     case MG_ARR_A_COLS: copy_out(s, L.A.col.p, L.A.nnz, out); break;

@@ -165,6 +165,10 @@ struct Level {
   // mesh and DOF map
   int dim = 0, degree = 0, nloc = 0;
   int64_t nv = 0, nc = 0, ne = 0, ndofs = 0, nfree = 0;
+  // unknowns per DOF node (dim for elasticity) and the number of free DOF
+  // nodes; nfree = ncomp * nfree_s counts the unknowns of the level
+  int ncomp = 1;
+  int64_t nfree_s = 0;
   DBuf<double> coords;
   DBuf<int32_t> cells;
   DBuf<uint8_t> dirv;

@@ -239,7 +239,73 @@ static void element_assembly(Ctx &c, Level &L, bool mass, Csr &A) {
   assemble_pairs(s, keys, vals, npairs, sentinel, L.nfree, (int64_t)ncols, A);
 }
 
-void assemble_fine(Ctx &c, Level &L) { element_assembly(c, L, false, L.A); }
+// Linear elasticity (Sec. 6.2): vector unknown (DOF node s, component p) =
+// s * dim + p; with int d_k phi_i d_l phi_j = |T| sum_ab g_a[k] g_b[l] Kref[a][b][i][j],
+//   K[(i,p),(j,q)] = |T| sum_ab Kref[a][b][i][j] (mu delta_pq g_a.g_b
+//                                               + mu g_a[q] g_b[p] + lambda g_a[p] g_b[q]).
+// One thread per (cell, local DOF i, component p) writes nloc * dim pairs.
+__global__ void k_element_pairs_elast(const double *X, const int32_t *cells, const int32_t *cell_dofs,
+                                      const int32_t *free_index, int64_t nc, int dim, int nloc, double mu,
+                                      double lam, uint64_t ncols, uint64_t sentinel, uint64_t *keys,
+                                      double *vals) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * nloc * dim) return;
+  int64_t c = t / (nloc * dim);
+  int ip = (int)(t - c * nloc * dim);
+  int i = ip / dim, p = ip % dim;
+  int nb = dim + 1;
+  double g[4][3];
+  double vol = simplex_grads(X, cells + c * nb, dim, g);
+  // C[q][a][b] = mu delta_pq g_a.g_b + mu g_a[q] g_b[p] + lambda g_a[p] g_b[q]
+  double C[3][4][4];
+  for (int a = 0; a < nb; ++a)
+    for (int b = 0; b < nb; ++b) {
+      double gg = 0;
+      for (int x = 0; x < dim; ++x) gg += g[a][x] * g[b][x];
+      for (int q = 0; q < dim; ++q)
+        C[q][a][b] = (q == p ? mu * gg : 0.0) + mu * g[a][q] * g[b][p] + lam * g[a][p] * g[b][q];
+    }
+  const int32_t *cd = cell_dofs + c * nloc;
+  int32_t ri = free_index[cd[i]];
+  for (int j = 0; j < nloc; ++j) {
+    int32_t cj = free_index[cd[j]];
+    for (int q = 0; q < dim; ++q) {
+      double sum = 0;
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) sum += C[q][a][b] * c_ref[((a * nb + b) * nloc + i) * nloc + j];
+      int64_t o = t * (int64_t)(nloc * dim) + j * dim + q;
+      keys[o] = (ri >= 0 && cj >= 0) ? (uint64_t)(ri * dim + p) * ncols + (uint64_t)(cj * dim + q) : sentinel;
+      vals[o] = vol * sum;
+    }
+  }
+}
+
+static void elasticity_assembly(Ctx &c, Level &L) {
+  hipStream_t s = c.stream;
+  std::vector<double> ref;
+  reference_tensor(L.dim, L.degree, false, ref);
+  MG_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_ref), ref.data(), ref.size() * sizeof(double), 0,
+                                hipMemcpyHostToDevice, s));
+  const double E = c.opt.young, nu = c.opt.poisson_ratio;
+  const double mu = E / (2.0 * (1.0 + nu)), lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const int dim = L.dim;
+  int64_t npairs = L.nc * (int64_t)(L.nloc * dim) * (L.nloc * dim);
+  uint64_t ncols = (uint64_t)L.nfree;
+  uint64_t sentinel = (uint64_t)L.nfree * ncols;
+  DBuf<uint64_t> keys;
+  DBuf<double> vals;
+  keys.alloc(npairs);
+  vals.alloc(npairs);
+  k_element_pairs_elast<<<grid_for(L.nc * L.nloc * dim, 256), 256, 0, s>>>(
+      L.coords, L.cells, L.cell_dofs, L.free_index, L.nc, dim, L.nloc, mu, lam, ncols, sentinel, keys, vals);
+  MG_LAUNCH_CHECK();
+  assemble_pairs(s, keys, vals, npairs, sentinel, L.nfree, (int64_t)ncols, L.A);
+}
+
+void assemble_fine(Ctx &c, Level &L) {
+  if (c.opt.problem == MG_PROBLEM_ELASTICITY) elasticity_assembly(c, L);
+  else element_assembly(c, L, false, L.A);
+}
 
 void assemble_mass(Ctx &c, Level &L) { element_assembly(c, L, true, c.M); }
 

@@ -245,6 +245,8 @@ void build_dofmap(Ctx &c, Level &L, const mg_mesh &m) {
   MG_LAUNCH_CHECK();
   L.nfree = exclusive_scan(s, isfree.p, scan.p, L.ndofs);
   if (L.nfree == 0) fail(MG_ERR_ARG, "level has no free DOFs");
+  L.nfree_s = L.nfree;
+  L.ncomp = 1;
   L.free_index.alloc(L.ndofs);
   L.free_dofs.alloc(L.nfree);
   k_free_maps<<<grid_for(L.ndofs, 256), 256, 0, s>>>(isfree, scan, L.ndofs, L.free_index, L.free_dofs);

@@ -172,6 +172,13 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
     pos += st.size() * L.nloc;
     std::sort(d.begin(), d.end());
     d.erase(std::unique(d.begin(), d.end()), d.end());
+    if (L.ncomp > 1) {  // every component of the patch's DOF nodes: s * ncomp + c
+      std::vector<int32_t> v;
+      v.reserve(d.size() * L.ncomp);
+      for (int32_t x : d)
+        for (int k = 0; k < L.ncomp; ++k) v.push_back(x * L.ncomp + k);
+      d.swap(v);
+    }
     if (!d.empty()) dofs.push_back(std::move(d));
   }
   // greedy colouring over shared DOFs

@@ -126,6 +126,20 @@ __global__ void k_locate(const double *fnodes, const int32_t *ffree, int64_t nf,
   }
 }
 
+// vector ELL row (i, c) = scalar row i with columns j -> j * ncomp + c
+__global__ void k_expand_ell(const int32_t *col, const double *val, int64_t nrows, int pw, int ncomp,
+                             int32_t *vcol, double *vval) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncomp * pw) return;
+  int64_t vr = t / pw;
+  int k = (int)(t - vr * pw);
+  int64_t r = vr / ncomp;
+  int cmp = (int)(vr - r * ncomp);
+  int32_t j = col[r * pw + k];
+  vcol[t] = j >= 0 ? j * ncomp + cmp : -1;
+  vval[t] = val[r * pw + k];
+}
+
 void build_prolongation(Ctx &c, Level &F, const Level &C, const mg_mesh &cm) {
   hipStream_t s = c.stream;
   const int dim = C.dim;
@@ -169,16 +183,16 @@ void build_prolongation(Ctx &c, Level &F, const Level &C, const mg_mesh &cm) {
   list.alloc(total);
   k_bucket_fill<<<grid_for(C.nc, 256), 256, 0, s>>>(C.coords, C.cells, C.nc, dim, g, off, cursor, list);
   MG_LAUNCH_CHECK();
-  // locate and evaluate the coarse basis
+  // locate and evaluate the coarse basis (per free DOF node)
   F.pw = C.nloc;
-  F.locate.alloc(F.nfree);
-  F.pcol.alloc(F.nfree * F.pw);
-  F.pval.alloc(F.nfree * F.pw);
+  F.locate.alloc(F.nfree_s);
+  F.pcol.alloc(F.nfree_s * F.pw);
+  F.pval.alloc(F.nfree_s * F.pw);
   DBuf<int> bad;
   bad.alloc(1);
   int init = 2147483647;
   MG_HIP(hipMemcpyAsync(bad.p, &init, sizeof(int), hipMemcpyHostToDevice, s));
-  k_locate<<<grid_for(F.nfree, 128), 128, 0, s>>>(F.nodes, F.free_dofs, F.nfree, C.coords, C.cells, C.cell_dofs,
+  k_locate<<<grid_for(F.nfree_s, 128), 128, 0, s>>>(F.nodes, F.free_dofs, F.nfree_s, C.coords, C.cells, C.cell_dofs,
                                                  C.free_index, dim, C.degree, C.nloc, g, off, list, F.locate,
                                                  F.pcol, F.pval, bad);
   MG_LAUNCH_CHECK();
@@ -187,6 +201,16 @@ void build_prolongation(Ctx &c, Level &F, const Level &C, const mg_mesh &cm) {
   MG_HIP(hipStreamSynchronize(s));
   if (hb != 2147483647)
     fail(MG_ERR_LOCATE, "free DOF %d of a fine level lies outside the next coarser mesh", hb);
+  if (F.ncomp > 1) {  // P (x) I: every component interpolated on its own
+    DBuf<int32_t> vc;
+    DBuf<double> vv;
+    vc.alloc(F.nfree * F.pw);
+    vv.alloc(F.nfree * F.pw);
+    k_expand_ell<<<grid_for(F.nfree * F.pw, 256), 256, 0, s>>>(F.pcol, F.pval, F.nfree_s, F.pw, F.ncomp, vc, vv);
+    MG_LAUNCH_CHECK();
+    F.pcol = std::move(vc);
+    F.pval = std::move(vv);
+  }
   ell_to_csr(c, F.nfree, C.nfree, F.pw, F.pcol, F.pval, false, F.Pc);
   ell_to_csr(c, F.nfree, C.nfree, F.pw, F.pcol, F.pval, true, F.Rc);
 }

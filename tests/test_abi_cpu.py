@@ -58,6 +58,8 @@ def test_setup_rejects_bad_input_on_host():
     assert setup_status([meshgen.cube_mesh(2, 0)], degree=3)[0] == MG_ERR_ARG
     assert setup_status([mesh], degree=4)[0] == MG_ERR_ARG
     assert setup_status([mesh, meshgen.cube_mesh(2, 0)])[0] == MG_ERR_ARG
+    assert setup_status([mesh], problem="elasticity", poisson_ratio=0.5)[0] == MG_ERR_ARG
+    assert setup_status([mesh], problem="elasticity", young=-1.0)[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_sigma=100)[0] == MG_ERR_ARG
     assert setup_status([mesh], nu=-1)[0] == MG_ERR_ARG
 

@@ -1,0 +1,106 @@
+"""GPU parity for linear elasticity (Sec. 6.2): vector P1/P2 on the 3D lattice
+and plane strain on the square, against the oracle: operators 1e-12 (fine) /
+1e-11 (Galerkin) relative, P (x) I transfers 1e-12, patch membership bit-exact,
+one sandwich and one V-cycle 1e-10, PCG iterations within one and the solution
+1e-8 (FP64) or 1e-6 (mixed, against the converged FP64 solution)."""
+import functools
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+from tests.parity_util import from_dev, rel_err, sparse_close, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (workload, scale, degree)
+    "lattice_p1": ("lattice", 2, 1),
+    "lattice_p2": ("lattice", 4, 2),
+    "square_p2_plane_strain": ("square_1025", 32, 2),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def pair(name, precision="fp64", smoother="chebyshev"):
+    from paper_2402_12947_amd import Solver
+    wl, scale, degree = CASES[name]
+    meshes = meshgen.hierarchy(wl, seed=0, scale=scale)
+    print(f"[elasticity {name} {precision} {smoother}]", flush=True)
+    gpu = Solver(meshes, degree=degree, tau=0.1, layers=1, precision=precision, problem="elasticity",
+                 global_smoother=smoother)
+    ora = None
+    if precision == "fp64":
+        ora = oracle.Hierarchy(meshes, tau=0.1, layers=1,
+                               opts=oracle.Options(degree=degree, problem="elasticity", global_smoother=smoother))
+    return gpu, ora
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operators_transfers_patches(name):
+    gpu, ora = pair(name)
+    for l, lev in enumerate(ora.levels):
+        assert gpu.level_info(l)["n_components"] == lev.dofmap.dim
+        assert sparse_close(gpu.matrix(l), lev.A, 1e-12 if l == 0 else 1e-11), f"A_{l}"
+        if l < len(ora.levels) - 1:
+            assert sparse_close(gpu.prolongation(l), lev.P, 1e-12), f"P_{l}"
+            ptr, dofs = gpu.get_array(l, "patch_ptr"), gpu.get_array(l, "patch_dofs")
+            assert len(ptr) - 1 == len(lev.patch_dofs)
+            for d, B in enumerate(lev.patch_dofs):
+                assert np.array_equal(dofs[ptr[d]:ptr[d + 1]], B)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_smoother_vcycle_pcg(name):
+    gpu, ora = pair(name)
+    n = ora.levels[0].A.shape[0]
+    b, u0 = meshgen.random_rhs(n, 1), meshgen.random_rhs(n, 2)
+    u = to_dev(u0)
+    gpu.smooth(0, to_dev(b), u, 1)
+    assert rel_err(from_dev(u), ora.smooth(0, b, u0.copy(), 1)) < 1e-10
+    u = to_dev(u0)
+    gpu.vcycle(to_dev(b), u)
+    assert rel_err(from_dev(u), ora.vcycle(b, u0.copy())) < 1e-10
+    x_o, it_o, conv_o, _ = ora.pcg(b, 1e-10, 300)
+    u = to_dev(np.zeros(n))
+    st = gpu.pcg(to_dev(b), u, 1e-10, 300)
+    assert conv_o and st["converged"] and abs(st["iterations"] - it_o) <= 1
+    assert rel_err(from_dev(u), x_o) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["lattice_p1", "lattice_p2"])
+def test_mixed_precision(name):
+    _, ora = pair(name)
+    gmix, _ = pair(name, "mixed")
+    n = ora.levels[0].A.shape[0]
+    b = meshgen.random_rhs(n, 6)
+    x_ref, _, _, _ = ora.pcg(b, 1e-12, 300)
+    _, it_o, _, _ = ora.pcg(b, 1e-8, 300)
+    u = to_dev(np.zeros(n))
+    st = gmix.pcg(to_dev(b), u, 1e-8, 300)
+    assert st["converged"] and abs(st["iterations"] - it_o) <= 1
+    assert rel_err(from_dev(u), x_ref) < 1e-6
+
+
+def test_sgs_global_smoother():
+    """The paper's lattice runs use symmetric Gauss-Seidel as S_g."""
+    gpu, ora = pair("lattice_p1", "fp64", "sgs")
+    n = ora.levels[0].A.shape[0]
+    b = meshgen.random_rhs(n, 3)
+    u0 = meshgen.random_rhs(n, 4)
+    u = to_dev(u0)
+    gpu.vcycle(to_dev(b), u)
+    assert rel_err(from_dev(u), ora.vcycle(b, u0.copy())) < 1e-10
+    _, it_o, conv_o, _ = ora.pcg(b, 1e-8, 300)
+    st = gpu.pcg(to_dev(b), to_dev(np.zeros(n)), 1e-8, 300)
+    assert conv_o and st["converged"] and abs(st["iterations"] - it_o) <= 1
+
+
+def test_rhs_from_nodal_is_poisson_only():
+    from paper_2402_12947_amd import MG_ERR_ARG, MgError
+    gpu, ora = pair("lattice_p1")
+    n = ora.levels[0].A.shape[0]
+    with pytest.raises(MgError) as e:
+        gpu.rhs_from_nodal(to_dev(np.zeros(n)), to_dev(np.zeros(n)))
+    assert e.value.code == MG_ERR_ARG
