@@ -207,6 +207,22 @@ mg_status mg_vcycle(mg_ctx *c, const double *b, double *u);
 mg_status mg_pcg_solve(mg_ctx *c, const double *b, double *u, double rtol, int32_t maxit,
                        mg_solve_stats *st);
 
+/* Several right-hand sides of one operator (the block form of mg_pcg_solve):
+ * solves A_0 u[r] = b[r], r < nrhs, each column with exactly the method,
+ * scalars and stopping rule of mg_pcg_solve, but advanced together in blocks
+ * of up to 4 columns whose vectors are interleaved, so that every operator
+ * stream of the cycle (the smoothers' sparse products, residuals, transfers,
+ * patch rows) and of CG is read once per block instead of once per column.
+ * A column that has converged keeps its iterate while the others go on.
+ * b[r], u[r]: device FP64 vectors of n_free(0); no u[r] may alias another
+ * vector.  st (may be NULL) receives nrhs records; solve_ms is the time of the
+ * block the column ran in.  Results agree with column-by-column mg_pcg_solve
+ * to rounding (the order of a few sums differs).  Returns MG_NOT_CONVERGED if
+ * any column did not converge in maxit iterations, MG_ERR_BREAKDOWN if one
+ * broke down. */
+mg_status mg_pcg_solve_multi(mg_ctx *c, int32_t nrhs, const double *const *b, double *const *u, double rtol,
+                             int32_t maxit, mg_solve_stats *st);
+
 /* Multigrid as a stationary solver (Sec. 2, Algorithm alg:mg repeated; the
  * Poisson experiments of Sec. 6.1): from u = 0, u <- Vcycle(A_0, b, u) until
  * ||b - A u||_2 <= rtol ||b||_2 (the residual recomputed after every cycle) or
@@ -222,7 +238,8 @@ mg_status mg_vcycle_solve(mg_ctx *c, const double *b, double *u, double rtol, in
  * with the same method and stopping rule as mg_pcg_solve.  b[i * nrhs + r] and
  * u[i * nrhs + r] are device FP64 vectors of instance i's n_free.  Every
  * instance runs on its own context stream from its own host thread, so the
- * instances' kernels overlap on the GPU; contexts created with use_graph = 1
+ * instances' kernels overlap on the GPU, and solves its right-hand sides as
+ * block solves (mg_pcg_solve_multi); contexts created with use_graph = 1
  * replay their V-cycles from captured hipGraphs.  The contexts must be
  * distinct.  st (may be NULL) receives n_inst * nrhs records; *wall_ms (may be
  * NULL) the wall time of the whole batch.  Returns the first error of the

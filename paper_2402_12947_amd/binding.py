@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mg_vcycle": (C.c_int, [P, P, P]),
         "mg_pcg_solve": (C.c_int, [P, P, P, C.c_double, C.c_int32, C.POINTER(MgSolveStats)]),
         "mg_vcycle_solve": (C.c_int, [P, P, P, C.c_double, C.c_int32, C.POINTER(MgSolveStats)]),
+        "mg_pcg_solve_multi": (C.c_int, [P, C.c_int32, C.POINTER(P), C.POINTER(P), C.c_double, C.c_int32,
+                                         C.POINTER(MgSolveStats)]),
         "mg_rhs_from_nodal": (C.c_int, [P, P, P]),
         "mg_pcg_solve_batch": (C.c_int, [C.POINTER(P), C.c_int32, C.c_int32, C.POINTER(P), C.POINTER(P),
                                          C.c_double, C.c_int32, C.POINTER(MgSolveStats), C.POINTER(C.c_double)]),
@@ -263,6 +265,24 @@ class Solver:
         return {"status": code, "iterations": st.iterations, "converged": bool(st.converged),
                 "rel_residual": st.rel_residual, "true_rel_residual": st.true_rel_residual,
                 "solve_ms": st.solve_ms, "history": list(st.history[:st.n_history])}
+
+    def pcg_multi(self, bs: list, us: list, rtol: float = 1e-8, maxit: int = 500) -> dict:
+        """mg_pcg_solve_multi: the right-hand sides bs[r] (device float64
+        tensors) solved together in blocks; us[r] receive the solutions.
+        Returns the status and one statistics record per right-hand side."""
+        if len(bs) != len(us):
+            raise ValueError("bs and us must have the same length")
+        n = len(bs)
+        _sync()
+        pb = (C.c_void_p * max(1, n))(*[_ptr(t) for t in bs])
+        pu = (C.c_void_p * max(1, n))(*[_ptr(t) for t in us])
+        st = (MgSolveStats * max(1, n))()
+        code = self._check(lib().mg_pcg_solve_multi(self._h, n, pb, pu, rtol, maxit, st),
+                           allow=(MG_OK, MG_NOT_CONVERGED))
+        stats = [{"iterations": x.iterations, "converged": bool(x.converged), "rel_residual": x.rel_residual,
+                  "true_rel_residual": x.true_rel_residual, "solve_ms": x.solve_ms,
+                  "history": list(x.history[:x.n_history])} for x in st[:n]]
+        return {"status": code, "stats": stats}
 
     def mg_solve(self, b, u, rtol: float = 1e-8, maxit: int = 100) -> dict:
         """Multigrid as a stationary solver: V-cycles from u = 0 until the

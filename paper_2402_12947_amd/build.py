@@ -17,11 +17,11 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmgpcg.so")
 SOURCES = ["api.hip", "solve.hip", "setup_mesh.hip", "setup_assembly.hip", "setup_transfer.hip",
            "setup_galerkin.hip", "setup_patches.hip", "setup_dense.hip", "setup_patchfactor.hip",
-           "setup_eigen.hip"]
+           "setup_eigen.hip", "solve_block.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
-         # packed FP32 instructions are not generated (toolchain notes)
+         # no packed FP32 instructions: some of their forms have given wrong results on this target
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function",
          "-Wno-unused-variable", "-Wno-unused-result"]

@@ -27,6 +27,10 @@ void fail(mg_status code, const char *fmt, ...) {
 Ctx::~Ctx() {
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
+  for (int k = 0; k < 5; ++k) {
+    if (kgraph_exec[k]) (void)hipGraphExecDestroy(kgraph_exec[k]);
+    if (kgraph[k]) (void)hipGraphDestroy(kgraph[k]);
+  }
   for (auto &e : events) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -224,6 +228,273 @@ static void dot_to(Ctx &c, const double *x, const double *y, int64_t n, double *
   finish_sum(c.stream, c.partial, nb, out);
 }
 
+// ---------------------------------------------------------------------------
+// block solve: K right-hand sides of the same operator advanced together
+// (block vectors, unknown i of column q at i K + q).  The cycle is the
+// single-vector cycle above, column by column; the operator streams
+// (smoother, residual, transfers, patch rows) are shared by the K columns,
+// the dense patch and coarsest products run once per column.
+// ---------------------------------------------------------------------------
+template <class T>
+struct LB;
+template <>
+struct LB<double> {
+  static double *w(Level &L, int k) { return L.bw64[k].p; }
+  static double *res(Level &L) { return L.bres64.p; }
+};
+template <>
+struct LB<float> {
+  static float *w(Level &L, int k) { return L.bw32[k].p; }
+  static float *res(Level &L) { return L.bres32.p; }
+};
+
+static void ensure_block_work(Ctx &c) {
+  if (c.kr.p) return;
+  const bool mixed = c.opt.precision == MG_MIXED;
+  for (Level &L : c.lv) {
+    const int64_t n = L.nfree * MG_BLOCK_MAX;
+    for (int k = 0; k < 6; ++k) {
+      if (mixed) L.bw32[k].alloc(n); else L.bw64[k].alloc(n);
+    }
+    if (L.patch.total > 0) {
+      if (mixed) L.bres32.alloc(L.patch.total * MG_BLOCK_MAX);
+      else L.bres64.alloc(L.patch.total * MG_BLOCK_MAX);
+    }
+  }
+  const int64_t n0 = c.lv[0].nfree * MG_BLOCK_MAX;
+  c.kz.alloc(n0);
+  c.kp.alloc(n0);
+  c.kq.alloc(n0);
+  c.kx.alloc(n0);
+  c.kb.alloc(n0);
+  const int64_t pb = std::max<int64_t>(1024, spmv_dot_blocks(c.lv[0].S));
+  c.kpartial.alloc(pb * MG_BLOCK_MAX);
+  c.kr.alloc(n0);  // last: marks the block work as allocated
+}
+
+template <class T>
+static void local_correction_block(Ctx &c, Level &L, int K, const T *b, T *u, bool descending) {
+  T *res = LB<T>::res(L);
+  for (int k = 0; k < L.patch.ncolour; ++k) {
+    int col = descending ? L.patch.ncolour - 1 - k : k;
+    patch_residual_block<T>(c.stream, L.patch, col, K, b, u, res);
+    for (int q = 0; q < K; ++q)
+      patch_apply<T>(c.stream, L.patch, col, res + q, LV<T>::py(L), LV<T>::pz(L), u + q, K);
+  }
+}
+
+template <class T>
+static void chebyshev_block(Ctx &c, int l, int K, const T *b, T *&u, T *&alt) {
+  Level &L = c.lv[l];
+  const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  T *d = LB<T>::w(L, W_D);
+  const int k = c.opt.cheb_degree;
+  cheb_step_block<T>(c.stream, L.S, K, LV<T>::dinv(L), b, u, alt, d, k == 1 ? 3 : 1, 0.0, 1.0 / theta);
+  std::swap(u, alt);
+  for (int j = 1; j < k; ++j) {
+    double rho_new = 1.0 / (2.0 * sigma - rho);
+    cheb_step_block<T>(c.stream, L.S, K, LV<T>::dinv(L), b, u, alt, d, j == k - 1 ? 2 : 0, rho_new * rho,
+                       2.0 * rho_new / delta);
+    std::swap(u, alt);
+    rho = rho_new;
+  }
+}
+
+template <class T>
+static void smooth_block(Ctx &c, int l, int K, const T *b, T *u, int nu) {
+  Level &L = c.lv[l];
+  bool local = c.opt.local_correction && L.patch.n > 0;
+  T *cur = u, *alt = LB<T>::w(L, W_ALT);
+  if (u == alt) alt = LB<T>::w(L, W_T);
+  for (int s = 0; s < nu; ++s) {
+    if (local) local_correction_block<T>(c, L, K, b, cur, false);
+    if (c.opt.global_smoother == MG_SMOOTHER_SGS) {
+      const int nc = (int)L.sgs.size();
+      for (int k = 0; k < nc; ++k)
+        sgs_colour_sweep_block<T>(c.stream, L.sgs[k], K, L.sgs_pos[k], LV<T>::dinv(L), b, cur);
+      for (int k = nc - 1; k >= 0; --k)
+        sgs_colour_sweep_block<T>(c.stream, L.sgs[k], K, L.sgs_pos[k], LV<T>::dinv(L), b, cur);
+    } else {
+      chebyshev_block<T>(c, l, K, b, cur, alt);
+    }
+    if (local) local_correction_block<T>(c, L, K, b, cur, true);
+  }
+  if (cur != u) convert<T, T>(c.stream, cur, u, L.nfree * K);
+}
+
+template <class T>
+static void vcycle_zero_block(Ctx &c, int l, int K, const T *b, T *u) {
+  Level &L = c.lv[l];
+  if (L.coarsest) {
+    for (int q = 0; q < K; ++q) coarse_apply<T>(c.stream, L, b + q, u + q, K);
+    return;
+  }
+  fill<T>(c.stream, u, L.nfree * K, T(0));
+  smooth_block<T>(c, l, K, b, u, c.opt.nu);
+  T *r = LB<T>::w(L, W_R);
+  sell_spmv_block<T>(c.stream, L.S, K, u, r, SPMV_RESID, b);
+  Level &C = c.lv[l + 1];
+  sell_spmv_block<T>(c.stream, L.R, K, r, LB<T>::w(C, W_B), SPMV_SET, nullptr);
+  vcycle_zero_block<T>(c, l + 1, K, LB<T>::w(C, W_B), LB<T>::w(C, W_U));
+  sell_spmv_block<T>(c.stream, L.P, K, LB<T>::w(C, W_U), u, SPMV_ADD, nullptr);
+  smooth_block<T>(c, l, K, b, u, c.opt.nu);
+}
+
+// c.kz = B c.kr for K columns (FP64 in and out; mixed runs the cycle in FP32)
+static void precondition_block_eager(Ctx &c, int K) {
+  Level &L0 = c.lv[0];
+  const int64_t n = L0.nfree * K;
+  if (c.opt.precision == MG_MIXED) {
+    convert<double, float>(c.stream, c.kr, L0.bw32[W_B], n);
+    vcycle_zero_block<float>(c, 0, K, L0.bw32[W_B], L0.bw32[W_U]);
+    convert<float, double>(c.stream, L0.bw32[W_U], c.kz, n);
+  } else {
+    vcycle_zero_block<double>(c, 0, K, c.kr, c.kz);
+  }
+}
+
+static void precondition_block(Ctx &c, int K) {
+  if (!c.opt.use_graph) {
+    precondition_block_eager(c, K);
+    return;
+  }
+  if (!c.kgraph_exec[K]) {
+    MG_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      precondition_block_eager(c, K);
+    } catch (...) {
+      hipGraph_t g;
+      (void)hipStreamEndCapture(c.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    MG_HIP(hipStreamEndCapture(c.stream, &c.kgraph[K]));
+    MG_HIP(hipGraphInstantiate(&c.kgraph_exec[K], c.kgraph[K], nullptr, nullptr, 0));
+  }
+  MG_HIP(hipGraphLaunch(c.kgraph_exec[K], c.stream));
+}
+
+static void dot_block_to(Ctx &c, int K, const double *x, const double *y, int64_t n, double *out) {
+  const int nb = dot_blocks(n);
+  dot_partials_block(c.stream, K, x, y, n, c.kpartial, nb);
+  finish_sum_block(c.stream, K, c.kpartial, nb, out);
+}
+
+// CG on K columns in lockstep (K in {2, 4}; ncols <= K real columns, the rest
+// zero).  Each column is the single-vector CG of mg_pcg_solve with its own
+// scalars; a converged column is frozen (alpha = 0) while the others go on.
+// Returns whether every real column converged.
+static bool pcg_block(Ctx &c, int K, int ncols, const double *const *b, double *const *u, double rtol, int maxit,
+                      mg_solve_stats *st) {
+  Level &L0 = c.lv[0];
+  const int64_t n = L0.nfree;
+  hipStream_t s = c.stream;
+  ensure_block_work(c);
+  const double *bc[MG_BLOCK_MAX] = {};
+  double *uc[MG_BLOCK_MAX] = {};
+  for (int q = 0; q < ncols; ++q) {
+    bc[q] = b[q];
+    uc[q] = u[q];
+  }
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } guard{e0, e1};
+  MG_HIP(hipEventRecord(e0, s));
+  double *scal = c.scal.p;
+  double *h = c.h_scal;
+  fill<double>(s, scal, 8 * K, 0.0);
+  fill<double>(s, c.kx.p, n * K, 0.0);
+  gather_block(s, K, bc, L0.perm, c.kb, n);
+  copy64(s, c.kb, c.kr, n * K);
+  dot_block_to(c, K, c.kb, c.kb, n, scal + 7 * K);
+  MG_HIP(hipMemcpyAsync(h, scal + 7 * K, K * sizeof(double), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  double bnorm[MG_BLOCK_MAX], rel[MG_BLOCK_MAX];
+  int iters[MG_BLOCK_MAX] = {};
+  bool conv[MG_BLOCK_MAX] = {};
+  std::vector<double> hist[MG_BLOCK_MAX];
+  unsigned mask = 0;
+  for (int q = 0; q < K; ++q) {
+    bnorm[q] = std::sqrt(h[q]);
+    rel[q] = bnorm[q] > 0 ? 1.0 : 0.0;
+    hist[q].push_back(rel[q]);
+    conv[q] = bnorm[q] == 0.0;
+    if (!conv[q]) mask |= 1u << q;
+  }
+  int it = 0, broken = -1;
+  if (mask) {
+    precondition_block(c, K);
+    copy64(s, c.kz, c.kp, n * K);
+    dot_block_to(c, K, c.kr, c.kz, n, scal + 0);
+    const int nb = dot_blocks(n);
+    const int sb = spmv_dot_blocks(L0.S);
+    while (it < maxit) {
+      spmv_dot_block(s, L0.S, K, c.kp, c.kq, c.kpartial);
+      finish_sum_block(s, K, c.kpartial, sb, scal + K);
+      cg_alpha_block(s, K, mask, scal);
+      cg_update_xr_block(s, K, c.kx, c.kr, c.kp, c.kq, scal, n, c.kpartial, nb);
+      finish_sum_block(s, K, c.kpartial, nb, scal + 3 * K);
+      MG_HIP(hipMemcpyAsync(h, scal, 8 * K * sizeof(double), hipMemcpyDeviceToHost, s));
+      MG_HIP(hipStreamSynchronize(s));
+      ++it;
+      for (int q = 0; q < K; ++q) {
+        if (!((mask >> q) & 1u)) continue;
+        const double rr = h[3 * K + q];
+        if (h[6 * K + q] != 0.0 || !std::isfinite(rr)) {
+          broken = q;
+          break;
+        }
+        rel[q] = std::sqrt(rr) / bnorm[q];
+        hist[q].push_back(rel[q]);
+        iters[q] = it;
+        if (rel[q] <= rtol) {
+          conv[q] = true;
+          mask &= ~(1u << q);
+        }
+      }
+      if (broken >= 0 || !mask) break;
+      precondition_block(c, K);
+      dot_block_to(c, K, c.kr, c.kz, n, scal + 4 * K);
+      cg_beta_block(s, K, mask, scal);
+      cg_update_p_block(s, K, c.kp, c.kz, scal, n);
+    }
+  }
+  scatter_block(s, K, c.kx, L0.perm, uc, n);
+  MG_HIP(hipEventRecord(e1, s));
+  MG_HIP(hipEventSynchronize(e1));
+  float tms = 0;
+  MG_HIP(hipEventElapsedTime(&tms, e0, e1));
+  // true residuals in FP64
+  sell_spmv_block<double>(s, L0.S, K, c.kx, c.kq, SPMV_RESID, c.kb);
+  dot_block_to(c, K, c.kq, c.kq, n, scal + 7 * K);
+  MG_HIP(hipMemcpyAsync(h, scal + 7 * K, K * sizeof(double), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  if (st) {
+    for (int q = 0; q < ncols; ++q) {
+      mg_solve_stats &o = st[q];
+      std::memset(&o, 0, sizeof(o));
+      o.iterations = iters[q];
+      o.converged = conv[q] ? 1 : 0;
+      o.rel_residual = rel[q];
+      o.true_rel_residual = bnorm[q] > 0 ? std::sqrt(h[q]) / bnorm[q] : 0.0;
+      o.solve_ms = tms;
+      o.n_history = (int32_t)std::min<size_t>(hist[q].size(), MG_MAX_HISTORY);
+      for (int k = 0; k < o.n_history; ++k) o.history[k] = hist[q][k];
+    }
+  }
+  if (broken >= 0)
+    fail(MG_ERR_BREAKDOWN, "CG breakdown in column %d at iteration %d (p.Ap <= 0 or a non-finite value)", broken, it);
+  bool all = true;
+  for (int q = 0; q < ncols; ++q) all &= conv[q];
+  return all;
+}
+
 }  // namespace mg
 
 using namespace mg;
@@ -416,8 +687,8 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     c.xpos.alloc(n0);
     int64_t pb = std::max<int64_t>(1024, spmv_dot_blocks(c.lv[0].S));
     c.partial.alloc(pb);
-    c.scal.alloc(8);
-    MG_HIP(hipHostMalloc((void **)&c.h_scal, 8 * sizeof(double), hipHostMallocDefault));
+    c.scal.alloc(8 * MG_BLOCK_MAX);
+    MG_HIP(hipHostMalloc((void **)&c.h_scal, 8 * MG_BLOCK_MAX * sizeof(double), hipHostMallocDefault));
     MG_HIP(hipStreamSynchronize(c.stream));
     *out = h;
     return MG_OK;
@@ -568,6 +839,38 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
   MG_API_END(cp)
 }
 
+mg_status mg_pcg_solve_multi(mg_ctx *h, int32_t nrhs, const double *const *b, double *const *u, double rtol,
+                             int32_t maxit, mg_solve_stats *st) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || nrhs < 0 || (nrhs > 0 && (!b || !u))) fail(MG_ERR_ARG, "NULL argument or negative count");
+  Ctx &c = h->impl;
+  if (maxit < 0 || !(rtol >= 0)) fail(MG_ERR_ARG, "bad rtol or maxit");
+  for (int i = 0; i < nrhs; ++i) {
+    if (!b[i] || !u[i]) fail(MG_ERR_ARG, "NULL vector of right-hand side %d", i);
+    for (int j = 0; j < nrhs; ++j)
+      if (u[i] == b[j] || (j < i && u[i] == u[j])) fail(MG_ERR_ARG, "solution %d aliases another vector", i);
+  }
+  // groups of 4 columns; a remainder of 3 is padded with a zero column, 2
+  // runs as a block of two and 1 as a single-vector solve
+  bool not_conv = false;
+  for (int i = 0; i < nrhs;) {
+    const int left = nrhs - i;
+    if (left == 1) {
+      mg_status code = mg_pcg_solve(h, b[i], u[i], rtol, maxit, st ? st + i : nullptr);
+      if (code < 0) return code;
+      not_conv |= code == MG_NOT_CONVERGED;
+      i += 1;
+      continue;
+    }
+    const int K = left == 2 ? 2 : 4, ncols = std::min(left, K);
+    not_conv |= !pcg_block(c, K, ncols, b + i, u + i, rtol, maxit, st ? st + i : nullptr);
+    i += ncols;
+  }
+  return not_conv ? MG_NOT_CONVERGED : MG_OK;
+  MG_API_END(cp)
+}
+
 mg_status mg_vcycle_solve(mg_ctx *h, const double *b, double *u, double rtol, int32_t maxit, mg_solve_stats *st) {
   Ctx *cp = h ? &h->impl : nullptr;
   MG_API_BEGIN
@@ -653,16 +956,11 @@ mg_status mg_pcg_solve_batch(mg_ctx *const *cs, int32_t n_inst, int32_t nrhs, co
   }
   std::vector<mg_status> status(n_inst, MG_OK);
   auto t0 = std::chrono::steady_clock::now();
+  // one host thread per instance (each context has its own stream); the
+  // right-hand sides of an instance run as block solves
   auto work = [&](int i) {
-    for (int r = 0; r < nrhs; ++r) {
-      int k = i * nrhs + r;
-      mg_status code = mg_pcg_solve(cs[i], b[k], u[k], rtol, maxit, st ? st + k : nullptr);
-      if (code < 0) {
-        status[i] = code;
-        return;
-      }
-      if (code == MG_NOT_CONVERGED) status[i] = MG_NOT_CONVERGED;
-    }
+    const int64_t k = (int64_t)i * nrhs;
+    status[i] = mg_pcg_solve_multi(cs[i], nrhs, b + k, u + k, rtol, maxit, st ? st + k : nullptr);
   };
   std::vector<std::thread> threads;
   threads.reserve(n_inst);

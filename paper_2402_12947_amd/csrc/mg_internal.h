@@ -219,6 +219,12 @@ struct Level {
   DBuf<float> res32;
   DBuf<double> py64, pz64;     // patch apply partial products [inv.ysize], [inv.zsize]
   DBuf<float> py32, pz32;
+  // the same for block solves: MG_BLOCK_MAX interleaved columns, allocated on
+  // the first block solve
+  DBuf<double> bw64[6];
+  DBuf<float> bw32[6];
+  DBuf<double> bres64;
+  DBuf<float> bres32;
   double setup_ms = 0;
 };
 
@@ -247,8 +253,17 @@ struct Ctx {
   // captured V-cycle graph
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
+  // block CG work (FP64, level 0, solve order, MG_BLOCK_MAX interleaved
+  // columns; allocated on the first block solve) and the block V-cycle
+  // graphs (index: block width)
+  DBuf<double> kr, kz, kp, kq, kx, kb, kpartial;
+  hipGraphExec_t kgraph_exec[5] = {};
+  hipGraph_t kgraph[5] = {};
   ~Ctx();
 };
+
+// right-hand sides advanced together by one block solve
+constexpr int MG_BLOCK_MAX = 4;
 
 // ---------------------------------------------------------------------------
 // setup stages (setup_*.hip)
@@ -289,10 +304,12 @@ void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T 
 
 template <class T>
 void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, const T *u, T *res);
+// res, b and u are read and written at stride vs (one column of a block vector
+// when vs > 1)
 template <class T>
-void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u);
+void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u, int vs = 1);
 template <class T>
-void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u);
+void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u, int vs = 1);
 template <class T>
 void sgs_colour_sweep(hipStream_t s, const Sell &S, const int32_t *pos, const T *dinv, const T *b, T *u);
 
@@ -316,6 +333,33 @@ void dot_partials(hipStream_t s, const double *x, const double *y, int64_t n, do
                   int nblocks);
 int dot_blocks(int64_t n);
 void finish_sum(hipStream_t s, const double *part, int nblocks, double *out);
+
+// ---------------------------------------------------------------------------
+// block solve kernels (solve_block.hip): K in {2, 4} columns interleaved,
+// unknown i of column q at index i K + q
+// ---------------------------------------------------------------------------
+template <class T>
+void sell_spmv_block(hipStream_t s, const Sell &S, int K, const T *x, T *y, int mode, const T *b);
+template <class T>
+void cheb_step_block(hipStream_t s, const Sell &S, int K, const T *dinv, const T *b, const T *x, T *xout, T *d,
+                     int flags, double c_d, double c_r);
+template <class T>
+void sgs_colour_sweep_block(hipStream_t s, const Sell &S, int K, const int32_t *pos, const T *dinv, const T *b,
+                            T *u);
+template <class T>
+void patch_residual_block(hipStream_t s, const Patches &pt, int colour, int K, const T *b, const T *u, T *res);
+void spmv_dot_block(hipStream_t s, const Sell &S, int K, const double *p, double *q, double *part);
+void dot_partials_block(hipStream_t s, int K, const double *x, const double *y, int64_t n, double *part,
+                        int nblocks);
+void finish_sum_block(hipStream_t s, int K, const double *part, int nblocks, double *out);
+void cg_alpha_block(hipStream_t s, int K, unsigned mask, double *scal);
+void cg_update_xr_block(hipStream_t s, int K, double *x, double *r, const double *p, const double *q,
+                        const double *scal, int64_t n, double *part, int nblocks);
+void cg_beta_block(hipStream_t s, int K, unsigned mask, double *scal);
+void cg_update_p_block(hipStream_t s, int K, double *p, const double *z, const double *scal, int64_t n);
+// cols: host array of K device pointers (canonical order; NULL = zero column)
+void gather_block(hipStream_t s, int K, const double *const *cols, const int32_t *perm, double *y, int64_t n);
+void scatter_block(hipStream_t s, int K, const double *y, const int32_t *perm, double *const *cols, int64_t n);
 
 // CG helpers working on device scalars
 void cg_alpha(hipStream_t s, double *scal);

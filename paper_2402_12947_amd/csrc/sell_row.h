@@ -1,0 +1,179 @@
+// Device helpers shared by the single-vector and the block (several
+// right-hand sides) solve kernels: SELL-C row products, the wavefront LDS
+// ordering and the deterministic block reduction.
+#pragma once
+
+#include "mg_internal.h"
+
+namespace mg {
+
+// Column arrays of a SELL matrix as the solve kernels read them.
+struct SellCols {
+  const int64_t *sptr;
+  const int32_t *col;
+  const uint16_t *col16;
+  const int32_t *cbase;
+  const int32_t *ctab;
+};
+static inline SellCols cols_of(const Sell &S) {
+  return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p, S.ctab.p};
+}
+
+// Row `lane` of slice `sl` (sl is the same for the whole wavefront): the matrix
+// entries are streamed once per product, so they are loaded non-temporally and
+// leave the cache to the gathered vector; slices whose columns fit two windows
+// of 32768 read 16-bit columns.
+template <int U, class T, class C, class F>
+__device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
+                             F decode) {
+  // U independent gathers in flight per lane
+  T a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = 0;
+  int j = 0;
+  for (; j + U - 1 < w; j += U) {
+    int c[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = decode(__builtin_nontemporal_load(cp + (j + u) * 64));
+      v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] += v[u] * x[c[u]];
+  }
+  for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[decode(__builtin_nontemporal_load(cp + j * 64))];
+  T s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  if (U == 16) s += ((a[8] + a[9]) + (a[10] + a[11])) + ((a[12] + a[13]) + (a[14] + a[15]));
+  return s;
+}
+
+template <class T, int U = 8>
+__device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
+                             int lane) {
+  static_assert(U == 8 || U == 16, "8 or 16 gathers in flight");
+  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
+  const int64_t base = S.sptr[s32];
+  const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
+  const T *vp = val + base + lane;
+  const int b0 = S.cbase[2 * s32];
+  if (b0 >= 0) {
+    const int bh = S.cbase[2 * s32 + 1] - 0x8000;
+    return sell_dot<U>(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
+  }
+  if (b0 < -1) {
+    // window bases in lanes 0..15, picked per entry by a cross-lane read
+    const int tb = S.ctab[16 * (int64_t)s32 + (lane & 15)];
+    const int shift = b0 == -2 ? 13 : 12;
+    const int mask = (1 << shift) - 1;
+    return sell_dot<U>(S.col16 + base + lane, vp, x, w,
+                       [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); });
+  }
+  return sell_dot<U>(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; });
+}
+
+// the value array of the cycle's precision
+template <class T>
+static inline const T *sell_vals(const Sell &S) {
+  if constexpr (std::is_same<T, double>::value) return S.v64.p;
+  else return S.v32.p;
+}
+
+static inline unsigned sell_grid(const Sell &S) { return (unsigned)((S.nslices * 64 + 255) / 256); }
+
+// K values of one unknown in a block vector: the K right-hand sides of a
+// block solve are interleaved, unknown i holding entries i K .. i K + K - 1,
+// so one gather fetches all K columns (8 to 32 bytes).
+template <class T, int K>
+struct alignas(sizeof(T) * K) BlockRow {
+  T v[K];
+};
+
+// Row `lane` of a slice times K interleaved vectors: every matrix entry is
+// read once and used K times.  U gathers in flight per lane (4 when a gather
+// is 32 bytes, to bound the registers of the K U accumulators).
+template <int U, int K, class T, class C, class F>
+__device__ inline void sell_dot_k(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
+                                  F decode, T (&out)[K]) {
+  using R = BlockRow<T, K>;
+  const R *__restrict__ xr = reinterpret_cast<const R *>(x);
+  T a[U][K];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int q = 0; q < K; ++q) a[u][q] = 0;
+  int j = 0;
+  for (; j + U - 1 < w; j += U) {
+    int c[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = decode(__builtin_nontemporal_load(cp + (j + u) * 64));
+      v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const R xv = xr[c[u]];
+#pragma unroll
+      for (int q = 0; q < K; ++q) a[u][q] += v[u] * xv.v[q];
+    }
+  }
+  for (; j < w; ++j) {
+    const T v = __builtin_nontemporal_load(vp + j * 64);
+    const R xv = xr[decode(__builtin_nontemporal_load(cp + j * 64))];
+#pragma unroll
+    for (int q = 0; q < K; ++q) a[0][q] += v * xv.v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    T s = (a[0][q] + a[1][q]) + (a[2][q] + a[3][q]);
+    if constexpr (U == 8) s += (a[4][q] + a[5][q]) + (a[6][q] + a[7][q]);
+    out[q] = s;
+  }
+}
+
+template <class T, int K>
+__device__ inline void sell_row_k(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
+                                  int lane, T (&out)[K]) {
+  constexpr int U = sizeof(T) * K > 16 ? 4 : 8;
+  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
+  const int64_t base = S.sptr[s32];
+  const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
+  const T *vp = val + base + lane;
+  const int b0 = S.cbase[2 * s32];
+  if (b0 >= 0) {
+    const int bh = S.cbase[2 * s32 + 1] - 0x8000;
+    sell_dot_k<U, K>(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; },
+                     out);
+  } else if (b0 < -1) {
+    const int tb = S.ctab[16 * (int64_t)s32 + (lane & 15)];
+    const int shift = b0 == -2 ? 13 : 12;
+    const int mask = (1 << shift) - 1;
+    sell_dot_k<U, K>(S.col16 + base + lane, vp, x, w,
+                     [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); }, out);
+  } else {
+    sell_dot_k<U, K>(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; }, out);
+  }
+}
+
+// Orders this wavefront's LDS accesses (writes before reads of other lanes).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double block_sum(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace mg

@@ -16,73 +16,9 @@
 // * Coarsest level: dense product with the precomputed inverse (FP64).
 // * CG vector updates and deterministic two-stage inner products.
 #include "mg_internal.h"
+#include "sell_row.h"
 
 namespace mg {
-
-// Column arrays of a SELL matrix as the solve kernels read them.
-struct SellCols {
-  const int64_t *sptr;
-  const int32_t *col;
-  const uint16_t *col16;
-  const int32_t *cbase;
-  const int32_t *ctab;
-};
-static inline SellCols cols_of(const Sell &S) {
-  return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p, S.ctab.p};
-}
-
-// Row `lane` of slice `sl` (sl is the same for the whole wavefront): the matrix
-// entries are streamed once per product, so they are loaded non-temporally and
-// leave the cache to the gathered vector; slices whose columns fit two windows
-// of 32768 read 16-bit columns.
-template <int U, class T, class C, class F>
-__device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
-                             F decode) {
-  // U independent gathers in flight per lane
-  T a[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) a[u] = 0;
-  int j = 0;
-  for (; j + U - 1 < w; j += U) {
-    int c[U];
-    T v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      c[u] = decode(__builtin_nontemporal_load(cp + (j + u) * 64));
-      v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) a[u] += v[u] * x[c[u]];
-  }
-  for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[decode(__builtin_nontemporal_load(cp + j * 64))];
-  T s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  if (U == 16) s += ((a[8] + a[9]) + (a[10] + a[11])) + ((a[12] + a[13]) + (a[14] + a[15]));
-  return s;
-}
-
-template <class T, int U = 8>
-__device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
-                             int lane) {
-  static_assert(U == 8 || U == 16, "8 or 16 gathers in flight");
-  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
-  const int64_t base = S.sptr[s32];
-  const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
-  const T *vp = val + base + lane;
-  const int b0 = S.cbase[2 * s32];
-  if (b0 >= 0) {
-    const int bh = S.cbase[2 * s32 + 1] - 0x8000;
-    return sell_dot<U>(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
-  }
-  if (b0 < -1) {
-    // window bases in lanes 0..15, picked per entry by a cross-lane read
-    const int tb = S.ctab[16 * (int64_t)s32 + (lane & 15)];
-    const int shift = b0 == -2 ? 13 : 12;
-    const int mask = (1 << shift) - 1;
-    return sell_dot<U>(S.col16 + base + lane, vp, x, w,
-                       [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); });
-  }
-  return sell_dot<U>(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; });
-}
 
 // Unknowns are numbered in the operator's row order (solve order), so the row
 // of a SELL position is the position itself; positions past nrows are padding.
@@ -101,15 +37,6 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nrow
   else if (MODE == SPMV_ADD) y[pos] += acc;
   else y[pos] = b[pos] - acc;
 }
-
-template <class T>
-static const T *sell_vals(const Sell &S);
-template <>
-const double *sell_vals<double>(const Sell &S) { return S.v64.p; }
-template <>
-const float *sell_vals<float>(const Sell &S) { return S.v32.p; }
-
-static inline unsigned sell_grid(const Sell &S) { return (unsigned)((S.nslices * 64 + 255) / 256); }
 
 template <class T>
 void sell_spmv(hipStream_t s, const Sell &S, const T *x, T *y, int mode, const T *b) {
@@ -224,13 +151,6 @@ void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, co
 template void patch_residual<double>(hipStream_t, const Patches &, int, const double *, const double *, double *);
 template void patch_residual<float>(hipStream_t, const Patches &, int, const float *, const float *, float *);
 
-// Orders this wavefront's LDS accesses (writes before reads of other lanes).
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // e = X r with X symmetric, stored as packed lower 32 x 32 tiles (PackedInv).
 // Row items: one wavefront per (system k, tile row I, chunk of at most
 // PACK_CHUNK tiles).  Lane (h, j) = (lane >> 5, lane & 31) reads rows 2 s + h,
@@ -251,7 +171,7 @@ __global__ __launch_bounds__(256) void k_packed_rows(int i0, int i1, const int32
                                                      const int32_t *__restrict__ ptr,
                                                      const int64_t *__restrict__ toff,
                                                      const int64_t *__restrict__ zoff, const TM *__restrict__ pk,
-                                                     const TV *__restrict__ res, TM *__restrict__ py,
+                                                     const TV *__restrict__ res, int vs, TM *__restrict__ py,
                                                      TM *__restrict__ pz) {
   constexpr int PT = PATCH_TILE;
   __shared__ TM tl[4][PT][PT + 1];
@@ -265,12 +185,12 @@ __global__ __launch_bounds__(256) void k_packed_rows(int i0, int i1, const int32
   const int k = r_sys[item], I = r_row[item];
   const int J0 = r_chunk[item] * PACK_CHUNK, J1 = min(I + 1, J0 + PACK_CHUNK);
   const int k0 = ptr[k], n = ptr[k + 1] - k0, nb = (n + PT - 1) / PT;
-  const TV *r = res + k0;
+  const TV *r = res + (int64_t)k0 * vs;  // entry i of the system at r[i vs]
   TM rI[16];
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     int i = I * PT + 2 * s + h;
-    rI[s] = i < n ? (TM)r[i] : (TM)0;
+    rI[s] = i < n ? (TM)r[(int64_t)i * vs] : (TM)0;
   }
   const TM *tile = pk + toff[k] + ((int64_t)I * (I + 1) / 2 + J0) * PT * PT + h * PT + j;
   TM *zcol = pz + zoff[k] + (int64_t)(I - 1) * PT + j;  // + 32 (J nb - J (J + 1) / 2 - J)
@@ -294,7 +214,7 @@ __global__ __launch_bounds__(256) void k_packed_rows(int i0, int i1, const int32
       if (h == 0) zcol[(int64_t)PT * ((int64_t)J * nb - (int64_t)J * (J + 1) / 2 - J)] = cs;
     }
     const int jj = J * PT + j;
-    if (h == 0) Rs[j] = jj < n ? (TM)r[jj] : (TM)0;
+    if (h == 0) Rs[j] = jj < n ? (TM)r[(int64_t)jj * vs] : (TM)0;
 #pragma unroll
     for (int s = 0; s < 16; ++s) Ts[2 * s + h][j] = v[s];
     wave_sync();
@@ -319,7 +239,7 @@ __global__ __launch_bounds__(256) void k_packed_gather(int i0, int i1, const int
                                                        const int32_t *__restrict__ map,
                                                        const int64_t *__restrict__ zoff,
                                                        const TM *__restrict__ py, const TM *__restrict__ pz,
-                                                       TV *__restrict__ u) {
+                                                       TV *__restrict__ u, int vs) {
   constexpr int PT = PATCH_TILE;
   const int item = i0 + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (item >= i1) return;
@@ -344,40 +264,42 @@ __global__ __launch_bounds__(256) void k_packed_gather(int i0, int i1, const int
   e += __shfl_xor(e, 32);
   const int i = J * PT + j;
   if (h == 0 && i < n) {
-    if (SET) u[i] = (TV)e;
-    else u[map[k0 + i]] += (TV)e;
+    if (SET) u[(int64_t)i * vs] = (TV)e;
+    else u[(int64_t)map[k0 + i] * vs] += (TV)e;
   }
 }
 
 template <class TM, class TV, bool SET>
 static void packed_apply(hipStream_t s, const PackedInv &P, const TM *pk, int colour, const int32_t *ptr,
-                         const int32_t *map, const TV *res, TM *py, TM *pz, TV *u) {
+                         const int32_t *map, const TV *res, TM *py, TM *pz, TV *u, int vs) {
   int r0 = P.colour_r_first[colour], r1 = P.colour_r_first[colour + 1];
   int g0 = P.colour_g_first[colour], g1 = P.colour_g_first[colour + 1];
   if (r1 <= r0) return;
   k_packed_rows<TM, TV><<<(unsigned)((r1 - r0 + 3) / 4), 256, 0, s>>>(r0, r1, P.r_sys, P.r_row, P.r_chunk, P.r_slot,
-                                                                      ptr, P.tile_off, P.zoff, pk, res, py, pz);
+                                                                      ptr, P.tile_off, P.zoff, pk, res, vs, py, pz);
   MG_LAUNCH_CHECK();
   k_packed_gather<TM, TV, SET><<<(unsigned)((g1 - g0 + 3) / 4), 256, 0, s>>>(g0, g1, P.g_sys, P.g_row, P.g_slot,
-                                                                             ptr, map, P.zoff, py, pz, u);
+                                                                             ptr, map, P.zoff, py, pz, u, vs);
   MG_LAUNCH_CHECK();
 }
 
+// res and u may be one column of a block vector: entry i at res[i vs], u[i vs]
 template <class T>
-void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u) {
+void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u, int vs) {
   const T *pk = std::is_same<T, double>::value ? (const T *)pt.inv.v64.p : (const T *)pt.inv.v32.p;
-  packed_apply<T, T, false>(s, pt.inv, pk, colour, pt.ptr, pt.dofs, res, py, pz, u);
+  packed_apply<T, T, false>(s, pt.inv, pk, colour, pt.ptr, pt.dofs, res, py, pz, u, vs);
 }
-template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *, double *, double *);
-template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *, float *, float *);
+template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *, double *, double *,
+                                  int);
+template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *, float *, float *, int);
 
 // coarsest level: u = A^-1 b with the packed FP64 inverse (FP64 arithmetic)
 template <class T>
-void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u) {
-  packed_apply<double, T, true>(s, L.cpk, L.cpk.v64.p, 0, L.cptr, nullptr, b, L.cpy.p, L.cpz.p, u);
+void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u, int vs) {
+  packed_apply<double, T, true>(s, L.cpk, L.cpk.v64.p, 0, L.cptr, nullptr, b, L.cpy.p, L.cpz.p, u, vs);
 }
-template void coarse_apply<double>(hipStream_t, const Level &, const double *, double *);
-template void coarse_apply<float>(hipStream_t, const Level &, const float *, float *);
+template void coarse_apply<double>(hipStream_t, const Level &, const double *, double *, int);
+template void coarse_apply<float>(hipStream_t, const Level &, const float *, float *, int);
 
 
 
@@ -456,19 +378,6 @@ void add64(hipStream_t s, double *y, const double *x, int64_t n) {
 // ---------------------------------------------------------------------------
 // inner products: per-block partial sums, then one block sums them in order
 // ---------------------------------------------------------------------------
-__device__ inline double block_sum(double v) {
-  __shared__ double red[256];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
-  return r;
-}
-
 int dot_blocks(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);

@@ -68,3 +68,14 @@ def test_binding_requires_built_library(tmp_path):
     from paper_2402_12947_amd.binding import load_library
     with pytest.raises(ImportError):
         load_library(str(tmp_path / "missing.so"))
+
+
+def test_solve_entry_points_reject_null_context_on_host():
+    import ctypes
+    from paper_2402_12947_amd import MG_ERR_ARG
+    from paper_2402_12947_amd.binding import MgSolveStats, lib
+    st = (MgSolveStats * 2)()
+    ptrs = (ctypes.c_void_p * 2)(None, None)
+    assert lib().mg_pcg_solve(None, None, None, 1e-8, 10, st) == MG_ERR_ARG
+    assert lib().mg_pcg_solve_multi(None, 2, ptrs, ptrs, 1e-8, 10, st) == MG_ERR_ARG
+    assert lib().mg_pcg_solve_batch(None, 1, 1, ptrs, ptrs, 1e-8, 10, st, None) == MG_ERR_ARG
