@@ -53,7 +53,7 @@ CHEB_KERNEL = "k_cheb"
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("solve.hip", "mg_internal.h"):
+    for f in ("solve.hip", "sell_row.h", "mg_internal.h"):
         with open(os.path.join(ROOT, "paper_2402_12947_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -285,6 +285,8 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);
 void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,
                 bool transpose, Csr &A);
 void spgemm(Ctx &c, const Csr &A, const Csr &B, Csr &C);
+// removes off-diagonal entries with |a_ij| <= 1e-12 sqrt(|a_ii a_jj|) (square A)
+void drop_cancelled(Ctx &c, Csr &A);
 void solve_order(Ctx &c, Level &L, int sigma, bool want32);
 void build_transfer_sell(Ctx &c, Level &F, const Level &C, bool want32);
 void permute_patches(Ctx &c, Level &L);

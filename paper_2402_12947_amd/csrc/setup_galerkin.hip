@@ -159,6 +159,7 @@ void galerkin_product(Ctx &c, Level &F, Level &C) {
   Csr AP;
   spgemm(c, F.A, F.Pc, AP);
   spgemm(c, F.Rc, AP, C.A);
+  drop_cancelled(c, C.A);
 }
 
 }  // namespace mg
