@@ -139,6 +139,8 @@ typedef struct {
   int64_t sell_nnz16;       /* nonzeros stored with 16-bit column indices      */
   int32_t n_components;     /* unknowns per DOF node (1; dim for elasticity):
                                n_free = n_components * free DOF nodes          */
+  int32_t sell_unroll;      /* gathers in flight per lane in the level's
+                               sparse products (4 or 8, chosen by timing)      */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */

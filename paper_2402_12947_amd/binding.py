@@ -56,7 +56,8 @@ class MgLevelInfo(C.Structure):
                 ("lambda_adj", C.c_double), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
                 ("lanczos_steps", C.c_int32), ("lanczos_steps_adj", C.c_int32), ("sell_sigma", C.c_int32),
                 ("sell_stored", C.c_int64), ("is_coarsest", C.c_int32), ("setup_ms", C.c_double),
-                ("sell_nnz16", C.c_int64), ("n_components", C.c_int32)]
+                ("sell_nnz16", C.c_int64), ("n_components", C.c_int32),
+                ("sell_unroll", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:

@@ -1018,6 +1018,7 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->sell_stored = L.S.stored;
   o->sell_nnz16 = L.S.nnz16;
   o->n_components = L.ncomp;
+  o->sell_unroll = L.S.unroll;
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;
   return MG_OK;

@@ -95,6 +95,10 @@ constexpr int SELL_C = 64;
 struct Sell {
   int64_t nrows = 0, ncols = 0, nslices = 0, stored = 0;
   int sigma = 1;
+  // gathers in flight per lane in the products with this matrix (4 or 8):
+  // short rows run faster with 4 and twice the resident wavefronts, long rows
+  // with 8; the solve-order autotuner times both on the level operator
+  int unroll = 8;
   DBuf<int64_t> slice_ptr;  // [nslices + 1]
   DBuf<int32_t> perm;       // [nslices * 64] row at each position (identity), -1 = padding
   DBuf<int32_t> col;        // [stored]

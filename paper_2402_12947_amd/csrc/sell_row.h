@@ -43,15 +43,16 @@ __device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp,
     for (int u = 0; u < U; ++u) a[u] += v[u] * x[c[u]];
   }
   for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[decode(__builtin_nontemporal_load(cp + j * 64))];
-  T s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  if (U == 16) s += ((a[8] + a[9]) + (a[10] + a[11])) + ((a[12] + a[13]) + (a[14] + a[15]));
+  T s = (a[0] + a[1]) + (a[2] + a[3]);
+  if constexpr (U >= 8) s += (a[4] + a[5]) + (a[6] + a[7]);
+  if constexpr (U == 16) s += ((a[8] + a[9]) + (a[10] + a[11])) + ((a[12] + a[13]) + (a[14] + a[15]));
   return s;
 }
 
 template <class T, int U = 8>
 __device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
                              int lane) {
-  static_assert(U == 8 || U == 16, "8 or 16 gathers in flight");
+  static_assert(U == 4 || U == 8 || U == 16, "4, 8 or 16 gathers in flight");
   const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
   const int64_t base = S.sptr[s32];
   const int w = (int)((S.sptr[s32 + 1] - base) >> 6);

@@ -789,24 +789,39 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
 // inside windows of 128 and of 1024 rows are built as well and the layout whose
 // Chebyshev-step kernel runs fastest on this GPU is kept (short windows cut most
 // of the padding while neighbouring rows still gather neighbouring entries).
+// On levels of at least 65536 unknowns every layout is timed with 4 and with 8
+// gathers in flight per lane.
 void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
+  // the faster of 4 and 8 gathers in flight for the current layout
+  auto pick_unroll = [&]() {
+    L.S.unroll = 8;
+    const double t8 = time_cheb(c, L, want32);
+    L.S.unroll = 4;
+    const double t4 = time_cheb(c, L, want32);
+    if (t8 <= t4) L.S.unroll = 8;
+    return std::min(t4, t8);
+  };
   if (sigma >= 1) {
     order_with(c, L, sigma, want32);
+    if (L.nfree >= 65536) pick_unroll();
     return;
   }
   order_with(c, L, 1, want32);
-  if ((double)L.S.stored <= 1.02 * (double)L.A.nnz || L.nfree < 65536) return;
-  int best = 1;
-  double tbest = time_cheb(c, L, want32);
+  if (L.nfree < 65536) return;
+  double tbest = pick_unroll();
+  int best = 1, best_unroll = L.S.unroll;
+  if ((double)L.S.stored <= 1.02 * (double)L.A.nnz) return;
   for (int cand : {128, 1024}) {
     order_with(c, L, cand, want32);
-    double t = time_cheb(c, L, want32);
+    double t = pick_unroll();
     if (t < tbest) {
       tbest = t;
       best = cand;
+      best_unroll = L.S.unroll;
     }
   }
   if (best != 1024) order_with(c, L, best, want32);
+  L.S.unroll = best_unroll;
 }
 
 // ---------------------------------------------------------------------------
