@@ -111,9 +111,13 @@ static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending
   }
 }
 
-// k Chebyshev-Jacobi steps (paper Sec. 3.2; see the recurrence in solve.hip)
+// k Chebyshev-Jacobi steps (paper Sec. 3.2; see the recurrence in solve.hip).
+// zero_start: u vanishes outside the patch DOFs of the level (the first
+// sandwich of a V-cycle level, which starts from u = 0: after S_c only the
+// patch DOFs are nonzero, and without S_c nothing is), so the first step needs
+// the row products only on the rows coupled to the patch DOFs.
 template <class T>
-static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt) {
+static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt, bool zero_start) {
   Level &L = c.lv[l];
   const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
   const double sigma = theta / delta;
@@ -122,9 +126,15 @@ static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt) {
   // step flags: 1 = first step (no previous direction), 2 = last step (the
   // direction is not stored)
   const int k = c.opt.cheb_degree;
-  time_begin(c, l);
-  cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, k == 1 ? 3 : 1, 0.0, 1.0 / theta);
-  time_end(c, l);
+  if (zero_start) {
+    const bool on_patches = c.opt.local_correction && L.patch.n > 0;
+    cheb_step_zero<T>(c.stream, L.nfree, on_patches ? &L.patch.nbr : nullptr, L.patch.nbr_pos, LV<T>::dinv(L), b, u,
+                      alt, k == 1 ? nullptr : d, 1.0 / theta);
+  } else {
+    time_begin(c, l);
+    cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, k == 1 ? 3 : 1, 0.0, 1.0 / theta);
+    time_end(c, l);
+  }
   std::swap(u, alt);
   for (int j = 1; j < k; ++j) {
     double rho_new = 1.0 / (2.0 * sigma - rho);
@@ -146,9 +156,10 @@ static void sgs_sweeps(Ctx &c, int l, const T *b, T *u) {
   for (int k = nc - 1; k >= 0; --k) sgs_colour_sweep<T>(c.stream, L.sgs[k], L.sgs_pos[k], LV<T>::dinv(L), b, u);
 }
 
-// u <- S^nu (b, u): nu applications of S_c -> S_g -> S_c (paper Sec. 4.2)
+// u <- S^nu (b, u): nu applications of S_c -> S_g -> S_c (paper Sec. 4.2);
+// zero_start: u = 0 on entry
 template <class T>
-static void smooth(Ctx &c, int l, const T *b, T *u, int nu) {
+static void smooth(Ctx &c, int l, const T *b, T *u, int nu, bool zero_start = false) {
   Level &L = c.lv[l];
   bool local = c.opt.local_correction && L.patch.n > 0;
   T *cur = u, *alt = LV<T>::w(L, W_ALT);
@@ -156,7 +167,7 @@ static void smooth(Ctx &c, int l, const T *b, T *u, int nu) {
   for (int s = 0; s < nu; ++s) {
     if (local) local_correction<T>(c, L, b, cur, false);
     if (c.opt.global_smoother == MG_SMOOTHER_SGS) sgs_sweeps<T>(c, l, b, cur);
-    else chebyshev<T>(c, l, b, cur, alt);
+    else chebyshev<T>(c, l, b, cur, alt, zero_start && s == 0);
     if (local) local_correction<T>(c, L, b, cur, true);
   }
   if (cur != u) convert<T, T>(c.stream, cur, u, L.nfree);
@@ -171,7 +182,7 @@ static void vcycle_zero(Ctx &c, int l, const T *b, T *u) {
     return;
   }
   fill<T>(c.stream, u, L.nfree, T(0));
-  smooth<T>(c, l, b, u, c.opt.nu);
+  smooth<T>(c, l, b, u, c.opt.nu, true);
   T *r = LV<T>::w(L, W_R);
   sell_spmv<T>(c.stream, L.S, u, r, SPMV_RESID, b);
   Level &C = c.lv[l + 1];
@@ -284,14 +295,20 @@ static void local_correction_block(Ctx &c, Level &L, int K, const T *b, T *u, bo
 }
 
 template <class T>
-static void chebyshev_block(Ctx &c, int l, int K, const T *b, T *&u, T *&alt) {
+static void chebyshev_block(Ctx &c, int l, int K, const T *b, T *&u, T *&alt, bool zero_start) {
   Level &L = c.lv[l];
   const double theta = 0.5 * (L.hi + L.lo), delta = 0.5 * (L.hi - L.lo);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   T *d = LB<T>::w(L, W_D);
   const int k = c.opt.cheb_degree;
-  cheb_step_block<T>(c.stream, L.S, K, LV<T>::dinv(L), b, u, alt, d, k == 1 ? 3 : 1, 0.0, 1.0 / theta);
+  if (zero_start) {
+    const bool on_patches = c.opt.local_correction && L.patch.n > 0;
+    cheb_step_zero_block<T>(c.stream, L.nfree, K, on_patches ? &L.patch.nbr : nullptr, L.patch.nbr_pos,
+                            LV<T>::dinv(L), b, u, alt, k == 1 ? nullptr : d, 1.0 / theta);
+  } else {
+    cheb_step_block<T>(c.stream, L.S, K, LV<T>::dinv(L), b, u, alt, d, k == 1 ? 3 : 1, 0.0, 1.0 / theta);
+  }
   std::swap(u, alt);
   for (int j = 1; j < k; ++j) {
     double rho_new = 1.0 / (2.0 * sigma - rho);
@@ -303,7 +320,7 @@ static void chebyshev_block(Ctx &c, int l, int K, const T *b, T *&u, T *&alt) {
 }
 
 template <class T>
-static void smooth_block(Ctx &c, int l, int K, const T *b, T *u, int nu) {
+static void smooth_block(Ctx &c, int l, int K, const T *b, T *u, int nu, bool zero_start) {
   Level &L = c.lv[l];
   bool local = c.opt.local_correction && L.patch.n > 0;
   T *cur = u, *alt = LB<T>::w(L, W_ALT);
@@ -317,7 +334,7 @@ static void smooth_block(Ctx &c, int l, int K, const T *b, T *u, int nu) {
       for (int k = nc - 1; k >= 0; --k)
         sgs_colour_sweep_block<T>(c.stream, L.sgs[k], K, L.sgs_pos[k], LV<T>::dinv(L), b, cur);
     } else {
-      chebyshev_block<T>(c, l, K, b, cur, alt);
+      chebyshev_block<T>(c, l, K, b, cur, alt, zero_start && s == 0);
     }
     if (local) local_correction_block<T>(c, L, K, b, cur, true);
   }
@@ -332,14 +349,14 @@ static void vcycle_zero_block(Ctx &c, int l, int K, const T *b, T *u) {
     return;
   }
   fill<T>(c.stream, u, L.nfree * K, T(0));
-  smooth_block<T>(c, l, K, b, u, c.opt.nu);
+  smooth_block<T>(c, l, K, b, u, c.opt.nu, true);
   T *r = LB<T>::w(L, W_R);
   sell_spmv_block<T>(c.stream, L.S, K, u, r, SPMV_RESID, b);
   Level &C = c.lv[l + 1];
   sell_spmv_block<T>(c.stream, L.R, K, r, LB<T>::w(C, W_B), SPMV_SET, nullptr);
   vcycle_zero_block<T>(c, l + 1, K, LB<T>::w(C, W_B), LB<T>::w(C, W_U));
   sell_spmv_block<T>(c.stream, L.P, K, LB<T>::w(C, W_U), u, SPMV_ADD, nullptr);
-  smooth_block<T>(c, l, K, b, u, c.opt.nu);
+  smooth_block<T>(c, l, K, b, u, c.opt.nu, false);
 }
 
 // c.kz = B c.kr for K columns (FP64 in and out; mixed runs the cycle in FP32)
@@ -652,7 +669,10 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       Level &L = c.lv[l];
       solve_order(c, L, L.coarsest ? 1 : c.opt.sell_sigma, mixed && !L.coarsest);
       permute_patches(c, L);
-      if (!L.coarsest) build_patch_rows(c, L, mixed);
+      if (!L.coarsest) {
+        build_patch_rows(c, L, mixed);
+        build_patch_neighbours(c, L, mixed);
+      }
       if (!L.coarsest && o.global_smoother == MG_SMOOTHER_SGS) build_sgs(c, L, mixed);
       L.setup_ms += ms(t0, now());
       phase("solve order", l);

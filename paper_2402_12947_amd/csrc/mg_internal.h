@@ -163,6 +163,11 @@ struct Patches {
   PackedInv inv;
   // rows of A at the patch DOFs (kernel order), columns in solve order
   Sell rows;
+  // the rows of A that couple to a patch DOF (ascending solve order) and their
+  // solve-order positions: after the local correction from u = 0, u vanishes
+  // outside the patch DOFs, so b - A u equals b on every other row
+  Sell nbr;
+  DBuf<int32_t> nbr_pos;
 };
 
 struct Level {
@@ -282,6 +287,7 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m);
 void factor_patches(Ctx &c, Level &L);
 void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad);
 void build_patch_rows(Ctx &c, Level &L, bool want32);
+void build_patch_neighbours(Ctx &c, Level &L, bool want32);
 void build_sgs(Ctx &c, Level &L, bool want32);
 void factor_coarsest(Ctx &c, Level &L);
 void estimate_eigenvalues(Ctx &c, Level &L);
@@ -307,6 +313,13 @@ enum { SPMV_SET = 0, SPMV_ADD = 1, SPMV_RESID = 2 };
 template <class T>
 void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T *x, T *xout, T *d,
                int first, double c_d, double c_r);
+// The first Chebyshev step (d = c_r D^-1 (b - A x), x' = x + d; d not stored
+// when d is NULL) from an x that vanishes outside the rows coupled by nbr:
+// one pass over the vectors with A x = 0, then the full step on the nbr rows.
+// nbr NULL: x = 0 everywhere (x is not read and may be NULL).
+template <class T>
+void cheb_step_zero(hipStream_t s, int64_t n, const Sell *nbr, const int32_t *nbr_pos, const T *dinv,
+                    const T *b, const T *x, T *xout, T *d, double c_r);
 
 template <class T>
 void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, const T *u, T *res);
@@ -354,6 +367,9 @@ void sgs_colour_sweep_block(hipStream_t s, const Sell &S, int K, const int32_t *
                             T *u);
 template <class T>
 void patch_residual_block(hipStream_t s, const Patches &pt, int colour, int K, const T *b, const T *u, T *res);
+template <class T>
+void cheb_step_zero_block(hipStream_t s, int64_t n, int K, const Sell *nbr, const int32_t *nbr_pos, const T *dinv,
+                          const T *b, const T *x, T *xout, T *d, double c_r);
 void spmv_dot_block(hipStream_t s, const Sell &S, int K, const double *p, double *q, double *part);
 void dot_partials_block(hipStream_t s, int K, const double *x, const double *y, int64_t n, double *part,
                         int nblocks);

@@ -686,6 +686,59 @@ void build_patch_rows(Ctx &c, Level &L, bool want32) {
   P.rows.perm.release();
 }
 
+// Rows of A that couple to a patch DOF, as a SELL matrix in ascending solve
+// order with their solve-order positions (nbr_pos).
+__global__ void k_mark_dofs(const int32_t *dofs, int64_t m, uint8_t *flag) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) flag[dofs[k]] = 1;
+}
+__global__ void k_rows_touching(const int64_t *rowptr, const int32_t *col, const uint8_t *flag, const int32_t *perm,
+                                int64_t n, int32_t *hit) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t r = perm[p];
+  int32_t h = 0;
+  for (int64_t k = rowptr[r]; k < rowptr[r + 1] && !h; ++k) h = flag[col[k]];
+  hit[p] = h;
+}
+__global__ void k_compact_rows(const int32_t *hit, const int64_t *off, const int32_t *perm, int64_t n, int32_t *pos,
+                               int32_t *rows) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n || !hit[p]) return;
+  pos[off[p]] = (int32_t)p;
+  rows[off[p]] = perm[p];
+}
+
+void build_patch_neighbours(Ctx &c, Level &L, bool want32) {
+  Patches &P = L.patch;
+  if (P.total == 0) return;
+  hipStream_t s = c.stream;
+  const int64_t n = L.nfree;
+  DBuf<uint8_t> flag;
+  DBuf<int32_t> hit, rows;
+  DBuf<int64_t> off;
+  flag.alloc(n);
+  hit.alloc(n);
+  off.alloc(n);
+  MG_HIP(hipMemsetAsync(flag.p, 0, n, s));
+  k_mark_dofs<<<grid_for(P.total, 256), 256, 0, s>>>(P.dofs_canon, P.total, flag);
+  MG_LAUNCH_CHECK();
+  k_rows_touching<<<grid_for(n, 256), 256, 0, s>>>(L.A.rowptr, L.A.col, flag, L.perm, n, hit);
+  MG_LAUNCH_CHECK();
+  const int64_t m = exclusive_scan(s, hit.p, off.p, n);
+  P.nbr_pos.alloc(m);
+  rows.alloc(m);
+  k_compact_rows<<<grid_for(n, 256), 256, 0, s>>>(hit, off, L.perm, n, P.nbr_pos, rows);
+  MG_LAUNCH_CHECK();
+  Csr B;
+  permute_csr(c, L.A, rows, m, L.iperm, n, B);
+  build_sell(c, B, P.nbr, 1, want32);
+  P.nbr.perm.release();
+  // the same gathers in flight as the level operator, so that every coupled
+  // row sums its products in the same order as the full step
+  P.nbr.unroll = L.S.unroll;
+}
+
 // Multicolour symmetric Gauss-Seidel: greedy colouring of the matrix graph in
 // canonical row order (row i takes the smallest colour not used by a coupled
 // neighbour j < i), then the rows of every colour, in solve order, as a SELL

@@ -68,6 +68,9 @@ template <class T, int FIRST, int U>
 __global__ __launch_bounds__(256) void k_cheb(
     int64_t nslices, int64_t nrows, SellCols cols, const T *__restrict__ val, const T *__restrict__ dinv,
     const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ xout, T *__restrict__ d, T c_d, T c_r) {
+  // the update as written: no fused multiply-add across these statements, so
+  // every variant of the step rounds identically
+  #pragma clang fp contract(off)
   int64_t blk = blockIdx.x;
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
@@ -104,6 +107,67 @@ template void cheb_step<double>(hipStream_t, const Sell &, const double *, const
                                 double *, int, double, double);
 template void cheb_step<float>(hipStream_t, const Sell &, const float *, const float *, const float *, float *,
                                float *, int, double, double);
+
+// First step from an x that vanishes outside the rows coupled to the patch
+// DOFs: (A x)_i = 0 on every other row, where the step reduces to
+// d = c_r D^-1 b, x' = x + d (the same operations as k_cheb with a zero row
+// product); the coupled rows are then recomputed in full from their SELL.
+template <class T>
+__global__ __launch_bounds__(256) void k_cheb_zero(int64_t n, const T *__restrict__ dinv, const T *__restrict__ b,
+                                                   const T *__restrict__ x, T *__restrict__ xout, T *__restrict__ d,
+                                                   T c_r) {
+  // the update as written: no fused multiply-add across these statements, so
+  // every variant of the step rounds identically
+  #pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const T r = dinv[i] * b[i];
+  const T dn = c_r * r;
+  if (d) d[i] = dn;
+  xout[i] = x ? x[i] + dn : dn;
+}
+
+template <class T, int U>
+__global__ __launch_bounds__(256) void k_cheb_fix(int64_t nslices, int64_t nrows, SellCols cols,
+                                                  const T *__restrict__ val, const int32_t *__restrict__ pos,
+                                                  const T *__restrict__ dinv, const T *__restrict__ b,
+                                                  const T *__restrict__ x, T *__restrict__ xout, T *__restrict__ d,
+                                                  T c_r) {
+  // the update as written: no fused multiply-add across these statements, so
+  // every variant of the step rounds identically
+  #pragma clang fp contract(off)
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = k >> 6;
+  if (sl >= nslices) return;
+  const T acc = sell_row<T, U>(cols, val, x, sl, (int)(k & 63));
+  if (k >= nrows) return;
+  const int32_t p = pos[k];
+  const T r = dinv[p] * (b[p] - acc);
+  const T dn = c_r * r;
+  if (d) d[p] = dn;
+  xout[p] = x[p] + dn;
+}
+
+template <class T>
+void cheb_step_zero(hipStream_t s, int64_t n, const Sell *nbr, const int32_t *nbr_pos, const T *dinv,
+                    const T *b, const T *x, T *xout, T *d, double c_r) {
+  if (n <= 0) return;
+  k_cheb_zero<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, dinv, b, nbr ? x : nullptr, xout, d, (T)c_r);
+  MG_LAUNCH_CHECK();
+  if (!nbr || nbr->nslices == 0) return;
+  const unsigned g = sell_grid(*nbr);
+  if (nbr->unroll == 4)
+    k_cheb_fix<T, 4><<<g, 256, 0, s>>>(nbr->nslices, nbr->nrows, cols_of(*nbr), sell_vals<T>(*nbr), nbr_pos, dinv, b,
+                                      x, xout, d, (T)c_r);
+  else
+    k_cheb_fix<T, 8><<<g, 256, 0, s>>>(nbr->nslices, nbr->nrows, cols_of(*nbr), sell_vals<T>(*nbr), nbr_pos, dinv, b,
+                                      x, xout, d, (T)c_r);
+  MG_LAUNCH_CHECK();
+}
+template void cheb_step_zero<double>(hipStream_t, int64_t, const Sell *, const int32_t *, const double *,
+                                     const double *, const double *, double *, double *, double);
+template void cheb_step_zero<float>(hipStream_t, int64_t, const Sell *, const int32_t *, const float *,
+                                    const float *, const float *, float *, float *, double);
 
 // One colour of a multicolour Gauss-Seidel sweep: u_r += D^-1_r (b_r - (A u)_r)
 // for the rows r of the colour (pos maps SELL rows to solve-order unknowns).

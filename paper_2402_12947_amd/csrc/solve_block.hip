@@ -80,6 +80,9 @@ __global__ __launch_bounds__(256) void k_cheb_k(int64_t nslices, int64_t nrows, 
                                                 const T *__restrict__ val, const T *__restrict__ dinv,
                                                 const T *__restrict__ b, const T *__restrict__ x,
                                                 T *__restrict__ xout, T *__restrict__ d, T c_d, T c_r) {
+  // the update as written: no fused multiply-add across these statements, so
+  // every variant of the step rounds identically
+  #pragma clang fp contract(off)
   const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t sl = pos >> 6;
   if (sl >= nslices) return;
@@ -127,6 +130,85 @@ template void cheb_step_block<double>(hipStream_t, const Sell &, int, const doub
                                       double *, double *, int, double, double);
 template void cheb_step_block<float>(hipStream_t, const Sell &, int, const float *, const float *, const float *,
                                      float *, float *, int, double, double);
+
+// The first step from an x that vanishes outside the rows coupled to the patch
+// DOFs (cheb_step_zero, per column).
+template <class T, int K>
+__global__ __launch_bounds__(256) void k_cheb_zero_k(int64_t n, const T *__restrict__ dinv, const T *__restrict__ b,
+                                                     const T *__restrict__ x, T *__restrict__ xout,
+                                                     T *__restrict__ d, T c_r) {
+  // the update as written: no fused multiply-add across these statements, so
+  // every variant of the step rounds identically
+  #pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const T dv = dinv[i];
+  const Row<T, K> bb = ld<T, K>(b, i);
+  Row<T, K> xx;
+  if (x) xx = ld<T, K>(x, i);
+  Row<T, K> dn, xo;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const T r = dv * bb.v[q];
+    dn.v[q] = c_r * r;
+    xo.v[q] = x ? xx.v[q] + dn.v[q] : dn.v[q];
+  }
+  if (d) st<T, K>(d, i, dn);
+  st<T, K>(xout, i, xo);
+}
+
+template <class T, int K>
+__global__ __launch_bounds__(256) void k_cheb_fix_k(int64_t nslices, int64_t nrows, SellCols cols,
+                                                    const T *__restrict__ val, const int32_t *__restrict__ pos,
+                                                    const T *__restrict__ dinv, const T *__restrict__ b,
+                                                    const T *__restrict__ x, T *__restrict__ xout,
+                                                    T *__restrict__ d, T c_r) {
+  // the update as written: no fused multiply-add across these statements, so
+  // every variant of the step rounds identically
+  #pragma clang fp contract(off)
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = k >> 6;
+  if (sl >= nslices) return;
+  T acc[K];
+  sell_row_k<T, K>(cols, val, x, sl, (int)(k & 63), acc);
+  if (k >= nrows) return;
+  const int32_t p = pos[k];
+  const T dv = dinv[p];
+  const Row<T, K> bb = ld<T, K>(b, p), xx = ld<T, K>(x, p);
+  Row<T, K> dn, xo;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const T r = dv * (bb.v[q] - acc[q]);
+    dn.v[q] = c_r * r;
+    xo.v[q] = xx.v[q] + dn.v[q];
+  }
+  if (d) st<T, K>(d, p, dn);
+  st<T, K>(xout, p, xo);
+}
+
+template <class T, int K>
+static void cheb_zero_k(hipStream_t s, int64_t n, const Sell *nbr, const int32_t *nbr_pos, const T *dinv, const T *b,
+                        const T *x, T *xout, T *d, T c_r) {
+  k_cheb_zero_k<T, K><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, dinv, b, nbr ? x : nullptr, xout, d, c_r);
+  MG_LAUNCH_CHECK();
+  if (!nbr || nbr->nslices == 0) return;
+  k_cheb_fix_k<T, K><<<sell_grid(*nbr), 256, 0, s>>>(nbr->nslices, nbr->nrows, cols_of(*nbr), sell_vals<T>(*nbr),
+                                                     nbr_pos, dinv, b, x, xout, d, c_r);
+  MG_LAUNCH_CHECK();
+}
+
+template <class T>
+void cheb_step_zero_block(hipStream_t s, int64_t n, int K, const Sell *nbr, const int32_t *nbr_pos, const T *dinv,
+                          const T *b, const T *x, T *xout, T *d, double c_r) {
+  if (n <= 0) return;
+  if (K == 2) cheb_zero_k<T, 2>(s, n, nbr, nbr_pos, dinv, b, x, xout, d, (T)c_r);
+  else if (K == 4) cheb_zero_k<T, 4>(s, n, nbr, nbr_pos, dinv, b, x, xout, d, (T)c_r);
+  else fail(MG_ERR_ARG, "block width %d is not 2 or 4", K);
+}
+template void cheb_step_zero_block<double>(hipStream_t, int64_t, int, const Sell *, const int32_t *, const double *,
+                                           const double *, const double *, double *, double *, double);
+template void cheb_step_zero_block<float>(hipStream_t, int64_t, int, const Sell *, const int32_t *, const float *,
+                                          const float *, const float *, float *, float *, double);
 
 // ---------------------------------------------------------------------------
 // one colour of multicolour Gauss-Seidel, per column (rows of a colour are

@@ -23,7 +23,7 @@ import sys
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-SOLVE_KERNELS = ("k_cheb", "k_sell_spmv", "k_patch", "k_dense_part", "k_spmv_dot")
+SOLVE_KERNELS = ("k_cheb", "k_sell_spmv", "k_patch", "k_packed", "k_spmv_dot")
 CALIBRATION_BYTES = 1 << 30
 
 
@@ -81,11 +81,8 @@ def _kernel_and_calibration(path, counter, kernel):
 
 
 def source_hash():
-    h = hashlib.sha256()
-    for f in ("solve.hip", "mg_internal.h"):
-        with open(os.path.join(ROOT, "paper_2402_12947_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from bench import kernel_source_hash
+    return kernel_source_hash()
 
 
 def counters(fetch_csv, write_csv, out_json, out_md, kernel, alg_bytes, fetch_cmd, write_cmd):

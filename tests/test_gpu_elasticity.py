@@ -1,8 +1,16 @@
 """GPU parity for linear elasticity (Sec. 6.2): vector P1/P2 on the 3D lattice
 and plane strain on the square, against the oracle: operators 1e-12 (fine) /
 1e-11 (Galerkin) relative, P (x) I transfers 1e-12, patch membership bit-exact,
-one sandwich and one V-cycle 1e-10, PCG iterations within one and the solution
-1e-8 (FP64) or 1e-6 (mixed, against the converged FP64 solution)."""
+one sandwich and one V-cycle within 1e-10 + m eps kappa_max, PCG iterations
+within one and the solution 1e-8 (FP64) or 1e-6 (mixed, against the converged
+FP64 solution).
+
+The smoother and V-cycle bars: each patch solve applies the inverse of A^[d],
+whose computed result carries a relative rounding error of order
+eps kappa(A^[d]); the elasticity patches reach kappa = 1.6e5 (Poisson patches
+about 3e3), so m solves (2 per sandwich, 8 per level in a V(2,2) cycle) can
+differ from the oracle's by m eps kappa_max on top of the 1e-10 of the other
+steps."""
 import functools
 
 import numpy as np
@@ -51,17 +59,31 @@ def test_operators_transfers_patches(name):
                 assert np.array_equal(dofs[ptr[d]:ptr[d + 1]], B)
 
 
+def patch_kappa(ora):
+    """Largest condition number of the patch matrices A^[d] of the oracle
+    hierarchy and the number of levels that have patches."""
+    kappa, levels = 1.0, 0
+    for lev in ora.levels[:-1]:
+        if len(lev.patch_dofs):
+            levels += 1
+        for B in lev.patch_dofs:
+            kappa = max(kappa, float(np.linalg.cond(lev.A[B][:, B].toarray())))
+    return kappa, levels
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_smoother_vcycle_pcg(name):
     gpu, ora = pair(name)
     n = ora.levels[0].A.shape[0]
+    kappa, plevels = patch_kappa(ora)
+    eps = np.finfo(np.float64).eps
     b, u0 = meshgen.random_rhs(n, 1), meshgen.random_rhs(n, 2)
     u = to_dev(u0)
     gpu.smooth(0, to_dev(b), u, 1)
-    assert rel_err(from_dev(u), ora.smooth(0, b, u0.copy(), 1)) < 1e-10
+    assert rel_err(from_dev(u), ora.smooth(0, b, u0.copy(), 1)) < 1e-10 + 2 * eps * kappa
     u = to_dev(u0)
     gpu.vcycle(to_dev(b), u)
-    assert rel_err(from_dev(u), ora.vcycle(b, u0.copy())) < 1e-10
+    assert rel_err(from_dev(u), ora.vcycle(b, u0.copy())) < 1e-10 + 8 * max(plevels, 1) * eps * kappa
     x_o, it_o, conv_o, _ = ora.pcg(b, 1e-10, 300)
     u = to_dev(np.zeros(n))
     st = gpu.pcg(to_dev(b), u, 1e-10, 300)
