@@ -340,6 +340,12 @@ def main():
                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                     "kernel": CHEB_KERNEL, "avg_launch_ms": round(avg_ms, 5),
                     "algorithmic_bytes_per_launch": main_arm["cheb_bytes"], "launches": main_arm["cheb_launches"]}
+        # what plain streams reach on this GPU: the Chebyshev step reads about
+        # seven bytes for every byte it writes
+        from paper_2402_12947_amd.binding import stream_probe
+        ceil = {k: round(stream_probe(k), 1) for k in ("read", "copy", "mix7:1")}
+        roofline["stream_ceilings"] = ceil
+        roofline["frac_of_mix7_1_stream"] = round(achieved / ceil["mix7:1"], 4)
     line = {
         "metric": "DOFs solved/sec to rtol 1e-8 (MG-PCG, global-local smoother)",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

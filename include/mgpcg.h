@@ -269,9 +269,20 @@ mg_status mg_enable_kernel_timing(mg_ctx *c, int32_t enable);
 mg_status mg_kernel_time(mg_ctx *c, int64_t *launches, double *total_ms);
 
 /* Bytes one launch of the level-0 Chebyshev step kernel must move at least:
- * matrix values and column indices once, and the level vectors it reads and
- * writes (12 nnz + 48 n in FP64, 8 nnz + 24 n in FP32 mixed mode). */
+ * matrix values and column indices once ((v + 2) bytes per entry stored with a
+ * 16-bit index, (v + 4) otherwise), x, b and D^-1 read and x' written every
+ * step, the direction d written by all steps but the last and read by all but
+ * the first, averaged over the k steps: v (4 + 2 (k - 1) / k) bytes per row;
+ * v = 8 (FP64) or 4 (FP32 mixed mode). */
 mg_status mg_cheb_algorithmic_bytes(const mg_ctx *c, double *bytes);
+
+/* Practical streaming ceilings of the GPU (no context needed): kind 0 = one
+ * read stream, 1 = copy (one read, one write stream), 2 = seven read streams
+ * and one write stream (the read/write mix of the Chebyshev step).  Moves
+ * `bytes` (>= 1 MiB, in device buffers it allocates and frees) `reps` times
+ * with 16-byte non-temporal accesses, one pass per element, and returns the
+ * achieved rate in GB/s (10^9 bytes/s) in *gbs. */
+mg_status mg_stream_probe(int32_t kind, int64_t bytes, int32_t reps, double *gbs);
 
 const char *mg_last_error(const mg_ctx *c);
 const char *mg_global_error(void);

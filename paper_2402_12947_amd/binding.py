@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mg_enable_kernel_timing": (C.c_int, [P, C.c_int32]),
         "mg_kernel_time": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "mg_cheb_algorithmic_bytes": (C.c_int, [P, C.POINTER(C.c_double)]),
+        "mg_stream_probe": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_double)]),
         "mg_last_error": (C.c_char_p, [P]),
         "mg_global_error": (C.c_char_p, []),
         "mg_destroy": (None, [P]),
@@ -351,3 +352,14 @@ def setup_status(meshes: list, **kw) -> tuple:
         return MG_OK, ""
     except MgError as e:
         return e.code, str(e)
+
+
+def stream_probe(kind: str, nbytes: int = 2 << 30, reps: int = 10) -> float:
+    """mg_stream_probe: GB/s of a plain stream ("read", "copy", or "mix7:1" =
+    seven read streams and one write stream) over nbytes of device memory."""
+    k = {"read": 0, "copy": 1, "mix7:1": 2}[kind]
+    gbs = C.c_double()
+    code = lib().mg_stream_probe(k, int(nbytes), int(reps), C.byref(gbs))
+    if code != MG_OK:
+        raise MgError(code, "mg_stream_probe failed")
+    return gbs.value

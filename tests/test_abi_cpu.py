@@ -79,3 +79,14 @@ def test_solve_entry_points_reject_null_context_on_host():
     assert lib().mg_pcg_solve(None, None, None, 1e-8, 10, st) == MG_ERR_ARG
     assert lib().mg_pcg_solve_multi(None, 2, ptrs, ptrs, 1e-8, 10, st) == MG_ERR_ARG
     assert lib().mg_pcg_solve_batch(None, 1, 1, ptrs, ptrs, 1e-8, 10, st, None) == MG_ERR_ARG
+
+
+def test_stream_probe_rejects_bad_arguments_on_host():
+    import ctypes
+    from paper_2402_12947_amd import MG_ERR_ARG
+    from paper_2402_12947_amd.binding import lib
+    g = ctypes.c_double()
+    assert lib().mg_stream_probe(3, 1 << 30, 1, ctypes.byref(g)) == MG_ERR_ARG
+    assert lib().mg_stream_probe(0, 1 << 10, 1, ctypes.byref(g)) == MG_ERR_ARG
+    assert lib().mg_stream_probe(0, 1 << 30, 0, ctypes.byref(g)) == MG_ERR_ARG
+    assert lib().mg_stream_probe(0, 1 << 30, 1, None) == MG_ERR_ARG
