@@ -799,6 +799,44 @@ void build_sgs(Ctx &c, Level &L, bool want32) {
   MG_HIP(hipStreamSynchronize(s));
 }
 
+// Keeps the faster of 4 and 8 gathers in flight for products y = S x
+// (x of length nx, y of length ny) in the cycle's precision.
+static void tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
+  hipStream_t s = c.stream;
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  float t[2] = {0, 0};
+  const int reps = 5;
+  auto timed = [&](auto *x, auto *y) {
+    for (int k = 0; k < 2; ++k) {
+      S.unroll = k == 0 ? 8 : 4;
+      sell_spmv(s, S, x, y, SPMV_SET, decltype(x)(nullptr));
+      MG_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) sell_spmv(s, S, x, y, SPMV_SET, decltype(x)(nullptr));
+      MG_HIP(hipEventRecord(e1, s));
+      MG_HIP(hipEventSynchronize(e1));
+      MG_HIP(hipEventElapsedTime(&t[k], e0, e1));
+    }
+  };
+  if (want32) {
+    DBuf<float> x, y;
+    x.alloc(nx);
+    y.alloc(ny);
+    fill<float>(s, x.p, nx, 0.5f);
+    timed(x.p, y.p);
+  } else {
+    DBuf<double> x, y;
+    x.alloc(nx);
+    y.alloc(ny);
+    fill<double>(s, x.p, nx, 0.5);
+    timed(x.p, y.p);
+  }
+  S.unroll = t[1] < t[0] ? 4 : 8;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 // average time of the level's Chebyshev-step kernel in its current layout
 static double time_cheb(Ctx &c, Level &L, bool want32) {
   hipStream_t s = c.stream;
@@ -926,6 +964,10 @@ void build_transfer_sell(Ctx &c, Level &F, const Level &C, bool want32) {
   ell_to_csr(c, F.nfree, C.nfree, F.pw, col, val, true, Rp);
   build_sell(c, Pp, F.P, 1, want32);
   build_sell(c, Rp, F.R, 1, want32);
+  if (F.nfree >= 65536) {
+    tune_unroll(c, F.P, C.nfree, F.nfree, want32);
+    tune_unroll(c, F.R, F.nfree, C.nfree, want32);
+  }
 }
 
 void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,
