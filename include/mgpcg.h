@@ -107,6 +107,12 @@ typedef struct {
                                components of a Dirichlet DOF clamped          */
   double young;             /* E (elasticity; paper: 6.9e10)                   */
   double poisson_ratio;     /* nu (elasticity; paper: 0.33), 0 <= nu < 0.5     */
+  int32_t sell_unroll;      /* gathers in flight per lane in the sparse
+                               products: 0 = chosen per level by timing, 4, 8 */
+  int32_t sell_mask;        /* -1 = chosen per matrix by timing; 1 = skip the
+                               values of each row's padding past the shortest
+                               row of its slice; 0 = read every stored entry.
+                               The result is the same bitwise either way      */
 } mg_options;
 
 typedef struct {
@@ -141,6 +147,10 @@ typedef struct {
                                n_free = n_components * free DOF nodes          */
   int32_t sell_unroll;      /* gathers in flight per lane in the level's
                                sparse products (4 or 8, chosen by timing)      */
+  int32_t sell_mask;        /* 1: the level's sparse products skip the values
+                               of each row's padding past the shortest row of
+                               its slice; 0: they read every stored entry
+                               (same result bitwise; chosen by timing)         */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -171,7 +181,7 @@ enum {
  * local_correction 1, adjusted_eig 1, MG_PATCH_MERGE, eig_tol 1e-8,
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
- * young 6.9e10, poisson_ratio 0.33. */
+ * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

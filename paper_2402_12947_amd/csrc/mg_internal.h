@@ -99,8 +99,14 @@ struct Sell {
   // short rows run faster with 4 and twice the resident wavefronts, long rows
   // with 8; the solve-order autotuner times both on the level operator
   int unroll = 8;
+  // 1: the products skip each row's padding past the slice's shortest row
+  // (row lengths rlen, per-slice minimum smin); 0: they use every stored
+  // entry.  Same result bitwise; the autotuner keeps the faster.
+  int mask = 0;
   DBuf<int64_t> slice_ptr;  // [nslices + 1]
   DBuf<int32_t> perm;       // [nslices * 64] row at each position (identity), -1 = padding
+  DBuf<uint16_t> rlen;      // [nslices * 64] entries of the row at each position, 0 = padding
+  DBuf<int32_t> smin;       // [nslices] shortest row of each slice
   DBuf<int32_t> col;        // [stored]
   DBuf<double> v64;         // [stored] (FP64 copy)
   DBuf<float> v32;          // [stored] (FP32 copy, mixed precision)

@@ -14,42 +14,79 @@ struct SellCols {
   const uint16_t *col16;
   const int32_t *cbase;
   const int32_t *ctab;
+  const uint16_t *rlen;
+  const int32_t *smin;
 };
 static inline SellCols cols_of(const Sell &S) {
-  return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p, S.ctab.p};
+  return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p, S.ctab.p, S.rlen.p, S.smin.p};
 }
 
 // Row `lane` of slice `sl` (sl is the same for the whole wavefront): the matrix
 // entries are streamed once per product, so they are loaded non-temporally and
 // leave the cache to the gathered vector; slices whose columns fit two windows
-// of 32768 read 16-bit columns.
+// of 32768 read 16-bit columns.  The slice is walked in rounds of U entries
+// (U gathers in flight per lane): rounds inside every row of the slice (below
+// the slice's shortest row, wmin) load all entries; the later rounds load
+// values and gather only up to each lane's own row length `len`, so the
+// padding at the end of the shorter rows costs no value traffic wherever a
+// whole cache line of it is padding (the rows of a slice are sorted by length
+// in the solve order).  With len = wmin = w every stored entry is used
+// (padding values are zero).  Entry j of the row goes to accumulator j mod U
+// and the accumulators are summed pairwise, an order that depends on the row
+// alone, so every variant and layout of a row rounds identically.
 template <int U, class T, class C, class F>
 __device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
-                             F decode) {
-  // U independent gathers in flight per lane
+                             int wmin, int len, F decode) {
   T a[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) a[u] = 0;
   int j = 0;
-  for (; j + U - 1 < w; j += U) {
-    int c[U];
+  for (; j + U <= wmin; j += U) {
+    C cr[U];
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      c[u] = decode(__builtin_nontemporal_load(cp + (j + u) * 64));
+      cr[u] = __builtin_nontemporal_load(cp + (j + u) * 64);
       v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) a[u] += v[u] * x[c[u]];
+    for (int u = 0; u < U; ++u) a[u] += v[u] * x[decode(cr[u])];
   }
-  for (; j < w; ++j) a[0] += __builtin_nontemporal_load(vp + j * 64) * x[decode(__builtin_nontemporal_load(cp + j * 64))];
+  for (; j < w; j += U) {
+    // all loads of the round are issued before the first use: the columns
+    // (past the slice width the last one again, which keeps every lane in
+    // the decode, as it may read across lanes), then the values and the
+    // gathers of the lane's own entries (zero beyond them)
+    C cr[U];
+    T v[U], g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cr[u] = __builtin_nontemporal_load(cp + (j + u < w ? j + u : w - 1) * 64);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = 0;
+      if (j + u < len) v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
+    }
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = decode(cr[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      g[u] = 0;
+      if (j + u < len) g[u] = x[c[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] += v[u] * g[u];
+  }
   T s = (a[0] + a[1]) + (a[2] + a[3]);
   if constexpr (U >= 8) s += (a[4] + a[5]) + (a[6] + a[7]);
   if constexpr (U == 16) s += ((a[8] + a[9]) + (a[10] + a[11])) + ((a[12] + a[13]) + (a[14] + a[15]));
   return s;
 }
 
-template <class T, int U = 8>
+// MASK: the rounds past the slice's shortest row skip each lane's padding
+// (row lengths read per lane); otherwise every stored entry is used.  Both
+// give bitwise the same result; which one is faster depends on the padding.
+template <class T, int U = 8, bool MASK = true>
 __device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
                              int lane) {
   static_assert(U == 4 || U == 8 || U == 16, "4, 8 or 16 gathers in flight");
@@ -57,20 +94,23 @@ __device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const
   const int64_t base = S.sptr[s32];
   const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
   const T *vp = val + base + lane;
+  const int wmin = MASK ? S.smin[s32] : w;
+  const int len = MASK ? (int)S.rlen[64 * (int64_t)s32 + lane] : w;
   const int b0 = S.cbase[2 * s32];
   if (b0 >= 0) {
     const int bh = S.cbase[2 * s32 + 1] - 0x8000;
-    return sell_dot<U>(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
+    return sell_dot<U>(S.col16 + base + lane, vp, x, w, wmin, len,
+                       [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; });
   }
   if (b0 < -1) {
     // window bases in lanes 0..15, picked per entry by a cross-lane read
     const int tb = S.ctab[16 * (int64_t)s32 + (lane & 15)];
     const int shift = b0 == -2 ? 13 : 12;
     const int mask = (1 << shift) - 1;
-    return sell_dot<U>(S.col16 + base + lane, vp, x, w,
+    return sell_dot<U>(S.col16 + base + lane, vp, x, w, wmin, len,
                        [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); });
   }
-  return sell_dot<U>(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; });
+  return sell_dot<U>(S.col + base + lane, vp, x, w, wmin, len, [](int32_t c) { return (int)c; });
 }
 
 // the value array of the cycle's precision
@@ -92,10 +132,11 @@ struct alignas(sizeof(T) * K) BlockRow {
 
 // Row `lane` of a slice times K interleaved vectors: every matrix entry is
 // read once and used K times.  U gathers in flight per lane (4 when a gather
-// is 32 bytes, to bound the registers of the K U accumulators).
+// is 32 bytes, to bound the registers of the K U accumulators); rounds, value
+// loads up to the row length and the order of the sums as in sell_dot.
 template <int U, int K, class T, class C, class F>
 __device__ inline void sell_dot_k(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
-                                  F decode, T (&out)[K]) {
+                                  int wmin, int len, F decode, T (&out)[K]) {
   using R = BlockRow<T, K>;
   const R *__restrict__ xr = reinterpret_cast<const R *>(x);
   T a[U][K];
@@ -104,26 +145,45 @@ __device__ inline void sell_dot_k(const C *__restrict__ cp, const T *__restrict_
 #pragma unroll
     for (int q = 0; q < K; ++q) a[u][q] = 0;
   int j = 0;
-  for (; j + U - 1 < w; j += U) {
-    int c[U];
+  for (; j + U <= wmin; j += U) {
+    C cr[U];
     T v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      c[u] = decode(__builtin_nontemporal_load(cp + (j + u) * 64));
+      cr[u] = __builtin_nontemporal_load(cp + (j + u) * 64);
       v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const R xv = xr[c[u]];
+      const R xv = xr[decode(cr[u])];
 #pragma unroll
       for (int q = 0; q < K; ++q) a[u][q] += v[u] * xv.v[q];
     }
   }
-  for (; j < w; ++j) {
-    const T v = __builtin_nontemporal_load(vp + j * 64);
-    const R xv = xr[decode(__builtin_nontemporal_load(cp + j * 64))];
+  for (; j < w; j += U) {
+    C cr[U];
+    T v[U];
 #pragma unroll
-    for (int q = 0; q < K; ++q) a[0][q] += v * xv.v[q];
+    for (int u = 0; u < U; ++u) cr[u] = __builtin_nontemporal_load(cp + (j + u < w ? j + u : w - 1) * 64);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = 0;
+      if (j + u < len) v[u] = __builtin_nontemporal_load(vp + (j + u) * 64);
+    }
+    int c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = decode(cr[u]);
+    R g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) g[u].v[q] = 0;
+      if (j + u < len) g[u] = xr[c[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < K; ++q) a[u][q] += v[u] * g[u].v[q];
   }
 #pragma unroll
   for (int q = 0; q < K; ++q) {
@@ -141,19 +201,21 @@ __device__ inline void sell_row_k(const SellCols &S, const T *__restrict__ val, 
   const int64_t base = S.sptr[s32];
   const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
   const T *vp = val + base + lane;
+  const int wmin = S.smin[s32];
+  const int len = S.rlen[64 * (int64_t)s32 + lane];
   const int b0 = S.cbase[2 * s32];
   if (b0 >= 0) {
     const int bh = S.cbase[2 * s32 + 1] - 0x8000;
-    sell_dot_k<U, K>(S.col16 + base + lane, vp, x, w, [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; },
-                     out);
+    sell_dot_k<U, K>(S.col16 + base + lane, vp, x, w, wmin, len,
+                     [=](uint16_t c) { return ((c & 0x8000) ? bh : b0) + (int)c; }, out);
   } else if (b0 < -1) {
     const int tb = S.ctab[16 * (int64_t)s32 + (lane & 15)];
     const int shift = b0 == -2 ? 13 : 12;
     const int mask = (1 << shift) - 1;
-    sell_dot_k<U, K>(S.col16 + base + lane, vp, x, w,
+    sell_dot_k<U, K>(S.col16 + base + lane, vp, x, w, wmin, len,
                      [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); }, out);
   } else {
-    sell_dot_k<U, K>(S.col + base + lane, vp, x, w, [](int32_t c) { return (int)c; }, out);
+    sell_dot_k<U, K>(S.col + base + lane, vp, x, w, wmin, len, [](int32_t c) { return (int)c; }, out);
   }
 }
 

@@ -450,7 +450,8 @@ __global__ void k_slice_width(const int64_t *rowptr, const int32_t *perm, int64_
 }
 
 __global__ void k_sell_fill(const int64_t *rowptr, const int32_t *ccol, const double *cval, const int32_t *perm,
-                            const int64_t *sptr, int64_t npos, int32_t *col, double *v64, float *v32) {
+                            const int64_t *sptr, int64_t npos, int32_t *col, double *v64, float *v32,
+                            uint16_t *rlen, unsigned long long *maxlen) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npos) return;
   int64_t sl = p / SELL_C;
@@ -459,6 +460,8 @@ __global__ void k_sell_fill(const int64_t *rowptr, const int32_t *ccol, const do
   int64_t w = (sptr[sl + 1] - base) / SELL_C;
   int32_t r = perm[p];
   int64_t b = r >= 0 ? rowptr[r] : 0, len = r >= 0 ? rowptr[r + 1] - rowptr[r] : 0;
+  rlen[p] = (uint16_t)(len < 0xFFFF ? len : 0xFFFF);
+  if (len > 0xFFFF) atomicMax(maxlen, (unsigned long long)len);
   int32_t pad = len > 0 ? ccol[b] : 0;
   for (int64_t j = 0; j < w; ++j) {
     int64_t o = base + j * SELL_C + lane;
@@ -468,6 +471,14 @@ __global__ void k_sell_fill(const int64_t *rowptr, const int32_t *ccol, const do
     v64[o] = vv;
     if (v32) v32[o] = (float)vv;
   }
+}
+
+__global__ void k_slice_min(const uint16_t *rlen, int64_t nslices, int32_t *smin) {
+  int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= nslices) return;
+  int m = 0xFFFF;
+  for (int l = 0; l < SELL_C; ++l) m = min(m, (int)rlen[sl * SELL_C + l]);
+  smin[sl] = m;
 }
 
 __device__ inline int wave_min_i(int v) {
@@ -580,25 +591,35 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
   S.col.alloc(S.stored);
   S.v64.alloc(S.stored);
   if (want32) S.v32.alloc(S.stored);
+  S.rlen.alloc(npos);
+  // cnt[0]: entries in 16-bit slices; cnt[1]: longest row above 65535 entries
+  DBuf<unsigned long long> cnt;
+  cnt.alloc(2);
+  MG_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), s));
   k_sell_fill<<<grid_for(npos, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, S.perm, S.slice_ptr, npos, S.col, S.v64,
-                                                 want32 ? S.v32.p : nullptr);
+                                                 want32 ? S.v32.p : nullptr, S.rlen, cnt.p + 1);
+  MG_LAUNCH_CHECK();
+  S.smin.alloc(S.nslices);
+  k_slice_min<<<grid_for(S.nslices, 256), 256, 0, s>>>(S.rlen, S.nslices, S.smin);
   MG_LAUNCH_CHECK();
   S.nnz = A.nnz;
+  // variants before any timing: the options' fixed choices, else skip the
+  // padding where it exceeds 2 % of the entries
+  S.mask = c.opt.sell_mask >= 0 ? c.opt.sell_mask : (double)S.stored > 1.02 * (double)A.nnz;
+  if (c.opt.sell_unroll) S.unroll = c.opt.sell_unroll;
   S.col16.alloc(S.stored);
   S.cbase.alloc(2 * S.nslices);
   S.ctab.alloc(16 * S.nslices);
-  DBuf<unsigned long long> cnt;
-  cnt.alloc(1);
-  MG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
   if (S.nslices > 0) {
     k_compress_cols<<<(unsigned)((S.nslices + 3) / 4), 256, 0, s>>>(S.nslices, S.slice_ptr, S.col, A.rowptr,
                                                                     A.nrows, S.col16, S.cbase, S.ctab, cnt);
     MG_LAUNCH_CHECK();
   }
-  unsigned long long h16 = 0;
-  MG_HIP(hipMemcpyAsync(&h16, cnt.p, sizeof(h16), hipMemcpyDeviceToHost, s));
+  unsigned long long h[2] = {0, 0};
+  MG_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
-  S.nnz16 = (int64_t)h16;
+  if (h[1] > 0) fail(MG_ERR_LIMIT, "a sparse row holds %llu entries (at most 65535 are supported)", h[1]);
+  S.nnz16 = (int64_t)h[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -799,24 +820,46 @@ void build_sgs(Ctx &c, Level &L, bool want32) {
   MG_HIP(hipStreamSynchronize(s));
 }
 
-// Keeps the faster of 4 and 8 gathers in flight for products y = S x
-// (x of length nx, y of length ny) in the cycle's precision.
+// The product variants (gathers in flight, padding skipped or not) the
+// autotuner times for S: those the options leave open; skipping the padding
+// only where the layout pads.
+static std::vector<std::pair<int, int>> variants(const Ctx &c, const Sell &S) {
+  std::vector<std::pair<int, int>> v;
+  for (int m = 0; m < 2; ++m) {
+    if (c.opt.sell_mask >= 0 ? m != c.opt.sell_mask : (m == 1 && S.stored <= S.nnz)) continue;
+    for (int u : {8, 4})
+      if (c.opt.sell_unroll == 0 || c.opt.sell_unroll == u) v.push_back({u, m});
+  }
+  return v;
+}
+
+// Keeps the fastest of 4 and 8 gathers in flight, with and (where the layout
+// pads) without skipping the padding, for products y = S x (x of length nx,
+// y of length ny) in the cycle's precision.
 static void tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
   hipStream_t s = c.stream;
   hipEvent_t e0, e1;
   MG_HIP(hipEventCreate(&e0));
   MG_HIP(hipEventCreate(&e1));
-  float t[2] = {0, 0};
+  float best = -1;
+  int best_u = 8, best_m = 0;
   const int reps = 5;
   auto timed = [&](auto *x, auto *y) {
-    for (int k = 0; k < 2; ++k) {
-      S.unroll = k == 0 ? 8 : 4;
+    for (auto [u, m] : variants(c, S)) {
+      S.unroll = u;
+      S.mask = m;
       sell_spmv(s, S, x, y, SPMV_SET, decltype(x)(nullptr));
       MG_HIP(hipEventRecord(e0, s));
       for (int r = 0; r < reps; ++r) sell_spmv(s, S, x, y, SPMV_SET, decltype(x)(nullptr));
       MG_HIP(hipEventRecord(e1, s));
       MG_HIP(hipEventSynchronize(e1));
-      MG_HIP(hipEventElapsedTime(&t[k], e0, e1));
+      float t = 0;
+      MG_HIP(hipEventElapsedTime(&t, e0, e1));
+      if (best < 0 || t < best) {
+        best = t;
+        best_u = u;
+        best_m = m;
+      }
     }
   };
   if (want32) {
@@ -832,7 +875,8 @@ static void tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
     fill<double>(s, x.p, nx, 0.5);
     timed(x.p, y.p);
   }
-  S.unroll = t[1] < t[0] ? 4 : 8;
+  S.unroll = best_u;
+  S.mask = best_m;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -883,14 +927,24 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
 // On levels of at least 65536 unknowns every layout is timed with 4 and with 8
 // gathers in flight per lane.
 void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
-  // the faster of 4 and 8 gathers in flight for the current layout
+  // the fastest of 4 and 8 gathers in flight, with and (where the layout
+  // pads) without skipping the padding, for the current layout
   auto pick_unroll = [&]() {
-    L.S.unroll = 8;
-    const double t8 = time_cheb(c, L, want32);
-    L.S.unroll = 4;
-    const double t4 = time_cheb(c, L, want32);
-    if (t8 <= t4) L.S.unroll = 8;
-    return std::min(t4, t8);
+    double best = -1;
+    int best_u = 8, best_m = 0;
+    for (auto [u, m] : variants(c, L.S)) {
+      L.S.unroll = u;
+      L.S.mask = m;
+      const double t = time_cheb(c, L, want32);
+      if (best < 0 || t < best) {
+        best = t;
+        best_u = u;
+        best_m = m;
+      }
+    }
+    L.S.unroll = best_u;
+    L.S.mask = best_m;
+    return best;
   };
   if (sigma >= 1) {
     order_with(c, L, sigma, want32);
@@ -900,7 +954,7 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
   order_with(c, L, 1, want32);
   if (L.nfree < 65536) return;
   double tbest = pick_unroll();
-  int best = 1, best_unroll = L.S.unroll;
+  int best = 1, best_unroll = L.S.unroll, best_mask = L.S.mask;
   if ((double)L.S.stored <= 1.02 * (double)L.A.nnz) return;
   for (int cand : {128, 1024}) {
     order_with(c, L, cand, want32);
@@ -909,10 +963,12 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
       tbest = t;
       best = cand;
       best_unroll = L.S.unroll;
+      best_mask = L.S.mask;
     }
   }
   if (best != 1024) order_with(c, L, best, want32);
   L.S.unroll = best_unroll;
+  L.S.mask = best_mask;
 }
 
 // ---------------------------------------------------------------------------

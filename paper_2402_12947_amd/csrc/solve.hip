@@ -5,7 +5,8 @@
 //   256/512-byte lines (non-temporal: they are streamed once), the source
 //   vector is gathered, 4 or 8 gathers in flight per lane (Sell::unroll,
 //   chosen per level by timing; with 4 the kernel needs half the registers
-//   and keeps 8 wavefronts per SIMD resident instead of 6).  Blocks
+//   and keeps 8 wavefronts per SIMD resident instead of 6), with or without
+//   skipping each row's padding (Sell::mask, also chosen by timing).  Blocks
 //   keep the hardware's round-robin spread over the 8 XCDs: renumbering them
 //   into one contiguous slice range per XCD was measured 1.6x slower on this
 //   kernel, into interleaved chunks of 1 to 64 blocks per XCD no faster.
@@ -24,7 +25,7 @@ namespace mg {
 
 // Unknowns are numbered in the operator's row order (solve order), so the row
 // of a SELL position is the position itself; positions past nrows are padding.
-template <class T, int MODE, int U>
+template <class T, int MODE, int U, bool M>
 __global__ __launch_bounds__(256) void k_sell_spmv(
     int64_t nslices, int64_t nrows, SellCols cols, const T *__restrict__ val, const T *__restrict__ x,
     T *__restrict__ y, const T *__restrict__ b) {
@@ -32,31 +33,36 @@ __global__ __launch_bounds__(256) void k_sell_spmv(
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
-  T acc = sell_row<T, U>(cols, val, x, sl, (int)(pos & 63));
+  T acc = sell_row<T, U, M>(cols, val, x, sl, (int)(pos & 63));
   if (pos >= nrows) return;
   if (MODE == SPMV_SET) y[pos] = acc;
   else if (MODE == SPMV_ADD) y[pos] += acc;
   else y[pos] = b[pos] - acc;
 }
 
-template <class T, int U>
+template <class T, int U, bool M>
 static void sell_spmv_u(hipStream_t s, const Sell &S, const T *x, T *y, int mode, const T *b) {
   const T *v = sell_vals<T>(S);
   unsigned g = sell_grid(S);
   if (mode == SPMV_SET)
-    k_sell_spmv<T, SPMV_SET, U><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
+    k_sell_spmv<T, SPMV_SET, U, M><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
   else if (mode == SPMV_ADD)
-    k_sell_spmv<T, SPMV_ADD, U><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
+    k_sell_spmv<T, SPMV_ADD, U, M><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
   else
-    k_sell_spmv<T, SPMV_RESID, U><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
+    k_sell_spmv<T, SPMV_RESID, U, M><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, x, y, b);
   MG_LAUNCH_CHECK();
 }
 
 template <class T>
 void sell_spmv(hipStream_t s, const Sell &S, const T *x, T *y, int mode, const T *b) {
   if (S.nslices == 0) return;
-  if (S.unroll == 4) sell_spmv_u<T, 4>(s, S, x, y, mode, b);
-  else sell_spmv_u<T, 8>(s, S, x, y, mode, b);
+  if (S.unroll == 4) {
+    if (S.mask) sell_spmv_u<T, 4, true>(s, S, x, y, mode, b);
+    else sell_spmv_u<T, 4, false>(s, S, x, y, mode, b);
+  } else {
+    if (S.mask) sell_spmv_u<T, 8, true>(s, S, x, y, mode, b);
+    else sell_spmv_u<T, 8, false>(s, S, x, y, mode, b);
+  }
 }
 template void sell_spmv<double>(hipStream_t, const Sell &, const double *, double *, int, const double *);
 template void sell_spmv<float>(hipStream_t, const Sell &, const float *, float *, int, const float *);
@@ -64,7 +70,7 @@ template void sell_spmv<float>(hipStream_t, const Sell &, const float *, float *
 // ---------------------------------------------------------------------------
 // Chebyshev-Jacobi step
 // ---------------------------------------------------------------------------
-template <class T, int FIRST, int U>
+template <class T, int FIRST, int U, bool M>
 __global__ __launch_bounds__(256) void k_cheb(
     int64_t nslices, int64_t nrows, SellCols cols, const T *__restrict__ val, const T *__restrict__ dinv,
     const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ xout, T *__restrict__ d, T c_d, T c_r) {
@@ -75,7 +81,7 @@ __global__ __launch_bounds__(256) void k_cheb(
   int64_t pos = blk * 256 + threadIdx.x;
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
-  T acc = sell_row<T, U>(cols, val, x, sl, (int)(pos & 63));
+  T acc = sell_row<T, U, M>(cols, val, x, sl, (int)(pos & 63));
   if (pos >= nrows) return;
   T r = dinv[pos] * (b[pos] - acc);
   T dn = (FIRST & 1) ? c_r * r : c_d * d[pos] + c_r * r;
@@ -83,16 +89,17 @@ __global__ __launch_bounds__(256) void k_cheb(
   xout[pos] = x[pos] + dn;
 }
 
-template <class T, int U>
+template <class T, int U, bool M>
 static void cheb_step_u(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T *x, T *xout, T *d,
                         int first, T c_d, T c_r) {
   const T *v = sell_vals<T>(S);
-  unsigned g = sell_grid(S);
+  const unsigned g = sell_grid(S);
+  const SellCols cs = cols_of(S);
   switch (first) {
-    case 1: k_cheb<T, 1, U><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, c_d, c_r); break;
-    case 2: k_cheb<T, 2, U><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, c_d, c_r); break;
-    case 3: k_cheb<T, 3, U><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, c_d, c_r); break;
-    default: k_cheb<T, 0, U><<<g, 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), v, dinv, b, x, xout, d, c_d, c_r);
+    case 1: k_cheb<T, 1, U, M><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, v, dinv, b, x, xout, d, c_d, c_r); break;
+    case 2: k_cheb<T, 2, U, M><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, v, dinv, b, x, xout, d, c_d, c_r); break;
+    case 3: k_cheb<T, 3, U, M><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, v, dinv, b, x, xout, d, c_d, c_r); break;
+    default: k_cheb<T, 0, U, M><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, v, dinv, b, x, xout, d, c_d, c_r);
   }
   MG_LAUNCH_CHECK();
 }
@@ -100,8 +107,13 @@ static void cheb_step_u(hipStream_t s, const Sell &S, const T *dinv, const T *b,
 template <class T>
 void cheb_step(hipStream_t s, const Sell &S, const T *dinv, const T *b, const T *x, T *xout, T *d, int first,
                double c_d, double c_r) {
-  if (S.unroll == 4) cheb_step_u<T, 4>(s, S, dinv, b, x, xout, d, first, (T)c_d, (T)c_r);
-  else cheb_step_u<T, 8>(s, S, dinv, b, x, xout, d, first, (T)c_d, (T)c_r);
+  if (S.unroll == 4) {
+    if (S.mask) cheb_step_u<T, 4, true>(s, S, dinv, b, x, xout, d, first, (T)c_d, (T)c_r);
+    else cheb_step_u<T, 4, false>(s, S, dinv, b, x, xout, d, first, (T)c_d, (T)c_r);
+  } else {
+    if (S.mask) cheb_step_u<T, 8, true>(s, S, dinv, b, x, xout, d, first, (T)c_d, (T)c_r);
+    else cheb_step_u<T, 8, false>(s, S, dinv, b, x, xout, d, first, (T)c_d, (T)c_r);
+  }
 }
 template void cheb_step<double>(hipStream_t, const Sell &, const double *, const double *, const double *, double *,
                                 double *, int, double, double);
@@ -539,7 +551,7 @@ void cg_update_p(hipStream_t s, double *p, const double *z, const double *scal, 
 }
 
 // q = A p (FP64 SELL) with partial sums of p.q
-template <int U>
+template <int U, bool M>
 __global__ __launch_bounds__(256) void k_spmv_dot(
     int64_t nslices, int64_t nrows, SellCols cols, const double *__restrict__ val, const double *__restrict__ p,
     double *__restrict__ q, double *__restrict__ part) {
@@ -548,7 +560,7 @@ __global__ __launch_bounds__(256) void k_spmv_dot(
   int64_t sl = pos >> 6;
   double contrib = 0;
   if (sl < nslices) {
-    double acc = sell_row<double, U>(cols, val, p, sl, (int)(pos & 63));
+    double acc = sell_row<double, U, M>(cols, val, p, sl, (int)(pos & 63));
     if (pos < nrows) {
       q[pos] = acc;
       contrib = acc * p[pos];
@@ -559,8 +571,15 @@ __global__ __launch_bounds__(256) void k_spmv_dot(
 }
 int spmv_dot_blocks(const Sell &S) { return (int)sell_grid(S); }
 void spmv_dot(hipStream_t s, const Sell &S, const double *p, double *q, double *part) {
-  if (S.unroll == 4) k_spmv_dot<4><<<sell_grid(S), 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), S.v64, p, q, part);
-  else k_spmv_dot<8><<<sell_grid(S), 256, 0, s>>>(S.nslices, S.nrows, cols_of(S), S.v64, p, q, part);
+  const unsigned g = sell_grid(S);
+  const SellCols cs = cols_of(S);
+  if (S.unroll == 4) {
+    if (S.mask) k_spmv_dot<4, true><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, S.v64, p, q, part);
+    else k_spmv_dot<4, false><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, S.v64, p, q, part);
+  } else {
+    if (S.mask) k_spmv_dot<8, true><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, S.v64, p, q, part);
+    else k_spmv_dot<8, false><<<g, 256, 0, s>>>(S.nslices, S.nrows, cs, S.v64, p, q, part);
+  }
   MG_LAUNCH_CHECK();
 }
 

@@ -1,0 +1,71 @@
+"""The sparse-product variants give bitwise the same results.
+
+Every SELL row product sums entry j of its row into accumulator j mod U and
+adds the accumulators pairwise, whether it skips the padding of the shorter
+rows of a slice (sell_mask = 1) or reads every stored entry (sell_mask = 0),
+so the autotuner's choice between them cannot change a result.  Checked on
+whole solves (every level operator, transfer, patch-row and split first-step
+product of the cycle) with the variant fixed by the options, against each
+other bit for bit and against the oracle at the FP64 bar.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+from tests.parity_util import from_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (workload, scale, degree, layers)
+    "square_p2": ("square_1025", 16, 2, 1),
+    "cube_p2": ("cube_129", 16, 2, 1),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _case(name):
+    wl, scale, degree, layers = CASES[name]
+    meshes = meshgen.hierarchy(wl, seed=0, scale=scale)
+    ora = oracle.Hierarchy(meshes, tau=0.1, layers=layers, opts=oracle.Options(degree=degree))
+    return meshes, ora
+
+
+def _solve(meshes, degree, layers, precision, unroll, mask, b, rtol):
+    import torch
+    from paper_2402_12947_amd import Solver
+    s = Solver(meshes, degree=degree, layers=layers, precision=precision, sell_sigma=128,
+               sell_unroll=unroll, sell_mask=mask)
+    info = [s.level_info(l) for l in range(s.n_levels - 1)]
+    assert all(lv["sell_unroll"] == unroll and lv["sell_mask"] == mask for lv in info)
+    u = torch.zeros_like(b)
+    st = s.pcg(b, u, rtol, 300)
+    s.close()
+    return from_dev(u), st["iterations"], info
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_masked_and_full_products_agree_bitwise(name, precision):
+    wl, scale, degree, layers = CASES[name]
+    meshes, ora = _case(name)
+    print(f"[case {name} {precision}] levels={[m['cells'].shape[0] for m in meshes]}", flush=True)
+    n = ora.levels[0].A.shape[0]
+    rhs = meshgen.random_rhs(n, 7)
+    # FP64: the oracle's iterate at the same tolerance; mixed: its solution
+    rtol = 1e-10 if precision == "fp64" else 1e-8
+    x_o, it_o, _, _ = ora.pcg(rhs, rtol, 300)
+    x_ref = x_o if precision == "fp64" else ora.pcg(rhs, 1e-12, 300)[0]
+    tol = 1e-8 if precision == "fp64" else 1e-6
+    b = to_dev(rhs)
+    for unroll in (4, 8):
+        u0, it0, info = _solve(meshes, degree, layers, precision, unroll, 0, b, rtol)
+        u1, it1, _ = _solve(meshes, degree, layers, precision, unroll, 1, b, rtol)
+        # the layouts pad, so the masked variant really skips entries
+        assert info[0]["sell_stored"] > info[0]["nnz"]
+        assert it0 == it1 and np.array_equal(u0, u1), (unroll, it0, it1)
+        assert abs(it0 - it_o) <= 1
+        assert np.max(np.abs(u0 - x_ref)) <= tol * np.max(np.abs(x_ref))
