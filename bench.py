@@ -367,9 +367,10 @@ def main():
                    "sell_sigma_level0": main_arm["levels"][0]["sell_sigma"],
                    "sell_padding_level0": round(main_arm["levels"][0]["sell_stored"]
                                                 / main_arm["levels"][0]["nnz"], 4),
-                   "levels_n_nnz_padding_sigma_idx16_unroll_mask": [
+                   "levels_n_nnz_padding_sigma_idx16_unroll_mask_rpl": [
                        [lv["n_free"], lv["nnz"], round(lv["sell_stored"] / max(1, lv["nnz"]), 4), lv["sell_sigma"],
-                        round(lv["sell_nnz16"] / max(1, lv["sell_stored"]), 4), lv["sell_unroll"], lv["sell_mask"]]
+                        round(lv["sell_nnz16"] / max(1, lv["sell_stored"]), 4), lv["sell_unroll"], lv["sell_mask"],
+                        lv["sell_rpl"]]
                        for lv in main_arm["levels"]]},
         "roofline": roofline,
         "arms": extra,

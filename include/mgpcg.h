@@ -113,6 +113,9 @@ typedef struct {
                                values of each row's padding past the shortest
                                row of its slice; 0 = read every stored entry.
                                The result is the same bitwise either way      */
+  int32_t sell_rpl;         /* lanes per row of the level operators' sparse
+                               products: 0 = chosen per level by timing,
+                               1, 2, 4 or 8                                    */
 } mg_options;
 
 typedef struct {
@@ -151,6 +154,8 @@ typedef struct {
                                of each row's padding past the shortest row of
                                its slice; 0: they read every stored entry
                                (same result bitwise; chosen by timing)         */
+  int32_t sell_rpl;         /* lanes per row of the level's operator products
+                               (1, 2, 4 or 8; chosen by timing)               */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -181,7 +186,7 @@ enum {
  * local_correction 1, adjusted_eig 1, MG_PATCH_MERGE, eig_tol 1e-8,
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
- * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1. */
+ * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

@@ -39,7 +39,8 @@ class MgOptions(C.Structure):
                 ("patch_policy", C.c_int32), ("eig_tol", C.c_double), ("eig_maxit", C.c_int32),
                 ("use_graph", C.c_int32), ("sell_sigma", C.c_int32), ("stream", C.c_void_p),
                 ("global_smoother", C.c_int32), ("problem", C.c_int32), ("young", C.c_double),
-                ("poisson_ratio", C.c_double), ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32)]
+                ("poisson_ratio", C.c_double), ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32),
+                ("sell_rpl", C.c_int32)]
 
 
 class MgSolveStats(C.Structure):
@@ -57,7 +58,7 @@ class MgLevelInfo(C.Structure):
                 ("lanczos_steps", C.c_int32), ("lanczos_steps_adj", C.c_int32), ("sell_sigma", C.c_int32),
                 ("sell_stored", C.c_int64), ("is_coarsest", C.c_int32), ("setup_ms", C.c_double),
                 ("sell_nnz16", C.c_int64), ("n_components", C.c_int32),
-                ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32)]
+                ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32), ("sell_rpl", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -146,7 +147,7 @@ class Solver:
                  local_correction: bool = True, adjusted_eig: bool = True, policy: str = "merge",
                  eig_tol: float = 1e-8, eig_maxit: int = 200, use_graph: bool = False, sell_sigma: int = 0,
                  global_smoother: str = "chebyshev", problem: str = "poisson", young: float = 6.9e10,
-                 poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1):
+                 poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1, sell_rpl: int = 0):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -172,6 +173,7 @@ class Solver:
         opt.poisson_ratio = poisson_ratio
         opt.sell_unroll = sell_unroll
         opt.sell_mask = sell_mask
+        opt.sell_rpl = sell_rpl
         keep: list = []
         arr = (MgMesh * len(meshes))(*[_mesh_struct(m, keep) for m in meshes])
         h = C.c_void_p()

@@ -562,6 +562,7 @@ void mg_default_options(mg_options *o) {
   o->sell_sigma = 0;
   o->sell_unroll = 0;
   o->sell_mask = -1;
+  o->sell_rpl = 0;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
   o->problem = MG_PROBLEM_POISSON;
   o->young = 6.9e10;
@@ -620,6 +621,8 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.sell_unroll != 0 && o.sell_unroll != 4 && o.sell_unroll != 8)
       fail(MG_ERR_ARG, "sell_unroll must be 0, 4 or 8");
     if (o.sell_mask < -1 || o.sell_mask > 1) fail(MG_ERR_ARG, "sell_mask must be -1, 0 or 1");
+    if (o.sell_rpl != 0 && o.sell_rpl != 1 && o.sell_rpl != 2 && o.sell_rpl != 4 && o.sell_rpl != 8)
+      fail(MG_ERR_ARG, "sell_rpl must be 0, 1, 2, 4 or 8");
     for (int l = 0; l < n_levels; ++l) validate_mesh(levels[l], dim, l);
     h = new mg_ctx();
     Ctx &c = h->impl;
@@ -1045,6 +1048,7 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->n_components = L.ncomp;
   o->sell_unroll = L.S.unroll;
   o->sell_mask = L.S.mask;
+  o->sell_rpl = L.S.rpl;
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;
   return MG_OK;

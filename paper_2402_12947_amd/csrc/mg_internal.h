@@ -103,9 +103,13 @@ struct Sell {
   // (row lengths rlen, per-slice minimum smin); 0: they use every stored
   // entry.  Same result bitwise; the autotuner keeps the faster.
   int mask = 0;
+  // lanes per row (1, 2, 4 or 8): a slice holds 64 / rpl rows, lane l works
+  // on entries t, t + rpl, ... (t = l mod rpl) of row l / rpl of its slice;
+  // long rows of small levels get rpl times the wavefronts
+  int rpl = 1;
   DBuf<int64_t> slice_ptr;  // [nslices + 1]
-  DBuf<int32_t> perm;       // [nslices * 64] row at each position (identity), -1 = padding
-  DBuf<uint16_t> rlen;      // [nslices * 64] entries of the row at each position, 0 = padding
+  DBuf<int32_t> perm;       // [nslices * 64] row at each position, -1 = padding
+  DBuf<uint16_t> rlen;      // [nslices * 64] entries held at each position, 0 = padding
   DBuf<int32_t> smin;       // [nslices] shortest row of each slice
   DBuf<int32_t> col;        // [stored]
   DBuf<double> v64;         // [stored] (FP64 copy)
@@ -297,7 +301,7 @@ void build_patch_neighbours(Ctx &c, Level &L, bool want32);
 void build_sgs(Ctx &c, Level &L, bool want32);
 void factor_coarsest(Ctx &c, Level &L);
 void estimate_eigenvalues(Ctx &c, Level &L);
-void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32);
+void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32, int rpl = 1);
 void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,
                 bool transpose, Csr &A);
 void spgemm(Ctx &c, const Csr &A, const Csr &B, Csr &C);

@@ -16,9 +16,23 @@ struct SellCols {
   const int32_t *ctab;
   const uint16_t *rlen;
   const int32_t *smin;
+  int rpl;
 };
 static inline SellCols cols_of(const Sell &S) {
-  return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p, S.ctab.p, S.rlen.p, S.smin.p};
+  return {S.slice_ptr.p, S.col.p, S.col16.p, S.cbase.p, S.ctab.p, S.rlen.p, S.smin.p, S.rpl};
+}
+
+// Row of SELL position pos (64 positions per slice, rpl lanes per row) and
+// whether this lane stores the row's result (the first of its lanes).
+struct SellRow {
+  int64_t row;
+  bool lead;
+};
+__device__ inline SellRow sell_row_of(const SellCols &S, int64_t pos) {
+  const int rpl = S.rpl;
+  if (rpl == 1) return {pos, true};
+  const int lane = (int)(pos & 63);
+  return {(pos >> 6) * (64 / rpl) + lane / rpl, (lane & (rpl - 1)) == 0};
 }
 
 // Row `lane` of slice `sl` (sl is the same for the whole wavefront): the matrix
@@ -86,11 +100,11 @@ __device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp,
 // MASK: the rounds past the slice's shortest row skip each lane's padding
 // (row lengths read per lane); otherwise every stored entry is used.  Both
 // give bitwise the same result; which one is faster depends on the padding.
-template <class T, int U = 8, bool MASK = true>
-__device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
-                             int lane) {
-  static_assert(U == 4 || U == 8 || U == 16, "4, 8 or 16 gathers in flight");
-  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
+// With rpl lanes per row the lanes' partial sums are added by a butterfly,
+// which leaves the same row product in every lane of the row.
+template <class T, int U, bool MASK>
+__device__ inline T sell_lane(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int s32,
+                              int lane) {
   const int64_t base = S.sptr[s32];
   const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
   const T *vp = val + base + lane;
@@ -111,6 +125,16 @@ __device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const
                        [=](uint16_t c) { return __shfl(tb, (int)c >> shift) + ((int)c & mask); });
   }
   return sell_dot<U>(S.col + base + lane, vp, x, w, wmin, len, [](int32_t c) { return (int)c; });
+}
+
+template <class T, int U = 8, bool MASK = false>
+__device__ inline T sell_row(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
+                             int lane) {
+  static_assert(U == 4 || U == 8 || U == 16, "4, 8 or 16 gathers in flight");
+  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
+  T r = sell_lane<T, U, MASK>(S, val, x, s32, lane);
+  for (int m = 1; m < S.rpl; m <<= 1) r += __shfl_xor(r, m);
+  return r;
 }
 
 // the value array of the cycle's precision
@@ -194,10 +218,9 @@ __device__ inline void sell_dot_k(const C *__restrict__ cp, const T *__restrict_
 }
 
 template <class T, int K>
-__device__ inline void sell_row_k(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
-                                  int lane, T (&out)[K]) {
+__device__ inline void sell_lane_k(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int s32,
+                                   int lane, T (&out)[K]) {
   constexpr int U = sizeof(T) * K > 16 ? 4 : 8;
-  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
   const int64_t base = S.sptr[s32];
   const int w = (int)((S.sptr[s32 + 1] - base) >> 6);
   const T *vp = val + base + lane;
@@ -217,6 +240,16 @@ __device__ inline void sell_row_k(const SellCols &S, const T *__restrict__ val, 
   } else {
     sell_dot_k<U, K>(S.col + base + lane, vp, x, w, wmin, len, [](int32_t c) { return (int)c; }, out);
   }
+}
+
+template <class T, int K>
+__device__ inline void sell_row_k(const SellCols &S, const T *__restrict__ val, const T *__restrict__ x, int64_t sl,
+                                  int lane, T (&out)[K]) {
+  const int s32 = __builtin_amdgcn_readfirstlane((int)sl);
+  sell_lane_k<T, K>(S, val, x, s32, lane, out);
+  for (int m = 1; m < S.rpl; m <<= 1)
+#pragma unroll
+    for (int q = 0; q < K; ++q) out[q] += __shfl_xor(out[q], m);
 }
 
 // Orders this wavefront's LDS accesses (writes before reads of other lanes).

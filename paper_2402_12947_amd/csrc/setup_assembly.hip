@@ -435,38 +435,58 @@ __global__ void k_identity_perm(int32_t *perm, int64_t npos, int64_t n) {
   if (p < npos) perm[p] = p < n ? (int32_t)p : -1;
 }
 
-__global__ void k_slice_width(const int64_t *rowptr, const int32_t *perm, int64_t nslices, int64_t *w64) {
+// Entries of a row of len entries that lane t of its rpl lanes holds
+// (entries t, t + rpl, t + 2 rpl, ...).
+__device__ inline int64_t lane_entries(int64_t len, int t, int rpl) {
+  return len > t ? (len - t + rpl - 1) / rpl : 0;
+}
+
+// Row at each SELL position: rpl lanes per row, 64 / rpl rows per slice; -1
+// past the last row.
+__global__ void k_sell_rows(int32_t *perm, int64_t npos, int64_t n, int rpl) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npos) return;
+  const int64_t r = (p / SELL_C) * (SELL_C / rpl) + (p % SELL_C) / rpl;
+  perm[p] = r < n ? (int32_t)r : -1;
+}
+
+__global__ void k_slice_width(const int64_t *rowptr, const int32_t *perm, int64_t nslices, int rpl, int64_t *w64) {
   int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sl >= nslices) return;
   int64_t w = 0;
   for (int l = 0; l < SELL_C; ++l) {
     int32_t r = perm[sl * SELL_C + l];
     if (r >= 0) {
-      int64_t len = rowptr[r + 1] - rowptr[r];
+      int64_t len = lane_entries(rowptr[r + 1] - rowptr[r], l % rpl, rpl);
       w = len > w ? len : w;
     }
   }
   w64[sl] = w * SELL_C;
 }
 
+// Position p = (slice, lane) holds entries t, t + rpl, ... (t = lane mod rpl)
+// of its row, entry t + j rpl at column j of the slice.
 __global__ void k_sell_fill(const int64_t *rowptr, const int32_t *ccol, const double *cval, const int32_t *perm,
-                            const int64_t *sptr, int64_t npos, int32_t *col, double *v64, float *v32,
+                            const int64_t *sptr, int64_t npos, int rpl, int32_t *col, double *v64, float *v32,
                             uint16_t *rlen, unsigned long long *maxlen) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npos) return;
   int64_t sl = p / SELL_C;
   int lane = (int)(p - sl * SELL_C);
+  const int t = lane % rpl;
   int64_t base = sptr[sl];
   int64_t w = (sptr[sl + 1] - base) / SELL_C;
   int32_t r = perm[p];
   int64_t b = r >= 0 ? rowptr[r] : 0, len = r >= 0 ? rowptr[r + 1] - rowptr[r] : 0;
-  rlen[p] = (uint16_t)(len < 0xFFFF ? len : 0xFFFF);
-  if (len > 0xFFFF) atomicMax(maxlen, (unsigned long long)len);
+  const int64_t mine = lane_entries(len, t, rpl);
+  rlen[p] = (uint16_t)(mine < 0xFFFF ? mine : 0xFFFF);
+  if (mine > 0xFFFF) atomicMax(maxlen, (unsigned long long)mine);
   int32_t pad = len > 0 ? ccol[b] : 0;
   for (int64_t j = 0; j < w; ++j) {
     int64_t o = base + j * SELL_C + lane;
-    int32_t cc = j < len ? ccol[b + j] : pad;
-    double vv = j < len ? cval[b + j] : 0.0;
+    const int64_t e = t + j * rpl;
+    int32_t cc = j < mine ? ccol[b + e] : pad;
+    double vv = j < mine ? cval[b + e] : 0.0;
     col[o] = cc;
     v64[o] = vv;
     if (v32) v32[o] = (float)vv;
@@ -511,7 +531,7 @@ __device__ int cover_windows(const int32_t *cp, int w, int bits, int *bases) {
 // column of the slice (two windows of 32768, else eight of 8192, else sixteen
 // of 4096) and write it, or keep the slice at 32 bits.
 __global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const int64_t *sptr, const int32_t *col,
-                                                       const int64_t *rp, int64_t nrows, uint16_t *col16,
+                                                       const uint16_t *rlen, uint16_t *col16,
                                                        int32_t *cbase, int32_t *ctab, unsigned long long *nnz16) {
   const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (sl >= nslices) return;
@@ -562,28 +582,30 @@ __global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const in
     mode = bits;
   }
   (void)mode;
-  const int64_t r = sl * SELL_C + lane;
-  unsigned long long len = r < nrows ? (unsigned long long)(rp[r + 1] - rp[r]) : 0ull;
+  unsigned long long len = rlen[sl * SELL_C + lane];
   for (int m = 32; m >= 1; m >>= 1) len += __shfl_xor(len, m);
   if (lane == 0) atomicAdd(nnz16, len);
 }
 
 // SELL-C layout of A with its rows in their given order (row = position); the
 // solve order (solve_order) is applied to A beforehand.
-void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
+void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32, int rpl) {
   hipStream_t s = c.stream;
   if (sigma != 1) fail(MG_ERR_ARG, "build_sell keeps the row order (sigma must be 1)");
+  if (rpl != 1 && rpl != 2 && rpl != 4 && rpl != 8) fail(MG_ERR_ARG, "lanes per row must be 1, 2, 4 or 8");
   S.nrows = A.nrows;
   S.ncols = A.ncols;
   S.sigma = 1;
-  S.nslices = (A.nrows + SELL_C - 1) / SELL_C;
+  S.rpl = rpl;
+  const int64_t rows_per_slice = SELL_C / rpl;
+  S.nslices = (A.nrows + rows_per_slice - 1) / rows_per_slice;
   int64_t npos = S.nslices * SELL_C;
   S.perm.alloc(npos);
-  k_identity_perm<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, A.nrows);
+  k_sell_rows<<<grid_for(npos, 256), 256, 0, s>>>(S.perm, npos, A.nrows, rpl);
   MG_LAUNCH_CHECK();
   DBuf<int64_t> w;
   w.alloc(S.nslices);
-  k_slice_width<<<grid_for(S.nslices, 256), 256, 0, s>>>(A.rowptr, S.perm, S.nslices, w);
+  k_slice_width<<<grid_for(S.nslices, 256), 256, 0, s>>>(A.rowptr, S.perm, S.nslices, rpl, w);
   MG_LAUNCH_CHECK();
   S.slice_ptr.alloc(S.nslices + 1);
   S.stored = exclusive_scan(s, w.p, S.slice_ptr.p, S.nslices);
@@ -596,8 +618,8 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
   DBuf<unsigned long long> cnt;
   cnt.alloc(2);
   MG_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), s));
-  k_sell_fill<<<grid_for(npos, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, S.perm, S.slice_ptr, npos, S.col, S.v64,
-                                                 want32 ? S.v32.p : nullptr, S.rlen, cnt.p + 1);
+  k_sell_fill<<<grid_for(npos, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, S.perm, S.slice_ptr, npos, rpl, S.col,
+                                                 S.v64, want32 ? S.v32.p : nullptr, S.rlen, cnt.p + 1);
   MG_LAUNCH_CHECK();
   S.smin.alloc(S.nslices);
   k_slice_min<<<grid_for(S.nslices, 256), 256, 0, s>>>(S.rlen, S.nslices, S.smin);
@@ -611,8 +633,8 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32) {
   S.cbase.alloc(2 * S.nslices);
   S.ctab.alloc(16 * S.nslices);
   if (S.nslices > 0) {
-    k_compress_cols<<<(unsigned)((S.nslices + 3) / 4), 256, 0, s>>>(S.nslices, S.slice_ptr, S.col, A.rowptr,
-                                                                    A.nrows, S.col16, S.cbase, S.ctab, cnt);
+    k_compress_cols<<<(unsigned)((S.nslices + 3) / 4), 256, 0, s>>>(S.nslices, S.slice_ptr, S.col, S.rlen,
+                                                                    S.col16, S.cbase, S.ctab, cnt);
     MG_LAUNCH_CHECK();
   }
   unsigned long long h[2] = {0, 0};
@@ -667,7 +689,7 @@ static void permute_csr(Ctx &c, const Csr &A, const int32_t *perm, int64_t nrows
   MG_HIP(hipStreamSynchronize(s));
 }
 
-static void order_with(Ctx &c, Level &L, int sigma, bool want32) {
+static void order_with(Ctx &c, Level &L, int sigma, bool want32, int rpl) {
   hipStream_t s = c.stream;
   const int64_t n = L.A.nrows;
   L.perm.alloc(n);
@@ -691,7 +713,7 @@ static void order_with(Ctx &c, Level &L, int sigma, bool want32) {
   Csr B;
   permute_csr(c, L.A, L.perm, n, L.iperm, n, B);
   L.S = Sell();
-  build_sell(c, B, L.S, 1, want32);
+  build_sell(c, B, L.S, 1, want32, rpl);
   L.S.sigma = sigma;
   dinv_of(c, B, L.dinv64, want32 ? &L.dinv32 : nullptr);
 }
@@ -753,10 +775,11 @@ void build_patch_neighbours(Ctx &c, Level &L, bool want32) {
   MG_LAUNCH_CHECK();
   Csr B;
   permute_csr(c, L.A, rows, m, L.iperm, n, B);
-  build_sell(c, B, P.nbr, 1, want32);
+  // the same lanes per row and gathers in flight as the level operator, so
+  // that every coupled row sums its products in the same order as the full
+  // step
+  build_sell(c, B, P.nbr, 1, want32, L.S.rpl);
   P.nbr.perm.release();
-  // the same gathers in flight as the level operator, so that every coupled
-  // row sums its products in the same order as the full step
   P.nbr.unroll = L.S.unroll;
 }
 
@@ -849,12 +872,17 @@ static void tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
       S.unroll = u;
       S.mask = m;
       sell_spmv(s, S, x, y, SPMV_SET, decltype(x)(nullptr));
-      MG_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) sell_spmv(s, S, x, y, SPMV_SET, decltype(x)(nullptr));
-      MG_HIP(hipEventRecord(e1, s));
-      MG_HIP(hipEventSynchronize(e1));
-      float t = 0;
-      MG_HIP(hipEventElapsedTime(&t, e0, e1));
+      // the fastest of three batches: clock and boost changes only slow a batch
+      float t = -1;
+      for (int batch = 0; batch < 3; ++batch) {
+        MG_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) sell_spmv(s, S, x, y, SPMV_SET, decltype(x)(nullptr));
+        MG_HIP(hipEventRecord(e1, s));
+        MG_HIP(hipEventSynchronize(e1));
+        float tb = 0;
+        MG_HIP(hipEventElapsedTime(&tb, e0, e1));
+        if (t < 0 || tb < t) t = tb;
+      }
       if (best < 0 || t < best) {
         best = t;
         best_u = u;
@@ -881,15 +909,22 @@ static void tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
   (void)hipEventDestroy(e1);
 }
 
-// average time of the level's Chebyshev-step kernel in its current layout
+// time of the level's Chebyshev-step kernel in its current layout: the
+// average launch of the fastest of three batches (clock and boost changes
+// only slow a batch)
 static double time_cheb(Ctx &c, Level &L, bool want32) {
   hipStream_t s = c.stream;
   const int64_t n = L.nfree;
   hipEvent_t e0, e1;
   MG_HIP(hipEventCreate(&e0));
   MG_HIP(hipEventCreate(&e1));
-  float ms = 0;
+  float ms = -1;
   const int reps = 5;
+  auto batch_ms = [&]() {
+    float t = 0;
+    MG_HIP(hipEventElapsedTime(&t, e0, e1));
+    if (ms < 0 || t < ms) ms = t;
+  };
   if (want32) {
     DBuf<float> v[4];
     for (auto &b : v) {
@@ -897,10 +932,13 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
       fill<float>(s, b.p, n, 0.5f);
     }
     cheb_step<float>(s, L.S, L.dinv32, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
-    MG_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) cheb_step<float>(s, L.S, L.dinv32, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
-    MG_HIP(hipEventRecord(e1, s));
-    MG_HIP(hipEventSynchronize(e1));
+    for (int batch = 0; batch < 3; ++batch) {
+      MG_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) cheb_step<float>(s, L.S, L.dinv32, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
+      MG_HIP(hipEventRecord(e1, s));
+      MG_HIP(hipEventSynchronize(e1));
+      batch_ms();
+    }
   } else {
     DBuf<double> v[4];
     for (auto &b : v) {
@@ -908,12 +946,14 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
       fill<double>(s, b.p, n, 0.5);
     }
     cheb_step<double>(s, L.S, L.dinv64, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
-    MG_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) cheb_step<double>(s, L.S, L.dinv64, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
-    MG_HIP(hipEventRecord(e1, s));
-    MG_HIP(hipEventSynchronize(e1));
+    for (int batch = 0; batch < 3; ++batch) {
+      MG_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) cheb_step<double>(s, L.S, L.dinv64, v[0], v[1], v[2], v[3], 0, 0.5, 0.5);
+      MG_HIP(hipEventRecord(e1, s));
+      MG_HIP(hipEventSynchronize(e1));
+      batch_ms();
+    }
   }
-  MG_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return ms / reps;
@@ -924,8 +964,13 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
 // inside windows of 128 and of 1024 rows are built as well and the layout whose
 // Chebyshev-step kernel runs fastest on this GPU is kept (short windows cut most
 // of the padding while neighbouring rows still gather neighbouring entries).
-// On levels of at least 65536 unknowns every layout is timed with 4 and with 8
-// gathers in flight per lane.
+// Levels of at least 65536 unknowns time every layout with 4 and 8 gathers
+// in flight per lane, with and without skipping the padding, and with 1 lane
+// per row and, where rows hold at least 8 entries per lane on average, 2, 4 or
+// 8 lanes per row.  Smaller levels take no timing (their choice is the same on
+// every run): the fewest lanes per row that give 4096 wavefronts (four per
+// SIMD), as long as each lane keeps 8 entries on average; the long Galerkin
+// rows of these levels otherwise leave most SIMDs with one wavefront or none.
 void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
   // the fastest of 4 and 8 gathers in flight, with and (where the layout
   // pads) without skipping the padding, for the current layout
@@ -946,29 +991,48 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
     L.S.mask = best_m;
     return best;
   };
-  if (sigma >= 1) {
-    order_with(c, L, sigma, want32);
-    if (L.nfree >= 65536) pick_unroll();
+  const bool tune = L.nfree >= 65536 && !L.coarsest;
+  const double avg = L.A.nrows ? (double)L.A.nnz / (double)L.A.nrows : 0.0;
+  std::vector<int> rpls;
+  if (c.opt.sell_rpl) {
+    rpls.push_back(c.opt.sell_rpl);
+  } else if (tune) {
+    rpls.push_back(1);
+    for (int r : {2, 4, 8})
+      if (avg >= 8.0 * r) rpls.push_back(r);
+  } else {
+    int r = 1;
+    while (r < 8 && (L.A.nrows * r + 63) / 64 < 4096 && avg >= 8.0 * (2 * r)) r *= 2;
+    rpls.push_back(r);
+  }
+  if (!tune) {
+    order_with(c, L, sigma >= 1 ? sigma : 1, want32, rpls[0]);
     return;
   }
-  order_with(c, L, 1, want32);
-  if (L.nfree < 65536) return;
-  double tbest = pick_unroll();
-  int best = 1, best_unroll = L.S.unroll, best_mask = L.S.mask;
-  if ((double)L.S.stored <= 1.02 * (double)L.A.nnz) return;
-  for (int cand : {128, 1024}) {
-    order_with(c, L, cand, want32);
-    double t = pick_unroll();
-    if (t < tbest) {
+  double tbest = -1;
+  int bs = 1, br = 1, bu = 8, bm = 0;
+  int last_s = 0, last_r = 0;
+  auto consider = [&](int sg, int r) {
+    order_with(c, L, sg, want32, r);
+    last_s = sg;
+    last_r = r;
+    const double t = pick_unroll();
+    if (tbest < 0 || t < tbest) {
       tbest = t;
-      best = cand;
-      best_unroll = L.S.unroll;
-      best_mask = L.S.mask;
+      bs = sg;
+      br = r;
+      bu = L.S.unroll;
+      bm = L.S.mask;
     }
+  };
+  for (int r : rpls) {
+    consider(sigma >= 1 ? sigma : 1, r);
+    if (sigma == 0 && (double)L.S.stored > 1.02 * (double)L.A.nnz)
+      for (int cand : {128, 1024}) consider(cand, r);
   }
-  if (best != 1024) order_with(c, L, best, want32);
-  L.S.unroll = best_unroll;
-  L.S.mask = best_mask;
+  if (bs != last_s || br != last_r) order_with(c, L, bs, want32, br);
+  L.S.unroll = bu;
+  L.S.mask = bm;
 }
 
 // ---------------------------------------------------------------------------

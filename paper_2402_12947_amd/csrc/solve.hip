@@ -23,8 +23,10 @@
 
 namespace mg {
 
-// Unknowns are numbered in the operator's row order (solve order), so the row
-// of a SELL position is the position itself; positions past nrows are padding.
+// Unknowns are numbered in the operator's row order (solve order): the row of
+// a SELL position is the position itself with one lane per row, position
+// 64 s + l holds row s 64 / rpl + l / rpl with rpl lanes per row; rows past
+// nrows are padding.
 template <class T, int MODE, int U, bool M>
 __global__ __launch_bounds__(256) void k_sell_spmv(
     int64_t nslices, int64_t nrows, SellCols cols, const T *__restrict__ val, const T *__restrict__ x,
@@ -34,10 +36,12 @@ __global__ __launch_bounds__(256) void k_sell_spmv(
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
   T acc = sell_row<T, U, M>(cols, val, x, sl, (int)(pos & 63));
-  if (pos >= nrows) return;
-  if (MODE == SPMV_SET) y[pos] = acc;
-  else if (MODE == SPMV_ADD) y[pos] += acc;
-  else y[pos] = b[pos] - acc;
+  const SellRow rw = sell_row_of(cols, pos);
+  const int64_t i = rw.row;
+  if (!rw.lead || i >= nrows) return;
+  if (MODE == SPMV_SET) y[i] = acc;
+  else if (MODE == SPMV_ADD) y[i] += acc;
+  else y[i] = b[i] - acc;
 }
 
 template <class T, int U, bool M>
@@ -82,11 +86,13 @@ __global__ __launch_bounds__(256) void k_cheb(
   int64_t sl = pos >> 6;
   if (sl >= nslices) return;
   T acc = sell_row<T, U, M>(cols, val, x, sl, (int)(pos & 63));
-  if (pos >= nrows) return;
-  T r = dinv[pos] * (b[pos] - acc);
-  T dn = (FIRST & 1) ? c_r * r : c_d * d[pos] + c_r * r;
-  if (!(FIRST & 2)) d[pos] = dn;  // the last step of a polynomial needs no direction
-  xout[pos] = x[pos] + dn;
+  const SellRow rw = sell_row_of(cols, pos);
+  const int64_t i = rw.row;
+  if (!rw.lead || i >= nrows) return;
+  T r = dinv[i] * (b[i] - acc);
+  T dn = (FIRST & 1) ? c_r * r : c_d * d[i] + c_r * r;
+  if (!(FIRST & 2)) d[i] = dn;  // the last step of a polynomial needs no direction
+  xout[i] = x[i] + dn;
 }
 
 template <class T, int U, bool M>
@@ -152,8 +158,9 @@ __global__ __launch_bounds__(256) void k_cheb_fix(int64_t nslices, int64_t nrows
   const int64_t sl = k >> 6;
   if (sl >= nslices) return;
   const T acc = sell_row<T, U>(cols, val, x, sl, (int)(k & 63));
-  if (k >= nrows) return;
-  const int32_t p = pos[k];
+  const SellRow rw = sell_row_of(cols, k);
+  if (!rw.lead || rw.row >= nrows) return;
+  const int32_t p = pos[rw.row];
   const T r = dinv[p] * (b[p] - acc);
   const T dn = c_r * r;
   if (d) d[p] = dn;
@@ -193,8 +200,9 @@ __global__ __launch_bounds__(256) void k_sgs_colour(int64_t nslices, int64_t nro
   int64_t sl = k >> 6;
   if (sl >= nslices) return;
   T acc = sell_row(cols, val, u, sl, (int)(k & 63));
-  if (k >= nrows) return;
-  const int32_t r = pos[k];
+  const SellRow rw = sell_row_of(cols, k);
+  if (!rw.lead || rw.row >= nrows) return;
+  const int32_t r = pos[rw.row];
   u[r] += dinv[r] * (b[r] - acc);
 }
 
@@ -213,7 +221,8 @@ template void sgs_colour_sweep<float>(hipStream_t, const Sell &, const int32_t *
 // local correction
 // ---------------------------------------------------------------------------
 // r = b - A u on the rows of one colour's patches: the patch rows of A are a
-// SELL matrix of their own (kernel order), streamed like the level operator.
+// SELL matrix of their own (kernel order, one lane per row, so a colour's row
+// range is a position range), streamed like the level operator.
 template <class T>
 __global__ __launch_bounds__(256) void k_patch_residual(int64_t k0, int64_t k1, SellCols cols,
                                                         const T *__restrict__ val,
@@ -561,9 +570,10 @@ __global__ __launch_bounds__(256) void k_spmv_dot(
   double contrib = 0;
   if (sl < nslices) {
     double acc = sell_row<double, U, M>(cols, val, p, sl, (int)(pos & 63));
-    if (pos < nrows) {
-      q[pos] = acc;
-      contrib = acc * p[pos];
+    const SellRow rw = sell_row_of(cols, pos);
+    if (rw.lead && rw.row < nrows) {
+      q[rw.row] = acc;
+      contrib = acc * p[rw.row];
     }
   }
   contrib = block_sum(contrib);

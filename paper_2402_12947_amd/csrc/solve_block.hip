@@ -38,17 +38,19 @@ __global__ __launch_bounds__(256) void k_spmv_k(int64_t nslices, int64_t nrows, 
   if (sl >= nslices) return;
   T acc[K];
   sell_row_k<T, K>(cols, val, x, sl, (int)(pos & 63), acc);
-  if (pos >= nrows) return;
+  const SellRow rw = sell_row_of(cols, pos);
+  const int64_t i = rw.row;
+  if (!rw.lead || i >= nrows) return;
   Row<T, K> o;
-  if (MODE == SPMV_ADD) o = ld<T, K>(y, pos);
-  if (MODE == SPMV_RESID) o = ld<T, K>(b, pos);
+  if (MODE == SPMV_ADD) o = ld<T, K>(y, i);
+  if (MODE == SPMV_RESID) o = ld<T, K>(b, i);
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     if (MODE == SPMV_SET) o.v[q] = acc[q];
     else if (MODE == SPMV_ADD) o.v[q] += acc[q];
     else o.v[q] -= acc[q];
   }
-  st<T, K>(y, pos, o);
+  st<T, K>(y, i, o);
 }
 
 template <class T, int K>
@@ -88,11 +90,13 @@ __global__ __launch_bounds__(256) void k_cheb_k(int64_t nslices, int64_t nrows, 
   if (sl >= nslices) return;
   T acc[K];
   sell_row_k<T, K>(cols, val, x, sl, (int)(pos & 63), acc);
-  if (pos >= nrows) return;
-  const T dv = dinv[pos];
-  const Row<T, K> bb = ld<T, K>(b, pos), xx = ld<T, K>(x, pos);
+  const SellRow rw = sell_row_of(cols, pos);
+  const int64_t i = rw.row;
+  if (!rw.lead || i >= nrows) return;
+  const T dv = dinv[i];
+  const Row<T, K> bb = ld<T, K>(b, i), xx = ld<T, K>(x, i);
   Row<T, K> dd;
-  if (!(FLAGS & 1)) dd = ld<T, K>(d, pos);
+  if (!(FLAGS & 1)) dd = ld<T, K>(d, i);
   Row<T, K> dn, xo;
 #pragma unroll
   for (int q = 0; q < K; ++q) {
@@ -100,8 +104,8 @@ __global__ __launch_bounds__(256) void k_cheb_k(int64_t nslices, int64_t nrows, 
     dn.v[q] = (FLAGS & 1) ? c_r * r : c_d * dd.v[q] + c_r * r;
     xo.v[q] = xx.v[q] + dn.v[q];
   }
-  if (!(FLAGS & 2)) st<T, K>(d, pos, dn);
-  st<T, K>(xout, pos, xo);
+  if (!(FLAGS & 2)) st<T, K>(d, i, dn);
+  st<T, K>(xout, i, xo);
 }
 
 template <class T, int K>
@@ -171,8 +175,9 @@ __global__ __launch_bounds__(256) void k_cheb_fix_k(int64_t nslices, int64_t nro
   if (sl >= nslices) return;
   T acc[K];
   sell_row_k<T, K>(cols, val, x, sl, (int)(k & 63), acc);
-  if (k >= nrows) return;
-  const int32_t p = pos[k];
+  const SellRow rw = sell_row_of(cols, k);
+  if (!rw.lead || rw.row >= nrows) return;
+  const int32_t p = pos[rw.row];
   const T dv = dinv[p];
   const Row<T, K> bb = ld<T, K>(b, p), xx = ld<T, K>(x, p);
   Row<T, K> dn, xo;
@@ -224,8 +229,9 @@ __global__ __launch_bounds__(256) void k_sgs_k(int64_t nslices, int64_t nrows, S
   if (sl >= nslices) return;
   T acc[K];
   sell_row_k<T, K>(cols, val, u, sl, (int)(k & 63), acc);
-  if (k >= nrows) return;
-  const int32_t r = pos[k];
+  const SellRow rw = sell_row_of(cols, k);
+  if (!rw.lead || rw.row >= nrows) return;
+  const int32_t r = pos[rw.row];
   const T dv = dinv[r];
   const Row<T, K> bb = ld<T, K>(b, r);
   Row<T, K> uu = ld<T, K>(u, r);
@@ -316,15 +322,16 @@ __global__ __launch_bounds__(256) void k_spmv_dot_k(int64_t nslices, int64_t nro
   if (sl < nslices) {
     double acc[K];
     sell_row_k<double, K>(cols, val, p, sl, (int)(pos & 63), acc);
-    if (pos < nrows) {
-      const Row<double, K> pp = ld<double, K>(p, pos);
+    const SellRow rw = sell_row_of(cols, pos);
+    if (rw.lead && rw.row < nrows) {
+      const Row<double, K> pp = ld<double, K>(p, rw.row);
       Row<double, K> o;
 #pragma unroll
       for (int q = 0; q < K; ++q) {
         o.v[q] = acc[q];
         contrib[q] = acc[q] * pp.v[q];
       }
-      st<double, K>(qv, pos, o);
+      st<double, K>(qv, rw.row, o);
     }
   }
   block_sums_out<K>(contrib, part);

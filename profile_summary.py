@@ -7,7 +7,7 @@
   python profile_summary.py counters <fetch_counter_collection.csv> <write_counter_collection.csv>
                             <out.json> <out.md> <kernel> <algorithmic_bytes> "<fetch cmd>" "<write cmd>"
       FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the largest-grid launches of
-      <kernel>, each scaled by the factor that maps the same counter, read on a
+      the kernels whose name matches the regular expression <kernel>, each scaled by the factor that maps the same counter, read on a
       1 GiB read + 1 GiB write elementwise kernel, to its known byte count.
 
   python profile_summary.py mfma <counter_collection.csv> <out.md> "<command>" "<title>"
@@ -18,6 +18,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 from collections import defaultdict
@@ -73,7 +74,7 @@ def _per_dispatch(path, counter):
 
 def _kernel_and_calibration(path, counter, kernel):
     d = _per_dispatch(path, counter)
-    ks = [(g, v) for (n, g, v) in d.values() if kernel in n]
+    ks = [(g, v) for (n, g, v) in d.values() if re.search(kernel, n)]
     gmax = max(g for g, _ in ks)
     vals = [v for g, v in ks if g == gmax]
     cal = [v for (n, g, v) in d.values() if "MulFunctor" in n and g * 1 >= (1 << 25)]

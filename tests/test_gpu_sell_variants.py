@@ -1,12 +1,14 @@
-"""The sparse-product variants give bitwise the same results.
+"""The sparse-product variants: bitwise equal where the summation order is the
+same, every one at the oracle's bar.
 
-Every SELL row product sums entry j of its row into accumulator j mod U and
-adds the accumulators pairwise, whether it skips the padding of the shorter
-rows of a slice (sell_mask = 1) or reads every stored entry (sell_mask = 0),
-so the autotuner's choice between them cannot change a result.  Checked on
-whole solves (every level operator, transfer, patch-row and split first-step
-product of the cycle) with the variant fixed by the options, against each
-other bit for bit and against the oracle at the FP64 bar.
+Every SELL row product sums entry j of a lane's share of its row into
+accumulator j mod U and adds the accumulators pairwise, whether it skips the
+padding of the shorter rows of a slice (sell_mask = 1) or reads every stored
+entry (sell_mask = 0), so that choice of the autotuner cannot change a result.
+With several lanes per row (sell_rpl) the row is split over the lanes, which
+changes the rounding of the row products only.  Checked on whole solves
+(every level operator, transfer, patch-row and split first-step product of
+the cycle) with the variant fixed by the options.
 """
 import functools
 
@@ -34,13 +36,13 @@ def _case(name):
     return meshes, ora
 
 
-def _solve(meshes, degree, layers, precision, unroll, mask, b, rtol):
+def _solve(meshes, degree, layers, precision, unroll, mask, b, rtol, rpl=1):
     import torch
     from paper_2402_12947_amd import Solver
     s = Solver(meshes, degree=degree, layers=layers, precision=precision, sell_sigma=128,
-               sell_unroll=unroll, sell_mask=mask)
+               sell_unroll=unroll, sell_mask=mask, sell_rpl=rpl)
     info = [s.level_info(l) for l in range(s.n_levels - 1)]
-    assert all(lv["sell_unroll"] == unroll and lv["sell_mask"] == mask for lv in info)
+    assert all(lv["sell_unroll"] == unroll and lv["sell_mask"] == mask and lv["sell_rpl"] == rpl for lv in info)
     u = torch.zeros_like(b)
     st = s.pcg(b, u, rtol, 300)
     s.close()
@@ -61,11 +63,11 @@ def test_masked_and_full_products_agree_bitwise(name, precision):
     x_ref = x_o if precision == "fp64" else ora.pcg(rhs, 1e-12, 300)[0]
     tol = 1e-8 if precision == "fp64" else 1e-6
     b = to_dev(rhs)
-    for unroll in (4, 8):
-        u0, it0, info = _solve(meshes, degree, layers, precision, unroll, 0, b, rtol)
-        u1, it1, _ = _solve(meshes, degree, layers, precision, unroll, 1, b, rtol)
+    for unroll, rpl in ((4, 1), (8, 1), (8, 4), (4, 8)):
+        u0, it0, info = _solve(meshes, degree, layers, precision, unroll, 0, b, rtol, rpl)
+        u1, it1, _ = _solve(meshes, degree, layers, precision, unroll, 1, b, rtol, rpl)
         # the layouts pad, so the masked variant really skips entries
         assert info[0]["sell_stored"] > info[0]["nnz"]
-        assert it0 == it1 and np.array_equal(u0, u1), (unroll, it0, it1)
+        assert it0 == it1 and np.array_equal(u0, u1), (unroll, rpl, it0, it1)
         assert abs(it0 - it_o) <= 1
         assert np.max(np.abs(u0 - x_ref)) <= tol * np.max(np.abs(x_ref))
