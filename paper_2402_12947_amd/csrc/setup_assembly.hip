@@ -856,10 +856,20 @@ static std::vector<std::pair<int, int>> variants(const Ctx &c, const Sell &S) {
   return v;
 }
 
+// Lanes per row of a matrix whose layout is not timed: the fewest that give
+// 4096 wavefronts (four per SIMD), as long as each lane keeps 8 entries on
+// average.
+static int rule_rpl(int64_t nrows, int64_t nnz) {
+  const double avg = nrows ? (double)nnz / (double)nrows : 0.0;
+  int r = 1;
+  while (r < 8 && (nrows * r + 63) / 64 < 4096 && avg >= 8.0 * (2 * r)) r *= 2;
+  return r;
+}
+
 // Keeps the fastest of 4 and 8 gathers in flight, with and (where the layout
 // pads) without skipping the padding, for products y = S x (x of length nx,
 // y of length ny) in the cycle's precision.
-static void tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
+static float tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
   hipStream_t s = c.stream;
   hipEvent_t e0, e1;
   MG_HIP(hipEventCreate(&e0));
@@ -907,6 +917,7 @@ static void tune_unroll(Ctx &c, Sell &S, int64_t nx, int64_t ny, bool want32) {
   S.mask = best_m;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return best;
 }
 
 // time of the level's Chebyshev-step kernel in its current layout: the
@@ -1001,9 +1012,7 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
     for (int r : {2, 4, 8})
       if (avg >= 8.0 * r) rpls.push_back(r);
   } else {
-    int r = 1;
-    while (r < 8 && (L.A.nrows * r + 63) / 64 < 4096 && avg >= 8.0 * (2 * r)) r *= 2;
-    rpls.push_back(r);
+    rpls.push_back(rule_rpl(L.A.nrows, L.A.nnz));
   }
   if (!tune) {
     order_with(c, L, sigma >= 1 ? sigma : 1, want32, rpls[0]);
@@ -1082,10 +1091,32 @@ void build_transfer_sell(Ctx &c, Level &F, const Level &C, bool want32) {
   Csr Pp, Rp;
   ell_to_csr(c, F.nfree, C.nfree, F.pw, col, val, false, Pp);
   ell_to_csr(c, F.nfree, C.nfree, F.pw, col, val, true, Rp);
+  // P: at most one entry per coarse basis function of a cell, one lane per
+  // row; R = P^T: a coarse row gathers every fine node of its support, and
+  // takes lanes per row like the level operators (timed where the fine level
+  // has at least 65536 unknowns, else by rule_rpl)
   build_sell(c, Pp, F.P, 1, want32);
-  build_sell(c, Rp, F.R, 1, want32);
-  if (F.nfree >= 65536) {
-    tune_unroll(c, F.P, C.nfree, F.nfree, want32);
+  const bool timing = F.nfree >= 65536;
+  if (timing) tune_unroll(c, F.P, C.nfree, F.nfree, want32);
+  if (!timing || c.opt.sell_rpl) {
+    build_sell(c, Rp, F.R, 1, want32, c.opt.sell_rpl ? c.opt.sell_rpl : rule_rpl(Rp.nrows, Rp.nnz));
+    if (timing) tune_unroll(c, F.R, F.nfree, C.nfree, want32);
+    return;
+  }
+  const double avg = Rp.nrows ? (double)Rp.nnz / (double)Rp.nrows : 0.0;
+  float best = -1;
+  int best_r = 1;
+  for (int r : {1, 2, 4, 8}) {
+    if (r > 1 && avg < 8.0 * r) break;
+    build_sell(c, Rp, F.R, 1, want32, r);
+    const float t = tune_unroll(c, F.R, F.nfree, C.nfree, want32);
+    if (best < 0 || t < best) {
+      best = t;
+      best_r = r;
+    }
+  }
+  if (F.R.rpl != best_r) {
+    build_sell(c, Rp, F.R, 1, want32, best_r);
     tune_unroll(c, F.R, F.nfree, C.nfree, want32);
   }
 }
