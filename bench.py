@@ -363,6 +363,7 @@ def main():
                    "setup_s": round(main_arm["setup_s"], 3),
                    "true_rel_residual": main_arm["true_rel_residual"],
                    "patches_level0": main_arm["levels"][0]["n_patches"],
+                   "patch_colours_one_launch_level0": main_arm["levels"][0]["patch_fused_colours"],
                    "coarsest_dofs": main_arm["levels"][-1]["n_free"], "graph": bool(args.graph),
                    "sell_sigma_level0": main_arm["levels"][0]["sell_sigma"],
                    "sell_padding_level0": round(main_arm["levels"][0]["sell_stored"]

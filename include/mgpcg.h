@@ -116,6 +116,10 @@ typedef struct {
   int32_t sell_rpl;         /* lanes per row of the level operators' sparse
                                products: 0 = chosen per level by timing,
                                1, 2, 4 or 8                                    */
+  int32_t patch_fused;      /* 1: a colour whose patches hold at most 256 DOFs
+                               and do not couple to each other runs its local
+                               correction as one launch; 0: always three
+                               launches (same result bitwise)                 */
 } mg_options;
 
 typedef struct {
@@ -156,6 +160,8 @@ typedef struct {
                                (same result bitwise; chosen by timing)         */
   int32_t sell_rpl;         /* lanes per row of the level's operator products
                                (1, 2, 4 or 8; chosen by timing)               */
+  int32_t patch_fused_colours; /* patch colours whose local correction runs
+                               as one launch                                   */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -186,7 +192,8 @@ enum {
  * local_correction 1, adjusted_eig 1, MG_PATCH_MERGE, eig_tol 1e-8,
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
- * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0. */
+ * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
+ * patch_fused 1. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

@@ -106,7 +106,15 @@ template <class T>
 static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending) {
   for (int k = 0; k < L.patch.ncolour; ++k) {
     int col = descending ? L.patch.ncolour - 1 - k : k;
+    if (L.patch.colour_fused[col]) {
+      patch_correct_small<T>(c.stream, L.patch, col, b, (const T *)nullptr, u);
+      continue;
+    }
     patch_residual<T>(c.stream, L.patch, col, b, u, LV<T>::res(L));
+    if (c.opt.patch_fused && L.patch.maxn <= SMALL_PATCH) {
+      patch_correct_small<T>(c.stream, L.patch, col, b, LV<T>::res(L), u);
+      continue;
+    }
     patch_apply<T>(c.stream, L.patch, col, LV<T>::res(L), LV<T>::py(L), LV<T>::pz(L), u);
   }
 }
@@ -563,6 +571,7 @@ void mg_default_options(mg_options *o) {
   o->sell_unroll = 0;
   o->sell_mask = -1;
   o->sell_rpl = 0;
+  o->patch_fused = 1;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
   o->problem = MG_PROBLEM_POISSON;
   o->young = 6.9e10;
@@ -623,6 +632,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.sell_mask < -1 || o.sell_mask > 1) fail(MG_ERR_ARG, "sell_mask must be -1, 0 or 1");
     if (o.sell_rpl != 0 && o.sell_rpl != 1 && o.sell_rpl != 2 && o.sell_rpl != 4 && o.sell_rpl != 8)
       fail(MG_ERR_ARG, "sell_rpl must be 0, 1, 2, 4 or 8");
+    if (o.patch_fused != 0 && o.patch_fused != 1) fail(MG_ERR_ARG, "patch_fused must be 0 or 1");
     for (int l = 0; l < n_levels; ++l) validate_mesh(levels[l], dim, l);
     h = new mg_ctx();
     Ctx &c = h->impl;
@@ -1049,6 +1059,8 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->sell_unroll = L.S.unroll;
   o->sell_mask = L.S.mask;
   o->sell_rpl = L.S.rpl;
+  o->patch_fused_colours = 0;
+  for (uint8_t f : L.patch.colour_fused) o->patch_fused_colours += f;
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;
   return MG_OK;

@@ -173,6 +173,11 @@ struct Patches {
   PackedInv inv;
   // rows of A at the patch DOFs (kernel order), columns in solve order
   Sell rows;
+  // per colour: 1 if every patch holds at most SMALL_PATCH DOFs and no patch
+  // row couples to a DOF of another patch of the colour, so that one launch
+  // per colour (patch_correct_small) equals the residual of all patches
+  // followed by all corrections
+  std::vector<uint8_t> colour_fused;
   // the rows of A that couple to a patch DOF (ascending solve order) and their
   // solve-order positions: after the local correction from u = 0, u vanishes
   // outside the patch DOFs, so b - A u equals b on every other row
@@ -337,6 +342,14 @@ void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, co
 // when vs > 1)
 template <class T>
 void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u, int vs = 1);
+// Patches of at most SMALL_PATCH DOFs, one workgroup per patch, bitwise
+// equal to patch_residual followed by patch_apply: with res = NULL the whole
+// local correction of one colour (residual, product with the packed inverse,
+// update of u) in one launch (colour_fused colours only); else the product
+// and the update, from the residual res of patch_residual.
+constexpr int SMALL_PATCH = 256;
+template <class T>
+void patch_correct_small(hipStream_t s, const Patches &pt, int colour, const T *b, const T *res, T *u);
 template <class T>
 void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u, int vs = 1);
 template <class T>

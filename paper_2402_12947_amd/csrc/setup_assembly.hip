@@ -722,11 +722,41 @@ static void order_with(Ctx &c, Level &L, int sigma, bool want32, int rpl) {
 // the level's solve order: the patch residual streams them as a SELL matrix.
 void build_patch_rows(Ctx &c, Level &L, bool want32) {
   Patches &P = L.patch;
+  P.colour_fused.assign(P.ncolour, 0);
   if (P.total == 0) return;
   Csr B;
   permute_csr(c, L.A, P.dofs_canon, P.total, L.iperm, L.nfree, B);
   build_sell(c, B, P.rows, 1, want32);
   P.rows.perm.release();
+  if (P.maxn > SMALL_PATCH || !c.opt.patch_fused) return;
+  // which colours may run as one launch: no row of a patch reads a DOF of
+  // another patch of its colour
+  hipStream_t s = c.stream;
+  std::vector<int64_t> rp(B.nrows + 1);
+  std::vector<int32_t> col(B.nnz), pos(P.total);
+  MG_HIP(hipMemcpyAsync(rp.data(), B.rowptr.p, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipMemcpyAsync(col.data(), B.col.p, col.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipMemcpyAsync(pos.data(), P.dofs.p, pos.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> owner(L.nfree, -1);
+  for (int cl = 0; cl < P.ncolour; ++cl) {
+    const int p0 = P.colour_first[cl], p1 = P.colour_first[cl + 1];
+    for (int p = p0; p < p1; ++p)
+      for (int32_t k = P.h_kptr[p]; k < P.h_kptr[p + 1]; ++k) owner[pos[k]] = p;
+    bool ok = true;
+    for (int p = p0; p < p1 && ok; ++p)
+      for (int32_t k = P.h_kptr[p]; k < P.h_kptr[p + 1] && ok; ++k)
+        for (int64_t e = rp[k]; e < rp[k + 1]; ++e) {
+          const int32_t o = owner[col[e]];
+          if (o >= 0 && o != p) {
+            ok = false;
+            break;
+          }
+        }
+    P.colour_fused[cl] = ok;
+    for (int p = p0; p < p1; ++p)
+      for (int32_t k = P.h_kptr[p]; k < P.h_kptr[p + 1]; ++k) owner[pos[k]] = -1;
+  }
 }
 
 // Rows of A that couple to a patch DOF, as a SELL matrix in ascending solve
@@ -976,9 +1006,9 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
 // Chebyshev-step kernel runs fastest on this GPU is kept (short windows cut most
 // of the padding while neighbouring rows still gather neighbouring entries).
 // Levels of at least 65536 unknowns time every layout with 4 and 8 gathers
-// in flight per lane, with and without skipping the padding, and with 1 lane
-// per row and, where rows hold at least 8 entries per lane on average, 2, 4 or
-// 8 lanes per row.  Smaller levels take no timing (their choice is the same on
+// in flight per lane, with and without skipping the padding; the sorting
+// window is chosen with one lane per row, and then, where rows hold at least
+// 8 entries per lane on average, 2, 4 and 8 lanes per row are timed with it.  Smaller levels take no timing (their choice is the same on
 // every run): the fewest lanes per row that give 4096 wavefronts (four per
 // SIMD), as long as each lane keeps 8 entries on average; the long Galerkin
 // rows of these levels otherwise leave most SIMDs with one wavefront or none.
@@ -1034,11 +1064,14 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
       bm = L.S.mask;
     }
   };
-  for (int r : rpls) {
-    consider(sigma >= 1 ? sigma : 1, r);
-    if (sigma == 0 && (double)L.S.stored > 1.02 * (double)L.A.nnz)
-      for (int cand : {128, 1024}) consider(cand, r);
-  }
+  // the sorting window with the first lanes-per-row candidate, then the other
+  // candidates with the best window found (each layout build streams the
+  // whole operator, so not every pair is built)
+  consider(sigma >= 1 ? sigma : 1, rpls[0]);
+  if (sigma == 0 && (double)L.S.stored > 1.02 * (double)L.A.nnz)
+    for (int cand : {128, 1024}) consider(cand, rpls[0]);
+  const int sbest = bs;
+  for (size_t q = 1; q < rpls.size(); ++q) consider(sbest, rpls[q]);
   if (bs != last_s || br != last_r) order_with(c, L, bs, want32, br);
   L.S.unroll = bu;
   L.S.mask = bm;

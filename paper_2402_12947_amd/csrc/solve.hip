@@ -390,6 +390,130 @@ template void patch_apply<double>(hipStream_t, const Patches &, int, const doubl
                                   int);
 template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *, float *, float *, int);
 
+// The local correction of one colour whose patches all hold at most
+// SMALL_PATCH DOFs, one workgroup per patch, in one launch instead of three:
+// the patch-row residual (whole SELL slices per wavefront, as in
+// k_patch_residual), then one wavefront per tile row I of the packed inverse
+// (the tile row is a single chunk, as nb <= PACK_CHUNK, and the steps are
+// those of k_packed_rows), then one wavefront per tile row J adding the row
+// products and the column products of the tiles below in k_packed_gather's
+// order.  The residual, the row products and the column products stay in LDS;
+// every sum is formed as in the three-kernel path, so the result is bitwise
+// the same.  With res given, the residual of the colour's patch rows comes
+// from k_patch_residual (patches whose rows read DOFs of other patches of the
+// colour need every residual before any update) and the launch replaces the
+// two launches of the packed product.
+template <class T>
+__global__ __launch_bounds__(256) void k_patch_small(int p0, SellCols cols, const T *__restrict__ val,
+                                                     const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ dofs,
+                                                     const int64_t *__restrict__ toff, const T *__restrict__ pk,
+                                                     const T *__restrict__ b, const T *__restrict__ res,
+                                                     T *__restrict__ u) {
+  constexpr int PT = PATCH_TILE, NB = SMALL_PATCH / PATCH_TILE;
+  static_assert(NB <= PACK_CHUNK, "a tile row of a small patch is one chunk");
+  __shared__ T rs[SMALL_PATCH];
+  __shared__ T ys[NB][PT];
+  __shared__ T zs[NB * (NB - 1) / 2][PT];
+  __shared__ T tl[4][PT][PT + 1];
+  __shared__ T rl[4][PT];
+  const int k = p0 + (int)blockIdx.x;
+  const int k0 = ptr[k], n = ptr[k + 1] - k0, nb = (n + PT - 1) / PT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // 1. r = b - A u on the patch rows
+  if (res) {
+    for (int i = threadIdx.x; i < n; i += 256) rs[i] = res[k0 + i];
+  } else if (n > 0) {
+    const int64_t s0 = k0 >> 6, s1 = (int64_t)(k0 + n - 1) >> 6;
+    for (int64_t sl = s0 + wave; sl <= s1; sl += 4) {
+      const T acc = sell_row(cols, val, u, sl, lane);
+      const int64_t kk = sl * 64 + lane;
+      if (kk >= k0 && kk < k0 + n) rs[kk - k0] = b[dofs[kk]] - acc;
+    }
+  }
+  __syncthreads();
+  const int h = lane >> 5, j = lane & 31;
+  // 2. tile rows: row products into ys, column products into zs; tile row I
+  // holds I + 1 tiles, so wavefront w takes rows w and nb - 1 - w (nb <= 8)
+  for (int I = 0; I < nb; ++I) {
+    if (min(I, nb - 1 - I) != wave) continue;
+    T(*Ts)[PT + 1] = tl[wave];
+    T *Rs = rl[wave];
+    T rI[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = I * PT + 2 * q + h;
+      rI[q] = i < n ? rs[i] : (T)0;
+    }
+    const T *tile = pk + toff[k] + (int64_t)I * (I + 1) / 2 * PT * PT + h * PT + j;
+    T yrow = 0;
+    T v[16], nxt[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) nxt[q] = __builtin_nontemporal_load(tile + 2 * q * PT);
+    for (int J = 0; J <= I; ++J) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = nxt[q];
+      tile += PT * PT;
+      if (J + 1 <= I) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) nxt[q] = __builtin_nontemporal_load(tile + 2 * q * PT);
+      }
+      if (J < I) {
+        T cs = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) cs += v[q] * rI[q];
+        cs += __shfl_xor(cs, 32);
+        if (h == 0) zs[J * nb - J * (J + 1) / 2 + (I - J - 1)][j] = cs;
+      }
+      const int jj = J * PT + j;
+      if (h == 0) Rs[j] = jj < n ? rs[jj] : (T)0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) Ts[2 * q + h][j] = v[q];
+      wave_sync();
+      T acc = 0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) acc += Ts[j][16 * h + t] * Rs[16 * h + t];
+      yrow += acc + __shfl_xor(acc, 32);
+      wave_sync();
+    }
+    if (h == 0) ys[I][j] = yrow;
+  }
+  __syncthreads();
+  // 3. e_J = row products of tile row J + column products of the tiles below
+  for (int J = wave; J < nb; J += 4) {
+    T e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+    if (h == 0) e0 += ys[J][j];
+    const int cnt = nb - J - 1;
+    const int zb = J * nb - J * (J + 1) / 2;
+    int t = h;
+    for (; t + 6 < cnt; t += 8) {
+      e0 += zs[zb + t][j];
+      e1 += zs[zb + t + 2][j];
+      e2 += zs[zb + t + 4][j];
+      e3 += zs[zb + t + 6][j];
+    }
+    for (; t < cnt; t += 2) e0 += zs[zb + t][j];
+    T e = (e0 + e1) + (e2 + e3);
+    e += __shfl_xor(e, 32);
+    const int i = J * PT + j;
+    if (h == 0 && i < n) u[dofs[k0 + i]] += e;
+  }
+}
+
+template <class T>
+void patch_correct_small(hipStream_t s, const Patches &pt, int colour, const T *b, const T *res, T *u) {
+  const int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
+  if (p1 <= p0) return;
+  if (pt.maxn > SMALL_PATCH || pt.rows.rpl != 1) fail(MG_ERR_ARG, "patch_correct_small: patches too large");
+  const T *pk = std::is_same<T, double>::value ? (const T *)pt.inv.v64.p : (const T *)pt.inv.v32.p;
+  k_patch_small<T><<<(unsigned)(p1 - p0), 256, 0, s>>>(p0, cols_of(pt.rows), sell_vals<T>(pt.rows), pt.ptr,
+                                                      pt.dofs, pt.inv.tile_off, pk, b, res, u);
+  MG_LAUNCH_CHECK();
+}
+template void patch_correct_small<double>(hipStream_t, const Patches &, int, const double *, const double *,
+                                          double *);
+template void patch_correct_small<float>(hipStream_t, const Patches &, int, const float *, const float *, float *);
+
 // coarsest level: u = A^-1 b with the packed FP64 inverse (FP64 arithmetic)
 template <class T>
 void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u, int vs) {

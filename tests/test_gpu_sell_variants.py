@@ -71,3 +71,35 @@ def test_masked_and_full_products_agree_bitwise(name, precision):
         assert it0 == it1 and np.array_equal(u0, u1), (unroll, rpl, it0, it1)
         assert abs(it0 - it_o) <= 1
         assert np.max(np.abs(u0 - x_ref)) <= tol * np.max(np.abs(x_ref))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("scale,one_launch", [(16, True), (4, False)])
+def test_fused_patch_correction_agrees_bitwise(precision, scale, one_launch):
+    """Small patches: one launch per colour when no patch row reads another
+    patch's DOF (1/16 of the 1025^2 P2 square: one patch), else the residual
+    launch and one launch for the packed-inverse product and update (1/4 size:
+    16 patches, two of them coupled through A); both bitwise equal to the
+    three-launch local correction, for one smoother application and a whole
+    solve."""
+    import torch
+    from paper_2402_12947_amd import Solver
+    meshes = meshgen.hierarchy("square_1025", seed=0, scale=scale)
+    print(f"[case square_1025/{scale} P2 {precision}]", flush=True)
+    out = {}
+    for fused in (True, False):
+        s = Solver(meshes, degree=2, layers=1, precision=precision, sell_sigma=128, sell_unroll=8,
+                   sell_mask=0, sell_rpl=1, patch_fused=fused)
+        info = s.level_info(0)
+        assert info["max_patch"] <= 256
+        assert info["patch_fused_colours"] == (int(one_launch) if fused else 0)
+        n = s.n_free(0)
+        b = to_dev(meshgen.random_rhs(n, 11))
+        u_s = to_dev(np.zeros(n))
+        s.smooth(0, b, u_s, 2)
+        u = torch.zeros_like(b)
+        st = s.pcg(b, u, 1e-8, 300)
+        out[fused] = (from_dev(u_s), from_dev(u), st["iterations"])
+        s.close()
+    assert np.array_equal(out[True][0], out[False][0])
+    assert np.array_equal(out[True][1], out[False][1]) and out[True][2] == out[False][2]
