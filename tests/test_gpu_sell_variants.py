@@ -63,7 +63,7 @@ def test_masked_and_full_products_agree_bitwise(name, precision):
     x_ref = x_o if precision == "fp64" else ora.pcg(rhs, 1e-12, 300)[0]
     tol = 1e-8 if precision == "fp64" else 1e-6
     b = to_dev(rhs)
-    for unroll, rpl in ((4, 1), (8, 1), (8, 4), (4, 8)):
+    for unroll, rpl in ((4, 1), (8, 1), (4, 2), (8, 4), (4, 8)):
         u0, it0, info = _solve(meshes, degree, layers, precision, unroll, 0, b, rtol, rpl)
         u1, it1, _ = _solve(meshes, degree, layers, precision, unroll, 1, b, rtol, rpl)
         # the layouts pad, so the masked variant really skips entries
