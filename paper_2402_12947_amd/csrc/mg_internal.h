@@ -144,7 +144,7 @@ struct Csr {
 // I at zoff[k] + 32 (J nb - J (J + 1) / 2) + 32 (I - J - 1)), then over gather
 // items (system, tile row J) that add them up in a fixed order.
 constexpr int PATCH_TILE = 32;
-constexpr int PACK_CHUNK = 32;
+constexpr int PACK_CHUNK = 16;
 struct PackedInv {
   int64_t packed = 0, ysize = 0, zsize = 0;
   DBuf<int64_t> tile_off, zoff;                 // [systems]

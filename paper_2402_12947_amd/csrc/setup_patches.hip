@@ -278,6 +278,28 @@ void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const 
   }
   P.colour_r_first[ncol] = (int)rs.size();
   P.colour_g_first[ncol] = (int)gs.size();
+  // within a colour, row items with the most tiles first: they are launched
+  // first, and the short items fill in behind them instead of leaving a tail
+  // of long ones (each item writes only its own slot, so the order of the
+  // items changes no result)
+  for (int col = 0; col < ncol; ++col) {
+    const int a = P.colour_r_first[col], b = P.colour_r_first[col + 1];
+    std::vector<int> ord(b - a);
+    for (int q = 0; q < b - a; ++q) ord[q] = a + q;
+    auto tiles = [&](int q) { return std::min(rr[q] + 1, (rc[q] + 1) * PACK_CHUNK) - rc[q] * PACK_CHUNK; };
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return tiles(x) > tiles(y); });
+    std::vector<int32_t> t0(b - a), t1(b - a), t2(b - a), t3(b - a);
+    for (int q = 0; q < b - a; ++q) {
+      t0[q] = rs[ord[q]];
+      t1[q] = rr[ord[q]];
+      t2[q] = rc[ord[q]];
+      t3[q] = rslot[ord[q]];
+    }
+    std::copy(t0.begin(), t0.end(), rs.begin() + a);
+    std::copy(t1.begin(), t1.end(), rr.begin() + a);
+    std::copy(t2.begin(), t2.end(), rc.begin() + a);
+    std::copy(t3.begin(), t3.end(), rslot.begin() + a);
+  }
   P.packed = tacc;
   P.ysize = (int64_t)slot * PATCH_TILE;
   P.zsize = zacc;
