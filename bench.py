@@ -107,7 +107,9 @@ def run_arm(meshes, degree, layers, rtol, steps, warmup, precision="fp64", local
     out = {"n": n, "setup_s": setup_s, "elapsed_s": elapsed, "iterations": [x["iterations"] for x in stats],
            "converged": all(x["converged"] for x in stats),
            "true_rel_residual": max(x["true_rel_residual"] for x in stats),
-           "levels": [s.level_info(l) for l in range(s.n_levels)]}
+           "levels": [s.level_info(l) for l in range(s.n_levels)],
+           # the solution of the first timed right-hand side (seed seed0 + warmup)
+           "first_seed": seed0 + warmup, "first_solution": us[warmup].cpu().numpy()}
     if timing and smoother == "chebyshev":
         launches, total_ms = s.kernel_time()
         out["cheb_launches"] = launches
@@ -331,6 +333,13 @@ def main():
         extra["global_local_mixed"] = {"dofs_per_s": mx["n"] * len(mx["iterations"]) / mx["elapsed_s"],
                                        "iterations": mx["iterations"][0], "setup_s": round(mx["setup_s"], 3),
                                        "true_rel_residual": mx["true_rel_residual"]}
+        if mx["first_seed"] == main_arm["first_seed"]:
+            # same right-hand side, same rtol: distance of the mixed-precision
+            # solution from the FP64 one (which the parity tests tie to the oracle)
+            import numpy as np
+            x64, xmx = main_arm["first_solution"], mx["first_solution"]
+            extra["global_local_mixed"]["rel_diff_vs_fp64_solution"] = float(
+                np.linalg.norm(xmx - x64) / max(np.linalg.norm(x64), 1e-300))
     roofline = None
     if args.smoother == "chebyshev":
         avg_ms = main_arm["cheb_avg_ms"]

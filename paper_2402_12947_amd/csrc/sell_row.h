@@ -43,11 +43,12 @@ __device__ inline SellRow sell_row_of(const SellCols &S, int64_t pos) {
 // the slice's shortest row, wmin) load all entries; the later rounds load
 // values and gather only up to each lane's own row length `len`, so the
 // padding at the end of the shorter rows costs no value traffic wherever a
-// whole cache line of it is padding (the rows of a slice are sorted by length
-// in the solve order).  With len = wmin = w every stored entry is used
-// (padding values are zero).  Entry j of the row goes to accumulator j mod U
-// and the accumulators are summed pairwise, an order that depends on the row
-// alone, so every variant and layout of a row rounds identically.
+// whole cache line of it is padding (the sorted layouts order the rows of a
+// slice by length).  With len = wmin = w every stored entry is used (padding
+// values are zero).  Entry j of the lane's share of its row goes to
+// accumulator j mod U and the accumulators are summed pairwise, an order that
+// depends only on the row and the lanes per row, so both variants round
+// identically.
 template <int U, class T, class C, class F>
 __device__ inline T sell_dot(const C *__restrict__ cp, const T *__restrict__ vp, const T *__restrict__ x, int w,
                              int wmin, int len, F decode) {
