@@ -1008,7 +1008,9 @@ static double time_cheb(Ctx &c, Level &L, bool want32) {
 // Levels of at least 65536 unknowns time every layout with 4 and 8 gathers
 // in flight per lane, with and without skipping the padding; the sorting
 // window is chosen with one lane per row, and then, where rows hold at least
-// 8 entries per lane on average, 2, 4 and 8 lanes per row are timed with it.  Smaller levels take no timing (their choice is the same on
+// 8 entries per lane on average, 2, 4 and 8 lanes per row are timed with it;
+// of layouts within 2 % of the fastest the one storing the fewest entries is
+// kept.  Smaller levels take no timing (their choice is the same on
 // every run): the fewest lanes per row that give 4096 wavefronts (four per
 // SIMD), as long as each lane keeps 8 entries on average; the long Galerkin
 // rows of these levels otherwise leave most SIMDs with one wavefront or none.
@@ -1048,21 +1050,30 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
     order_with(c, L, sigma >= 1 ? sigma : 1, want32, rpls[0]);
     return;
   }
-  double tbest = -1;
-  int bs = 1, br = 1, bu = 8, bm = 0;
+  // candidates within 2 % of the fastest count as equal (run-to-run noise of
+  // these timings); among them the layout that stores the fewest entries is
+  // kept, which moves the fewest bytes and makes the choice repeatable
+  struct Cand {
+    double t;
+    int64_t stored;
+    int sigma, rpl, unroll, mask;
+  };
+  std::vector<Cand> cands;
   int last_s = 0, last_r = 0;
+  auto best_of = [&]() {
+    double tmin = cands[0].t;
+    for (const Cand &q : cands) tmin = std::min(tmin, q.t);
+    const Cand *b = nullptr;
+    for (const Cand &q : cands)
+      if (q.t <= 1.02 * tmin && (!b || q.stored < b->stored)) b = &q;
+    return *b;
+  };
   auto consider = [&](int sg, int r) {
     order_with(c, L, sg, want32, r);
     last_s = sg;
     last_r = r;
     const double t = pick_unroll();
-    if (tbest < 0 || t < tbest) {
-      tbest = t;
-      bs = sg;
-      br = r;
-      bu = L.S.unroll;
-      bm = L.S.mask;
-    }
+    cands.push_back({t, L.S.stored, sg, r, L.S.unroll, L.S.mask});
   };
   // the sorting window with the first lanes-per-row candidate, then the other
   // candidates with the best window found (each layout build streams the
@@ -1070,11 +1081,12 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
   consider(sigma >= 1 ? sigma : 1, rpls[0]);
   if (sigma == 0 && (double)L.S.stored > 1.02 * (double)L.A.nnz)
     for (int cand : {128, 1024}) consider(cand, rpls[0]);
-  const int sbest = bs;
+  const int sbest = best_of().sigma;
   for (size_t q = 1; q < rpls.size(); ++q) consider(sbest, rpls[q]);
-  if (bs != last_s || br != last_r) order_with(c, L, bs, want32, br);
-  L.S.unroll = bu;
-  L.S.mask = bm;
+  const Cand b = best_of();
+  if (b.sigma != last_s || b.rpl != last_r) order_with(c, L, b.sigma, want32, b.rpl);
+  L.S.unroll = b.unroll;
+  L.S.mask = b.mask;
 }
 
 // ---------------------------------------------------------------------------
