@@ -329,10 +329,15 @@ def main():
                                "true_rel_residual": p["true_rel_residual"]}
     if "mixed" in arms and args.precision == "fp64":
         mx = run_arm(meshes, degree, layers, rtol, args.steps, 1, precision="mixed", local=True, policy=policy,
-                     smoother=args.smoother, problem=problem)
+                     smoother=args.smoother, problem=problem, timing=args.smoother == "chebyshev")
         extra["global_local_mixed"] = {"dofs_per_s": mx["n"] * len(mx["iterations"]) / mx["elapsed_s"],
                                        "iterations": mx["iterations"][0], "setup_s": round(mx["setup_s"], 3),
                                        "true_rel_residual": mx["true_rel_residual"]}
+        if "cheb_avg_ms" in mx:
+            # the same level-0 Chebyshev step in FP32 (values 4 bytes, vectors 4 bytes)
+            extra["global_local_mixed"]["level0_cheb_fp32"] = {
+                "avg_launch_ms": round(mx["cheb_avg_ms"], 5), "algorithmic_bytes_per_launch": mx["cheb_bytes"],
+                "achieved_gbs": round(mx["cheb_bytes"] / (mx["cheb_avg_ms"] * 1e-3) / 1e9, 1)}
         if mx["first_seed"] == main_arm["first_seed"]:
             # same right-hand side, same rtol: distance of the mixed-precision
             # solution from the FP64 one (which the parity tests tie to the oracle)

@@ -162,6 +162,10 @@ typedef struct {
                                (1, 2, 4 or 8; chosen by timing)               */
   int32_t patch_fused_colours; /* patch colours whose local correction runs
                                as one launch                                   */
+  int64_t sell_slices;      /* slices of the level operator's SELL layout      */
+  int64_t sell_slices_multiwindow; /* of them with 16-bit columns in 8 or 16
+                               windows (decoded with a cross-lane read)        */
+  int64_t sell_slices_32bit; /* of them with 32-bit columns                    */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */

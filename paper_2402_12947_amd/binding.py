@@ -59,7 +59,8 @@ class MgLevelInfo(C.Structure):
                 ("sell_stored", C.c_int64), ("is_coarsest", C.c_int32), ("setup_ms", C.c_double),
                 ("sell_nnz16", C.c_int64), ("n_components", C.c_int32),
                 ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32), ("sell_rpl", C.c_int32),
-                ("patch_fused_colours", C.c_int32)]
+                ("patch_fused_colours", C.c_int32), ("sell_slices", C.c_int64),
+                ("sell_slices_multiwindow", C.c_int64), ("sell_slices_32bit", C.c_int64)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:

@@ -1061,6 +1061,18 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->sell_rpl = L.S.rpl;
   o->patch_fused_colours = 0;
   for (uint8_t f : L.patch.colour_fused) o->patch_fused_colours += f;
+  o->sell_slices = L.S.nslices;
+  if (L.S.nslices > 0) {
+    // column form of each slice: cbase[2 s] >= 0 two windows, -1 32-bit,
+    // below -1 eight or sixteen windows
+    std::vector<int32_t> cb(2 * L.S.nslices);
+    if (hipMemcpy(cb.data(), L.S.cbase.p, cb.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return MG_ERR_HIP;
+    for (int64_t q = 0; q < L.S.nslices; ++q) {
+      o->sell_slices_multiwindow += cb[2 * q] < -1;
+      o->sell_slices_32bit += cb[2 * q] == -1;
+    }
+  }
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;
   return MG_OK;
