@@ -3,6 +3,7 @@
 // Sec. 6.2).  Host code here only orchestrates: every numerical step of the
 // solve phase is one of the HIP kernels of solve.hip.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -540,6 +541,9 @@ static thread_local std::string g_error;
 
 struct mg_ctx {
   Ctx impl;
+  // per level: slices of the operator's SELL layout in the eight/sixteen-window
+  // and in the 32-bit column forms (counted once at setup, for mg_get_level_info)
+  std::vector<std::array<int64_t, 2>> slice_forms;
 };
 
 template <class T>
@@ -727,6 +731,22 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     c.partial.alloc(pb);
     c.scal.alloc(8 * MG_BLOCK_MAX);
     MG_HIP(hipHostMalloc((void **)&c.h_scal, 8 * MG_BLOCK_MAX * sizeof(double), hipHostMallocDefault));
+    // column form of each slice: cbase[2 s] >= 0 two windows, -1 32-bit,
+    // below -1 eight or sixteen windows
+    for (const Level &L : c.lv) {
+      std::array<int64_t, 2> f = {0, 0};
+      if (L.S.nslices > 0) {
+        std::vector<int32_t> cb(2 * L.S.nslices);
+        MG_HIP(hipMemcpyAsync(cb.data(), L.S.cbase.p, cb.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              c.stream));
+        MG_HIP(hipStreamSynchronize(c.stream));
+        for (int64_t q = 0; q < L.S.nslices; ++q) {
+          f[0] += cb[2 * q] < -1;
+          f[1] += cb[2 * q] == -1;
+        }
+      }
+      h->slice_forms.push_back(f);
+    }
     MG_HIP(hipStreamSynchronize(c.stream));
     *out = h;
     return MG_OK;
@@ -1062,16 +1082,9 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->patch_fused_colours = 0;
   for (uint8_t f : L.patch.colour_fused) o->patch_fused_colours += f;
   o->sell_slices = L.S.nslices;
-  if (L.S.nslices > 0) {
-    // column form of each slice: cbase[2 s] >= 0 two windows, -1 32-bit,
-    // below -1 eight or sixteen windows
-    std::vector<int32_t> cb(2 * L.S.nslices);
-    if (hipMemcpy(cb.data(), L.S.cbase.p, cb.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
-      return MG_ERR_HIP;
-    for (int64_t q = 0; q < L.S.nslices; ++q) {
-      o->sell_slices_multiwindow += cb[2 * q] < -1;
-      o->sell_slices_32bit += cb[2 * q] == -1;
-    }
+  if (level < (int)h->slice_forms.size()) {
+    o->sell_slices_multiwindow = h->slice_forms[level][0];
+    o->sell_slices_32bit = h->slice_forms[level][1];
   }
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;
