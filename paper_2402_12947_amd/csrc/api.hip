@@ -190,7 +190,11 @@ static void vcycle_zero(Ctx &c, int l, const T *b, T *u) {
     coarse_apply<T>(c.stream, L, b, u);
     return;
   }
-  fill<T>(c.stream, u, L.nfree, T(0));
+  // u = 0; without local correction the first Chebyshev step from zero
+  // reads no u and writes every entry, so the fill is needed only before a
+  // local correction, a Gauss-Seidel sweep or when nothing smooths
+  const bool local = c.opt.local_correction && L.patch.n > 0;
+  if (local || c.opt.global_smoother != MG_SMOOTHER_CHEBYSHEV || c.opt.nu < 1) fill<T>(c.stream, u, L.nfree, T(0));
   smooth<T>(c, l, b, u, c.opt.nu, true);
   T *r = LV<T>::w(L, W_R);
   sell_spmv<T>(c.stream, L.S, u, r, SPMV_RESID, b);
