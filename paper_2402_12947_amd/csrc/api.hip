@@ -90,9 +90,12 @@ void ensure_work(Ctx &c, Level &L) {
 static void time_begin(Ctx &c, int l) {
   if (!c.timing || l != 0) return;
   if (c.events_used == c.events.size()) {
+    // timing only: no system-scope fence when the event is recorded (the
+    // default one writes back and invalidates the caches, which would slow
+    // the kernel that follows); the times are read after a stream sync
     hipEvent_t a, b;
-    MG_HIP(hipEventCreate(&a));
-    MG_HIP(hipEventCreate(&b));
+    MG_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+    MG_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
     c.events.push_back({a, b});
   }
   MG_HIP(hipEventRecord(c.events[c.events_used].first, c.stream));
