@@ -120,6 +120,10 @@ typedef struct {
                                and do not couple to each other runs its local
                                correction as one launch; 0: always three
                                launches (same result bitwise)                 */
+  int32_t use_initial_guess; /* 0: the solvers (mg_pcg_solve and its block and
+                               batch forms, mg_vcycle_solve) start from u = 0
+                               and ignore u on entry; 1: they start from the u
+                               passed in (a warm start)                       */
 } mg_options;
 
 typedef struct {
@@ -197,7 +201,7 @@ enum {
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
  * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
- * patch_fused 1. */
+ * patch_fused 1, use_initial_guess 0. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,
@@ -228,10 +232,12 @@ mg_status mg_smooth(mg_ctx *c, int32_t level, const double *b, double *u, int32_
 mg_status mg_vcycle(mg_ctx *c, const double *b, double *u);
 
 /* CG on A_0 u = b preconditioned by one V-cycle per iteration (Sec. 6.2),
- * from u = 0, stopping when ||b - A u||_2 <= rtol ||b||_2 (Sec. 6) on the
- * recursively updated residual.  st may be NULL.  Returns MG_NOT_CONVERGED if
- * maxit iterations were not enough (u holds the last iterate), or
- * MG_ERR_BREAKDOWN. */
+ * from u = 0 (or from the u passed in when use_initial_guess = 1: r_0 =
+ * b - A u_0), stopping when ||b - A u||_2 <= rtol ||b||_2 (Sec. 6) on the
+ * recursively updated residual; a warm start that already meets the tolerance
+ * returns u unchanged after 0 iterations, and b = 0 returns u = 0.  st may be
+ * NULL.  Returns MG_NOT_CONVERGED if maxit iterations were not enough (u holds
+ * the last iterate), or MG_ERR_BREAKDOWN. */
 mg_status mg_pcg_solve(mg_ctx *c, const double *b, double *u, double rtol, int32_t maxit,
                        mg_solve_stats *st);
 
@@ -242,6 +248,7 @@ mg_status mg_pcg_solve(mg_ctx *c, const double *b, double *u, double rtol, int32
  * stream of the cycle (the smoothers' sparse products, residuals, transfers,
  * patch rows) and of CG is read once per block instead of once per column.
  * A column that has converged keeps its iterate while the others go on.
+ * With use_initial_guess = 1 every column starts from its u[r] on entry.
  * b[r], u[r]: device FP64 vectors of n_free(0); no u[r] may alias another
  * vector.  st (may be NULL) receives nrhs records; solve_ms is the time of the
  * block the column ran in.  Results agree with column-by-column mg_pcg_solve
@@ -252,7 +259,8 @@ mg_status mg_pcg_solve_multi(mg_ctx *c, int32_t nrhs, const double *const *b, do
                              int32_t maxit, mg_solve_stats *st);
 
 /* Multigrid as a stationary solver (Sec. 2, Algorithm alg:mg repeated; the
- * Poisson experiments of Sec. 6.1): from u = 0, u <- Vcycle(A_0, b, u) until
+ * Poisson experiments of Sec. 6.1): from u = 0 (or the u passed in when
+ * use_initial_guess = 1), u <- Vcycle(A_0, b, u) until
  * ||b - A u||_2 <= rtol ||b||_2 (the residual recomputed after every cycle) or
  * maxit cycles.  st (may be NULL): iterations = cycles, history = relative
  * residual after each cycle.  Returns MG_NOT_CONVERGED if maxit cycles were

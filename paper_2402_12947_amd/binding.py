@@ -40,7 +40,7 @@ class MgOptions(C.Structure):
                 ("use_graph", C.c_int32), ("sell_sigma", C.c_int32), ("stream", C.c_void_p),
                 ("global_smoother", C.c_int32), ("problem", C.c_int32), ("young", C.c_double),
                 ("poisson_ratio", C.c_double), ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32),
-                ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32)]
+                ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32), ("use_initial_guess", C.c_int32)]
 
 
 class MgSolveStats(C.Structure):
@@ -150,7 +150,7 @@ class Solver:
                  eig_tol: float = 1e-8, eig_maxit: int = 200, use_graph: bool = False, sell_sigma: int = 0,
                  global_smoother: str = "chebyshev", problem: str = "poisson", young: float = 6.9e10,
                  poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1, sell_rpl: int = 0,
-                 patch_fused: bool = True):
+                 patch_fused: bool = True, use_initial_guess: bool = False):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -178,6 +178,7 @@ class Solver:
         opt.sell_mask = sell_mask
         opt.sell_rpl = sell_rpl
         opt.patch_fused = int(bool(patch_fused))
+        opt.use_initial_guess = int(bool(use_initial_guess))
         keep: list = []
         arr = (MgMesh * len(meshes))(*[_mesh_struct(m, keep) for m in meshes])
         h = C.c_void_p()

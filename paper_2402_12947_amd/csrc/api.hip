@@ -441,12 +441,19 @@ static bool pcg_block(Ctx &c, int K, int ncols, const double *const *b, double *
   MG_HIP(hipEventRecord(e0, s));
   double *scal = c.scal.p;
   double *h = c.h_scal;
+  const bool warm = c.opt.use_initial_guess != 0;
   fill<double>(s, scal, 8 * K, 0.0);
-  fill<double>(s, c.kx.p, n * K, 0.0);
   gather_block(s, K, bc, L0.perm, c.kb, n);
-  copy64(s, c.kb, c.kr, n * K);
+  if (warm) {  // x_0 = u (padding columns zero), r_0 = b - A x_0
+    gather_block(s, K, uc, L0.perm, c.kx, n);
+    sell_spmv_block<double>(s, L0.S, K, c.kx, c.kr, SPMV_RESID, c.kb);
+    dot_block_to(c, K, c.kr, c.kr, n, scal + 3 * K);
+  } else {
+    fill<double>(s, c.kx.p, n * K, 0.0);
+    copy64(s, c.kb, c.kr, n * K);
+  }
   dot_block_to(c, K, c.kb, c.kb, n, scal + 7 * K);
-  MG_HIP(hipMemcpyAsync(h, scal + 7 * K, K * sizeof(double), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipMemcpyAsync(h, scal, 8 * K * sizeof(double), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   double bnorm[MG_BLOCK_MAX], rel[MG_BLOCK_MAX];
   int iters[MG_BLOCK_MAX] = {};
@@ -454,10 +461,10 @@ static bool pcg_block(Ctx &c, int K, int ncols, const double *const *b, double *
   std::vector<double> hist[MG_BLOCK_MAX];
   unsigned mask = 0;
   for (int q = 0; q < K; ++q) {
-    bnorm[q] = std::sqrt(h[q]);
-    rel[q] = bnorm[q] > 0 ? 1.0 : 0.0;
+    bnorm[q] = std::sqrt(h[7 * K + q]);
+    rel[q] = bnorm[q] > 0 ? (warm ? std::sqrt(h[3 * K + q]) / bnorm[q] : 1.0) : 0.0;
     hist[q].push_back(rel[q]);
-    conv[q] = bnorm[q] == 0.0;
+    conv[q] = bnorm[q] == 0.0 || rel[q] <= rtol;
     if (!conv[q]) mask |= 1u << q;
   }
   int it = 0, broken = -1;
@@ -499,6 +506,8 @@ static bool pcg_block(Ctx &c, int K, int ncols, const double *const *b, double *
     }
   }
   scatter_block(s, K, c.kx, L0.perm, uc, n);
+  for (int q = 0; q < ncols; ++q)  // b = 0: u = 0 whatever the start
+    if (bnorm[q] == 0.0 && warm) fill<double>(s, uc[q], n, 0.0);
   MG_HIP(hipEventRecord(e1, s));
   MG_HIP(hipEventSynchronize(e1));
   float tms = 0;
@@ -583,6 +592,7 @@ void mg_default_options(mg_options *o) {
   o->sell_mask = -1;
   o->sell_rpl = 0;
   o->patch_fused = 1;
+  o->use_initial_guess = 0;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
   o->problem = MG_PROBLEM_POISSON;
   o->young = 6.9e10;
@@ -644,6 +654,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.sell_rpl != 0 && o.sell_rpl != 1 && o.sell_rpl != 2 && o.sell_rpl != 4 && o.sell_rpl != 8)
       fail(MG_ERR_ARG, "sell_rpl must be 0, 1, 2, 4 or 8");
     if (o.patch_fused != 0 && o.patch_fused != 1) fail(MG_ERR_ARG, "patch_fused must be 0 or 1");
+    if (o.use_initial_guess != 0 && o.use_initial_guess != 1) fail(MG_ERR_ARG, "use_initial_guess must be 0 or 1");
     for (int l = 0; l < n_levels; ++l) validate_mesh(levels[l], dim, l);
     h = new mg_ctx();
     Ctx &c = h->impl;
@@ -834,17 +845,28 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
   MG_HIP(hipEventRecord(e0, s));
   double *scal = c.scal.p;
   double *x = c.xpos.p;
+  const bool warm = c.opt.use_initial_guess != 0;
   fill<double>(s, scal, 8, 0.0);
-  fill<double>(s, x, n, 0.0);
   gather_perm<double, double>(s, b, L0.perm, c.bpos, n);
-  copy64(s, c.bpos, c.r, n);
+  if (warm) {  // x_0 = u, r_0 = b - A x_0
+    gather_perm<double, double>(s, u, L0.perm, x, n);
+    sell_spmv<double>(s, L0.S, x, c.r, SPMV_RESID, c.bpos);
+  } else {
+    fill<double>(s, x, n, 0.0);
+    copy64(s, c.bpos, c.r, n);
+  }
   dot_to(c, c.bpos, c.bpos, n, scal + 7);
   double bb = read_scalar(c, scal + 7);
   double bnorm = std::sqrt(bb);
-  std::vector<double> hist{bnorm > 0 ? 1.0 : 0.0};
-  int it = 0;
-  bool converged = bnorm == 0.0, breakdown = false;
   double rel = bnorm > 0 ? 1.0 : 0.0;
+  if (warm && bnorm > 0) {
+    dot_to(c, c.r, c.r, n, scal + 3);
+    rel = std::sqrt(read_scalar(c, scal + 3)) / bnorm;
+  }
+  if (bnorm == 0.0) fill<double>(s, x, n, 0.0);  // b = 0: u = 0 whatever the start
+  std::vector<double> hist{rel};
+  int it = 0;
+  bool converged = bnorm == 0.0 || rel <= rtol, breakdown = false;
   if (!converged) {
     precondition(c);
     copy64(s, c.z, c.p, n);
@@ -957,15 +979,27 @@ mg_status mg_vcycle_solve(mg_ctx *h, const double *b, double *u, double rtol, in
   MG_HIP(hipEventRecord(e0, s));
   double *scal = c.scal.p;
   double *x = c.xpos.p;
-  fill<double>(s, x, n, 0.0);
+  const bool warm = c.opt.use_initial_guess != 0;
   gather_perm<double, double>(s, b, L0.perm, c.bpos, n);
-  copy64(s, c.bpos, c.r, n);
+  if (warm) {
+    gather_perm<double, double>(s, u, L0.perm, x, n);
+  } else {
+    fill<double>(s, x, n, 0.0);
+    copy64(s, c.bpos, c.r, n);
+  }
   dot_to(c, c.bpos, c.bpos, n, scal + 7);
   const double bnorm = std::sqrt(read_scalar(c, scal + 7));
-  std::vector<double> hist{bnorm > 0 ? 1.0 : 0.0};
-  int it = 0;
   double rel = bnorm > 0 ? 1.0 : 0.0;
-  bool converged = rel <= rtol, bad = false;
+  if (bnorm == 0.0) {
+    fill<double>(s, x, n, 0.0);  // b = 0: u = 0 whatever the start
+  } else if (warm) {
+    sell_spmv<double>(s, L0.S, x, c.r, SPMV_RESID, c.bpos);
+    dot_to(c, c.r, c.r, n, scal + 7);
+    rel = std::sqrt(read_scalar(c, scal + 7)) / bnorm;
+  }
+  std::vector<double> hist{rel};
+  int it = 0;
+  bool converged = bnorm == 0.0 || rel <= rtol, bad = false;
   // x <- x + B (b - A x): one V-cycle per iteration (the cycle is affine in
   // its initial guess), then the residual of the new iterate
   while (!converged && it < maxit) {

@@ -39,6 +39,7 @@ def test_default_options_are_the_papers():
     assert (o.degree, o.nu, o.cheb_degree, o.local_correction, o.adjusted_eig) == (1, 2, 2, 1, 1)
     assert o.cheb_lo_frac == 0.1 and o.eig_tol == 1e-8 and o.eig_maxit == 200
     assert (o.sell_sigma, o.sell_unroll, o.sell_mask, o.sell_rpl, o.patch_fused) == (0, 0, -1, 0, 1)
+    assert o.use_initial_guess == 0
 
 
 def test_setup_rejects_bad_input_on_host():
