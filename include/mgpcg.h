@@ -231,6 +231,27 @@ mg_status mg_smooth(mg_ctx *c, int32_t level, const double *b, double *u, int32_
 /* u <- Vcycle(A_0, b, u) (Algorithm alg:mg) on level 0 from the given u. */
 mg_status mg_vcycle(mg_ctx *c, const double *b, double *u);
 
+/* Allocation-free form of mg_vcycle, for callers that cannot allocate device
+ * memory: code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It computes the same cycle as mg_vcycle (bitwise the same
+ * u) but keeps its four level-0 staging vectors (b and u in the solve order,
+ * the residual, the correction) in one static device array of the library,
+ * MG_NOALLOC_SCRATCH_BYTES per GPU, created when the library is loaded and
+ * held until the process ends; it calls no allocating routine and does not
+ * synchronise: the cycle is enqueued on the context's stream and u is valid
+ * once that stream has run it.  The cycle runs eagerly (no captured graph)
+ * and without kernel timing.  Limit: n_free(0) <= MG_NOALLOC_MAX_UNKNOWNS,
+ * else MG_ERR_LIMIT.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (nothing in it needs to start at zero: every
+ * entry a call reads was written earlier in the same call): calls ordered on
+ * one stream are safe, calls that overlap in time on one GPU (contexts on
+ * different streams, several host threads) race and give undefined results.
+ * b, u: device FP64 vectors of n_free(0); b must not alias u.
+ * Errors: MG_ERR_ARG, MG_ERR_LIMIT, MG_ERR_HIP. */
+#define MG_NOALLOC_MAX_UNKNOWNS 1048576
+#define MG_NOALLOC_SCRATCH_BYTES (4 * 8 * MG_NOALLOC_MAX_UNKNOWNS)
+mg_status mg_vcycle_noalloc(mg_ctx *c, const double *b, double *u);
+
 /* CG on A_0 u = b preconditioned by one V-cycle per iteration (Sec. 6.2),
  * from u = 0 (or from the u passed in when use_initial_guess = 1: r_0 =
  * b - A u_0), stopping when ||b - A u||_2 <= rtol ||b||_2 (Sec. 6) on the

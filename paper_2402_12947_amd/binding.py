@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                C.POINTER(P)]),
         "mg_smooth": (C.c_int, [P, C.c_int32, P, P, C.c_int32]),
         "mg_vcycle": (C.c_int, [P, P, P]),
+        "mg_vcycle_noalloc": (C.c_int, [P, P, P]),
         "mg_pcg_solve": (C.c_int, [P, P, P, C.c_double, C.c_int32, C.POINTER(MgSolveStats)]),
         "mg_vcycle_solve": (C.c_int, [P, P, P, C.c_double, C.c_int32, C.POINTER(MgSolveStats)]),
         "mg_pcg_solve_multi": (C.c_int, [P, C.c_int32, C.POINTER(P), C.POINTER(P), C.c_double, C.c_int32,
@@ -267,6 +268,14 @@ class Solver:
     def vcycle(self, b, u):
         _sync()
         self._check(lib().mg_vcycle(self._h, _ptr(b), _ptr(u)))
+
+    def vcycle_noalloc(self, b, u):
+        """mg_vcycle_noalloc: the cycle with its staging vectors in the
+        library's static device array; it returns without synchronising, so
+        the device is synchronised here before u is handed back."""
+        _sync()
+        self._check(lib().mg_vcycle_noalloc(self._h, _ptr(b), _ptr(u)))
+        _sync()
 
     def pcg(self, b, u, rtol: float = 1e-8, maxit: int = 500) -> dict:
         _sync()

@@ -11,6 +11,8 @@
 #include <thread>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 #include "mg_internal.h"
 
@@ -543,6 +545,33 @@ using namespace mg;
 
 static thread_local std::string g_error;
 
+// Staging vectors of mg_vcycle_noalloc: one static device array per GPU,
+// created with the code object and held until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: host code
+// uses only the device address that hipGetSymbolAddress returns for the
+// current device (resolve_noalloc, called by mg_setup), never the name.
+static __device__ __align__(256) double scratch[MG_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+static std::mutex g_noalloc_mu;
+static std::unordered_map<int, double *> g_noalloc_ptr;  // device -> address of its array
+
+// address of `scratch` on `device`, which must be the current device; looked
+// up once per device
+static double *resolve_noalloc(int device) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(device);
+  if (it != g_noalloc_ptr.end()) return it->second;
+  double *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&ptr), HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    fail(MG_ERR_HIP, "hipGetSymbolAddress of the static staging array failed on device %d: %s", device,
+         hipGetErrorString(e));
+  }
+  g_noalloc_ptr.emplace(device, ptr);
+  return ptr;
+}
+
 #define MG_API_BEGIN try {
 #define MG_API_END(ctxp)                                        \
   }                                                             \
@@ -667,6 +696,8 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       MG_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
       c.own_stream = true;
     }
+    MG_HIP(hipGetDevice(&c.device));
+    c.noalloc = resolve_noalloc(c.device);
     c.lv.resize(n_levels);
     const bool mixed = o.precision == MG_MIXED;
     auto now = [] { return std::chrono::steady_clock::now(); };
@@ -820,6 +851,41 @@ mg_status mg_vcycle(mg_ctx *h, const double *b, double *u) {
   add64(c.stream, c.xpos, c.z, L0.nfree);
   scatter_perm<double, double>(c.stream, c.xpos, L0.perm, u, L0.nfree);
   MG_HIP(hipStreamSynchronize(c.stream));
+  return MG_OK;
+  MG_API_END(cp)
+}
+
+mg_status mg_vcycle_noalloc(mg_ctx *h, const double *b, double *u) {
+  Ctx *cp = h ? &h->impl : nullptr;
+  MG_API_BEGIN
+  if (!h || !b || !u) fail(MG_ERR_ARG, "NULL argument");
+  Ctx &c = h->impl;
+  if (b == u) fail(MG_ERR_ARG, "b must not alias u");
+  Level &L0 = c.lv[0];
+  const int64_t n = L0.nfree;
+  if (n > MG_NOALLOC_MAX_UNKNOWNS)
+    fail(MG_ERR_LIMIT, "mg_vcycle_noalloc: level 0 has %lld unknowns, its static staging array holds %d",
+         (long long)n, MG_NOALLOC_MAX_UNKNOWNS);
+  if (!c.noalloc) fail(MG_ERR_HIP, "mg_vcycle_noalloc: no staging array on device %d", c.device);
+  // four vectors, each starting on a 512-byte boundary: 4 * stride <= the
+  // array's length whenever n <= MG_NOALLOC_MAX_UNKNOWNS
+  const int64_t stride = (n + 63) / 64 * 64;
+  double *bpos = c.noalloc, *xpos = bpos + stride, *r = xpos + stride, *z = r + stride;
+  // no timing events (creating one may allocate) and no graph (it is bound
+  // to the context's own buffers): the eager cycle, with the kernels and
+  // arguments of mg_vcycle apart from these four addresses
+  struct NoTiming {
+    Ctx &c;
+    bool was;
+    ~NoTiming() { c.timing = was; }
+  } keep{c, c.timing};
+  c.timing = false;
+  gather_perm<double, double>(c.stream, b, L0.perm, bpos, n);
+  gather_perm<double, double>(c.stream, u, L0.perm, xpos, n);
+  sell_spmv<double>(c.stream, L0.S, xpos, r, SPMV_RESID, bpos);
+  precondition_eager(c, r, z);
+  add64(c.stream, xpos, z, n);
+  scatter_perm<double, double>(c.stream, xpos, L0.perm, u, n);
   return MG_OK;
   MG_API_END(cp)
 }

@@ -258,6 +258,8 @@ struct Ctx {
   int layers = 1;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;                  // device current at setup
+  double *noalloc = nullptr;       // that device's static staging array (mg_vcycle_noalloc)
   std::vector<Level> lv;
   std::string err;
   // PCG work (FP64, level 0, solve order)
