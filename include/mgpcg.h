@@ -124,6 +124,15 @@ typedef struct {
                                batch forms, mg_vcycle_solve) start from u = 0
                                and ignore u on entry; 1: they start from the u
                                passed in (a warm start)                       */
+  int32_t sell_layout_levels; /* number of levels that sell_layout covers      */
+  const int32_t *sell_layout; /* NULL, or host [4 * sell_layout_levels]: for
+                               level l the values (sigma, unroll, mask, rpl)
+                               that fix that level operator's layout as
+                               sell_sigma, sell_unroll, sell_mask and sell_rpl
+                               do for every level (0, 0, -1, 0 leave the choice
+                               to the autotuner); copied by mg_setup.  Lets a
+                               measurement repeat the layouts of an earlier
+                               run, whose choices mg_level_info reports      */
 } mg_options;
 
 typedef struct {
@@ -201,7 +210,7 @@ enum {
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
  * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
- * patch_fused 1, use_initial_guess 0. */
+ * patch_fused 1, use_initial_guess 0, sell_layout_levels 0, sell_layout NULL. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,
@@ -316,12 +325,18 @@ mg_status mg_get_level_info(const mg_ctx *c, int32_t level, mg_level_info *out);
  * must be large enough (sizes above, from mg_get_level_info). */
 mg_status mg_get_array(const mg_ctx *c, int32_t level, int32_t what, void *out);
 
-/* Device-event timing of the level-0 Chebyshev step kernel: when enabled,
- * every launch of that kernel on the context's stream is bracketed by HIP
- * events; mg_kernel_time returns the number of launches since enabling and
- * their summed duration in milliseconds (synchronises the stream). */
+/* Device-event timing of the solve phase: when enabled (and until disabled),
+ * every launch of the full Chebyshev step kernel on each level, and every
+ * coarsest solve (the product with the coarsest level's stored inverse), is
+ * bracketed by HIP events on the context's stream, and the V-cycle runs
+ * eagerly even when use_graph = 1.  mg_level_kernel_time returns, for one
+ * level, the number of such launches since enabling and their summed
+ * duration in milliseconds (level < coarsest: Chebyshev steps; level =
+ * coarsest: coarsest solves); mg_kernel_time is its level-0 form.  Both
+ * synchronise the stream.  Enabling again resets the sums. */
 mg_status mg_enable_kernel_timing(mg_ctx *c, int32_t enable);
 mg_status mg_kernel_time(mg_ctx *c, int64_t *launches, double *total_ms);
+mg_status mg_level_kernel_time(mg_ctx *c, int32_t level, int64_t *launches, double *total_ms);
 
 /* Bytes one launch of the level-0 Chebyshev step kernel must move at least:
  * matrix values and column indices once ((v + 2) bytes per entry stored with a

@@ -40,7 +40,8 @@ class MgOptions(C.Structure):
                 ("use_graph", C.c_int32), ("sell_sigma", C.c_int32), ("stream", C.c_void_p),
                 ("global_smoother", C.c_int32), ("problem", C.c_int32), ("young", C.c_double),
                 ("poisson_ratio", C.c_double), ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32),
-                ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32), ("use_initial_guess", C.c_int32)]
+                ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32), ("use_initial_guess", C.c_int32),
+                ("sell_layout_levels", C.c_int32), ("sell_layout", C.POINTER(C.c_int32))]
 
 
 class MgSolveStats(C.Structure):
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mg_get_array": (C.c_int, [P, C.c_int32, C.c_int32, P]),
         "mg_enable_kernel_timing": (C.c_int, [P, C.c_int32]),
         "mg_kernel_time": (C.c_int, [P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+        "mg_level_kernel_time": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
         "mg_cheb_algorithmic_bytes": (C.c_int, [P, C.POINTER(C.c_double)]),
         "mg_stream_probe": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, C.POINTER(C.c_double)]),
         "mg_last_error": (C.c_char_p, [P]),
@@ -151,7 +153,7 @@ class Solver:
                  eig_tol: float = 1e-8, eig_maxit: int = 200, use_graph: bool = False, sell_sigma: int = 0,
                  global_smoother: str = "chebyshev", problem: str = "poisson", young: float = 6.9e10,
                  poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1, sell_rpl: int = 0,
-                 patch_fused: bool = True, use_initial_guess: bool = False):
+                 patch_fused: bool = True, use_initial_guess: bool = False, sell_layout=None):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -181,6 +183,11 @@ class Solver:
         opt.patch_fused = int(bool(patch_fused))
         opt.use_initial_guess = int(bool(use_initial_guess))
         keep: list = []
+        if sell_layout:  # [(sigma, unroll, mask, rpl) per level]
+            lay = np.ascontiguousarray(np.asarray(sell_layout, dtype=np.int32).reshape(-1, 4))
+            keep.append(lay)
+            opt.sell_layout_levels = lay.shape[0]
+            opt.sell_layout = lay.ctypes.data_as(C.POINTER(C.c_int32))
         arr = (MgMesh * len(meshes))(*[_mesh_struct(m, keep) for m in meshes])
         h = C.c_void_p()
         st = L.mg_setup(arr, len(meshes), tau, layers, C.byref(opt), C.byref(h))
@@ -322,10 +329,13 @@ class Solver:
     def enable_kernel_timing(self, on: bool = True):
         self._check(lib().mg_enable_kernel_timing(self._h, int(on)))
 
-    def kernel_time(self):
+    def kernel_time(self, level: int = 0):
+        """(launches, summed ms) of the timed kernels of `level` since timing
+        was enabled: full Chebyshev steps, or the coarsest solves on the
+        coarsest level."""
         n = C.c_int64()
         t = C.c_double()
-        self._check(lib().mg_kernel_time(self._h, C.byref(n), C.byref(t)))
+        self._check(lib().mg_level_kernel_time(self._h, level, C.byref(n), C.byref(t)))
         return n.value, t.value
 
     def cheb_bytes(self) -> float:

@@ -89,8 +89,10 @@ void ensure_work(Ctx &c, Level &L) {
 // ---------------------------------------------------------------------------
 // smoother and V-cycle
 // ---------------------------------------------------------------------------
-static void time_begin(Ctx &c, int l) {
-  if (!c.timing || l != 0) return;
+// slot: the level of a full Chebyshev step, or the coarsest level's index
+// for the coarsest solve
+static void time_begin(Ctx &c, int slot) {
+  if (!c.timing) return;
   if (c.events_used == c.events.size()) {
     // timing only: no system-scope fence when the event is recorded (the
     // default one writes back and invalidates the caches, which would slow
@@ -99,11 +101,13 @@ static void time_begin(Ctx &c, int l) {
     MG_HIP(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
     MG_HIP(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
     c.events.push_back({a, b});
+    c.event_slot.push_back(0);
   }
+  c.event_slot[c.events_used] = slot;
   MG_HIP(hipEventRecord(c.events[c.events_used].first, c.stream));
 }
-static void time_end(Ctx &c, int l) {
-  if (!c.timing || l != 0) return;
+static void time_end(Ctx &c) {
+  if (!c.timing) return;
   MG_HIP(hipEventRecord(c.events[c.events_used].second, c.stream));
   ++c.events_used;
 }
@@ -147,7 +151,7 @@ static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt, bool zero_start
   } else {
     time_begin(c, l);
     cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, k == 1 ? 3 : 1, 0.0, 1.0 / theta);
-    time_end(c, l);
+    time_end(c);
   }
   std::swap(u, alt);
   for (int j = 1; j < k; ++j) {
@@ -155,7 +159,7 @@ static void chebyshev(Ctx &c, int l, const T *b, T *&u, T *&alt, bool zero_start
     time_begin(c, l);
     cheb_step<T>(c.stream, L.S, LV<T>::dinv(L), b, u, alt, d, j == k - 1 ? 2 : 0, rho_new * rho,
                  2.0 * rho_new / delta);
-    time_end(c, l);
+    time_end(c);
     std::swap(u, alt);
     rho = rho_new;
   }
@@ -192,7 +196,9 @@ template <class T>
 static void vcycle_zero(Ctx &c, int l, const T *b, T *u) {
   Level &L = c.lv[l];
   if (L.coarsest) {
+    time_begin(c, l);
     coarse_apply<T>(c.stream, L, b, u);
+    time_end(c);
     return;
   }
   // u = 0; without local correction the first Chebyshev step from zero
@@ -622,6 +628,8 @@ void mg_default_options(mg_options *o) {
   o->sell_rpl = 0;
   o->patch_fused = 1;
   o->use_initial_guess = 0;
+  o->sell_layout_levels = 0;
+  o->sell_layout = nullptr;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
   o->problem = MG_PROBLEM_POISSON;
   o->young = 6.9e10;
@@ -684,10 +692,22 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       fail(MG_ERR_ARG, "sell_rpl must be 0, 1, 2, 4 or 8");
     if (o.patch_fused != 0 && o.patch_fused != 1) fail(MG_ERR_ARG, "patch_fused must be 0 or 1");
     if (o.use_initial_guess != 0 && o.use_initial_guess != 1) fail(MG_ERR_ARG, "use_initial_guess must be 0 or 1");
+    if (o.sell_layout_levels < 0 || (o.sell_layout_levels > 0 && !o.sell_layout))
+      fail(MG_ERR_ARG, "sell_layout must hold 4 values for each of sell_layout_levels levels");
+    for (int l = 0; l < o.sell_layout_levels; ++l) {
+      const int32_t *q = o.sell_layout + 4 * l;
+      if (q[0] < 0 || (q[0] > 1 && q[0] % SELL_C) || (q[1] != 0 && q[1] != 4 && q[1] != 8) || q[2] < -1 ||
+          q[2] > 1 || (q[3] != 0 && q[3] != 1 && q[3] != 2 && q[3] != 4 && q[3] != 8))
+        fail(MG_ERR_ARG, "sell_layout of level %d: (sigma, unroll, mask, rpl) must each be a value the "
+                         "options sell_sigma, sell_unroll, sell_mask, sell_rpl accept", l);
+    }
     for (int l = 0; l < n_levels; ++l) validate_mesh(levels[l], dim, l);
     h = new mg_ctx();
     Ctx &c = h->impl;
     c.opt = o;
+    if (o.sell_layout_levels > 0) c.layout.assign(o.sell_layout, o.sell_layout + 4 * o.sell_layout_levels);
+    c.opt.sell_layout = nullptr;  // the caller's array is not kept
+    c.opt.sell_layout_levels = 0;
     c.tau = quality_threshold;
     c.layers = patch_layers;
     if (o.stream) {
@@ -738,7 +758,21 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     for (int l = 0; l < n_levels; ++l) {
       auto t0 = now();
       Level &L = c.lv[l];
-      solve_order(c, L, L.coarsest ? 1 : c.opt.sell_sigma, mixed && !L.coarsest);
+      {
+        // a fixed per-level layout stands in for the global options while
+        // this level's operator layout is chosen
+        const mg_options keep = c.opt;
+        int sigma = c.opt.sell_sigma;
+        if (4 * l + 3 < (int)c.layout.size()) {
+          const int32_t *q = &c.layout[4 * l];
+          if (q[0]) sigma = q[0];
+          if (q[1]) c.opt.sell_unroll = q[1];
+          if (q[2] >= 0) c.opt.sell_mask = q[2];
+          if (q[3]) c.opt.sell_rpl = q[3];
+        }
+        solve_order(c, L, L.coarsest ? 1 : sigma, mixed && !L.coarsest);
+        c.opt = keep;
+      }
       permute_patches(c, L);
       if (!L.coarsest) {
         build_patch_rows(c, L, mixed);
@@ -1238,26 +1272,38 @@ mg_status mg_enable_kernel_timing(mg_ctx *h, int32_t enable) {
   Ctx &c = h->impl;
   c.timing = enable != 0;
   c.events_used = 0;
-  c.timed_launches = 0;
-  c.timed_ms = 0;
+  c.timed_launches.assign(c.lv.size(), 0);
+  c.timed_ms.assign(c.lv.size(), 0.0);
   return MG_OK;
 }
 
+// folds the recorded event pairs into the per-slot sums
+static void collect_times(Ctx &c) {
+  MG_HIP(hipStreamSynchronize(c.stream));
+  c.timed_launches.resize(c.lv.size(), 0);
+  c.timed_ms.resize(c.lv.size(), 0.0);
+  for (size_t k = 0; k < c.events_used; ++k) {
+    float t = 0;
+    MG_HIP(hipEventElapsedTime(&t, c.events[k].first, c.events[k].second));
+    c.timed_ms[c.event_slot[k]] += t;
+    ++c.timed_launches[c.event_slot[k]];
+  }
+  c.events_used = 0;
+}
+
 mg_status mg_kernel_time(mg_ctx *h, int64_t *launches, double *total_ms) {
+  return mg_level_kernel_time(h, 0, launches, total_ms);
+}
+
+mg_status mg_level_kernel_time(mg_ctx *h, int32_t level, int64_t *launches, double *total_ms) {
   Ctx *cp = h ? &h->impl : nullptr;
   MG_API_BEGIN
   if (!h || !launches || !total_ms) fail(MG_ERR_ARG, "NULL argument");
   Ctx &c = h->impl;
-  MG_HIP(hipStreamSynchronize(c.stream));
-  for (size_t k = 0; k < c.events_used; ++k) {
-    float t = 0;
-    MG_HIP(hipEventElapsedTime(&t, c.events[k].first, c.events[k].second));
-    c.timed_ms += t;
-    ++c.timed_launches;
-  }
-  c.events_used = 0;
-  *launches = c.timed_launches;
-  *total_ms = c.timed_ms;
+  if (level < 0 || level >= (int)c.lv.size()) fail(MG_ERR_ARG, "no level %d", level);
+  collect_times(c);
+  *launches = c.timed_launches[level];
+  *total_ms = c.timed_ms[level];
   return MG_OK;
   MG_API_END(cp)
 }

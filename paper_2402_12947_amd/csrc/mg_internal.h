@@ -258,6 +258,7 @@ struct Ctx {
   int layers = 1;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  std::vector<int32_t> layout;     // per-level fixed layout choices (4 per level)
   int device = 0;                  // device current at setup
   double *noalloc = nullptr;       // that device's static staging array (mg_vcycle_noalloc)
   std::vector<Level> lv;
@@ -273,9 +274,10 @@ struct Ctx {
   // kernel timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  std::vector<int> event_slot;          // level of each event pair
   size_t events_used = 0;
-  int64_t timed_launches = 0;
-  double timed_ms = 0;
+  std::vector<int64_t> timed_launches;  // per level
+  std::vector<double> timed_ms;
   // captured V-cycle graph
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;

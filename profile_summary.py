@@ -6,9 +6,12 @@
 
   python profile_summary.py counters <fetch_counter_collection.csv> <write_counter_collection.csv>
                             <out.json> <out.md> <kernel> <algorithmic_bytes> "<fetch cmd>" "<write cmd>"
-      FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the largest-grid launches of
-      the kernels whose name matches the regular expression <kernel>, each scaled by the factor that maps the same counter, read on a
-      1 GiB read + 1 GiB write elementwise kernel, to its known byte count.
+                            [grid] [title]
+      FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the launches of the kernels
+      whose name matches the regular expression <kernel> with the given grid
+      (default: the largest grid), each scaled by the factor that maps the same
+      counter, read on a 1 GiB read + 1 GiB write elementwise kernel, to its
+      known byte count.
 
   python profile_summary.py mfma <counter_collection.csv> <out.md> "<command>" "<title>"
       FP64 matrix-core work per dispatch (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512
@@ -49,9 +52,10 @@ def trace(path, out, cmd, title, note=""):
           "## All kernels by total time", "", "| kernel | calls | total ms | avg us |", "|---|---|---|---|"]
     for name, v in sorted(byname.items(), key=lambda kv: -sum(kv[1]))[:30]:
         L.append(f"| `{name}` | {len(v)} | {sum(v) / 1e3:.2f} | {statistics.mean(v):.1f} |")
-    L += ["", "## Solve-phase kernels by launch size (grid = threads; one grid size per level)", "",
+    L += ["", "## Solve-phase kernels by launch size (grid = threads; one grid size per level; the 40 largest "
+              "totals)", "",
           "| kernel | grid | calls | total ms | avg us | min us | max us |", "|---|---|---|---|---|---|---|"]
-    for (name, grid), v in sorted(bygrid.items(), key=lambda kv: -sum(kv[1])):
+    for (name, grid), v in sorted(bygrid.items(), key=lambda kv: -sum(kv[1]))[:40]:
         L.append(f"| `{name}` | {grid} | {len(v)} | {sum(v) / 1e3:.2f} | {statistics.mean(v):.1f} | "
                  f"{min(v):.1f} | {max(v):.1f} |")
     open(out, "w").write("\n".join(L) + "\n")
@@ -72,11 +76,12 @@ def _per_dispatch(path, counter):
     return out
 
 
-def _kernel_and_calibration(path, counter, kernel):
+def _kernel_and_calibration(path, counter, kernel, grid=None):
     d = _per_dispatch(path, counter)
     ks = [(g, v) for (n, g, v) in d.values() if re.search(kernel, n)]
-    gmax = max(g for g, _ in ks)
+    gmax = max(g for g, _ in ks) if grid is None else grid
     vals = [v for g, v in ks if g == gmax]
+    assert vals, f"no launch of {kernel} with grid {gmax}"
     cal = [v for (n, g, v) in d.values() if "MulFunctor" in n and g * 1 >= (1 << 25)]
     return gmax, vals, cal
 
@@ -86,10 +91,12 @@ def source_hash():
     return kernel_source_hash()
 
 
-def counters(fetch_csv, write_csv, out_json, out_md, kernel, alg_bytes, fetch_cmd, write_cmd):
+def counters(fetch_csv, write_csv, out_json, out_md, kernel, alg_bytes, fetch_cmd, write_cmd, grid=None,
+             title=None):
     alg_bytes = float(alg_bytes)
-    gf, fv, fcal = _kernel_and_calibration(fetch_csv, "FETCH_SIZE", kernel)
-    gw, wv, wcal = _kernel_and_calibration(write_csv, "WRITE_SIZE", kernel)
+    grid = int(grid) if grid else None
+    gf, fv, fcal = _kernel_and_calibration(fetch_csv, "FETCH_SIZE", kernel, grid)
+    gw, wv, wcal = _kernel_and_calibration(write_csv, "WRITE_SIZE", kernel, grid)
     assert gf == gw and fcal and wcal, "kernel or calibration launches missing"
     f_factor = CALIBRATION_BYTES / (statistics.median(fcal) * 1024)
     w_factor = CALIBRATION_BYTES / (statistics.median(wcal) * 1024)
@@ -103,7 +110,8 @@ def counters(fetch_csv, write_csv, out_json, out_md, kernel, alg_bytes, fetch_cm
          "traffic_over_algorithmic": (fetch_b + write_b) / alg_bytes,
          "kernel_source_hash": source_hash(), "command_fetch": fetch_cmd, "command_write": write_cmd}
     json.dump(d, open(out_json, "w"), indent=1)
-    L = [f"# HBM traffic of `{kernel}` (largest grid, {gf} threads)", "",
+    L = [f"# {title}" if title else f"# HBM traffic of `{kernel}` (largest grid, {gf} threads)", "",
+         f"Launches of the kernels matching `{kernel}` with a grid of {gf} threads.", "",
          "Commands (from the repository root, one MI355X):", "", "```", fetch_cmd, write_cmd, "```", "",
          "| quantity | value |", "|---|---|",
          f"| FETCH_SIZE per launch (raw, KiB) | {d['fetch_kib_per_launch_raw']:.0f} ({len(fv)} launches) |",
@@ -113,7 +121,10 @@ def counters(fetch_csv, write_csv, out_json, out_md, kernel, alg_bytes, fetch_cm
          f"| scale factors fetch / write | {f_factor:.4f} / {w_factor:.4f} |",
          f"| HBM bytes per launch (scaled) | {fetch_b + write_b:.4e} |",
          f"| algorithmic bytes per launch | {alg_bytes:.4e} |",
-         f"| traffic / algorithmic | {d['traffic_over_algorithmic']:.3f} |", ""]
+         f"| traffic / algorithmic | {d['traffic_over_algorithmic']:.3f} |", "",
+         "WRITE_SIZE counts the lines the L2 writes back during the dispatch; lines still dirty in the L2 "
+         "when the kernel ends (at most the 8 x 4 MB of L2) are written back later and counted with a later "
+         "dispatch, so the write figure can fall short of the bytes the kernel stores.", ""]
     open(out_md, "w").write("\n".join(L) + "\n")
     print(json.dumps(d))
 

@@ -67,6 +67,11 @@ def test_setup_rejects_bad_input_on_host():
     assert setup_status([mesh], sell_unroll=16)[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_mask=2)[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_rpl=3)[0] == MG_ERR_ARG
+    # per-level layouts follow the same rules as the global layout options
+    assert setup_status([mesh], sell_layout=[[100, 0, -1, 0]])[0] == MG_ERR_ARG
+    assert setup_status([mesh], sell_layout=[[0, 16, -1, 0]])[0] == MG_ERR_ARG
+    assert setup_status([mesh], sell_layout=[[0, 0, 2, 0]])[0] == MG_ERR_ARG
+    assert setup_status([mesh], sell_layout=[[0, 0, -1, 0], [1, 8, 1, 3]])[0] == MG_ERR_ARG
 
 
 def test_binding_requires_built_library(tmp_path):

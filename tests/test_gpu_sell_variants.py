@@ -103,3 +103,32 @@ def test_fused_patch_correction_agrees_bitwise(precision, scale, one_launch):
         s.close()
     assert np.array_equal(out[True][0], out[False][0])
     assert np.array_equal(out[True][1], out[False][1]) and out[True][2] == out[False][2]
+
+
+def test_per_level_layout_is_repeated():
+    """sell_layout fixes each level operator's layout: a hierarchy built with
+    the layouts another run's autotuner chose reports the same choices and
+    gives the same cycle to rounding (the transfer products are still chosen
+    by timing, and their gathers in flight set the order of a few sums)."""
+    from paper_2402_12947_amd import Solver
+    meshes = meshgen.hierarchy("square_1025", seed=0, scale=4)
+    print("[case square_1025/4 P2 layouts]", flush=True)
+    a = Solver(meshes, degree=2, layers=1)
+    keys = ("sell_sigma", "sell_unroll", "sell_mask", "sell_rpl")
+    la = [[a.level_info(l)[k] for k in keys] for l in range(a.n_levels - 1)]
+    n = a.n_free(0)
+    b = to_dev(meshgen.random_rhs(n, 5))
+    ua = to_dev(np.zeros(n))
+    a.vcycle(b, ua)
+    a.close()
+    fixed = Solver(meshes, degree=2, layers=1, sell_layout=la)
+    assert [[fixed.level_info(l)[k] for k in keys] for l in range(fixed.n_levels - 1)] == la
+    ub = to_dev(np.zeros(n))
+    fixed.vcycle(b, ub)
+    fixed.close()
+    x, y = from_dev(ua), from_dev(ub)
+    assert np.max(np.abs(x - y)) <= 1e-12 * np.max(np.abs(x))
+    # an explicit layout on level 0 only; the other levels stay autotuned
+    other = Solver(meshes, degree=2, layers=1, sell_layout=[[128, 4, 1, 2]])
+    assert [other.level_info(0)[k] for k in keys] == [128, 4, 1, 2]
+    other.close()
