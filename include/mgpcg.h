@@ -124,6 +124,13 @@ typedef struct {
                                batch forms, mg_vcycle_solve) start from u = 0
                                and ignore u on entry; 1: they start from the u
                                passed in (a warm start)                       */
+  int32_t sell_colform;     /* column indices of the sparse layouts: 0 = per
+                               slice the narrowest form that fits (16-bit in
+                               two windows of 32768, in eight of 8192, in
+                               sixteen of 4096, else 32-bit); 1 = start at the
+                               eight-window form, 2 = at the sixteen-window
+                               form, 3 = 32-bit everywhere (same results; for
+                               testing every decode path)                     */
   int32_t sell_layout_levels; /* number of levels that sell_layout covers      */
   const int32_t *sell_layout; /* NULL, or host [4 * sell_layout_levels]: for
                                level l the values (sigma, unroll, mask, rpl)
@@ -179,6 +186,7 @@ typedef struct {
   int64_t sell_slices_multiwindow; /* of them with 16-bit columns in 8 or 16
                                windows (decoded with a cross-lane read)        */
   int64_t sell_slices_32bit; /* of them with 32-bit columns                    */
+  int64_t sell_slices_16window; /* of the multiwindow slices, those with 16   */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -210,7 +218,8 @@ enum {
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
  * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
- * patch_fused 1, use_initial_guess 0, sell_layout_levels 0, sell_layout NULL. */
+ * patch_fused 1, use_initial_guess 0, sell_colform 0, sell_layout_levels 0,
+ * sell_layout NULL. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

@@ -76,8 +76,16 @@ class Level:
 
 
 class Hierarchy:
+    """prolongations (optional): P_l for l = 0 .. L-2 as sparse matrices over
+    the free DOFs in canonical order, used instead of point location (for
+    checks at sizes where the oracle's point location is too slow; the given
+    P is itself compared with the oracle's definition on sampled rows).
+    intervals (optional): (lo, hi) of the Chebyshev smoother per level, used
+    instead of the Lanczos estimate (likewise for large sizes)."""
+
     def __init__(self, meshes: list, tau: float = 0.1, layers: int = 1,
-                 opts: Options | None = None):
+                 opts: Options | None = None, prolongations: list | None = None,
+                 intervals: list | None = None):
         self.opts = opts = opts or Options()
         self.levels: list[Level] = []
         nlev = len(meshes)
@@ -101,29 +109,52 @@ class Hierarchy:
             lev = Level(dofmap=dm, A=A, dinv=1.0 / A.diagonal(), gamma=gamma,
                         patch_cells=pc, patch_dofs=pd, colours=cols, Mf=Mf)
             if l < nlev - 1:
-                lev.P, lev.locate_cell = prolongation(dm, dms[l + 1])
-                if elastic:  # each component interpolated on its own: P (x) I
-                    lev.P = sp.kron(lev.P, sp.identity(ncomp), format="csr")
+                if prolongations is not None:
+                    lev.P = sp.csr_matrix(prolongations[l])
+                else:
+                    lev.P, lev.locate_cell = prolongation(dm, dms[l + 1])
+                    if elastic:  # each component interpolated on its own: P (x) I
+                        lev.P = sp.kron(lev.P, sp.identity(ncomp), format="csr")
                 A = galerkin(A, lev.P)
             self.levels.append(lev)
         for l, lev in enumerate(self.levels):
             if l == nlev - 1:
                 lev.chol = sla.cho_factor(lev.A.toarray(), lower=True)
                 continue
-            lev.lam, _ = lanczos_lmax(lev.A, None, opts.eig_tol, opts.eig_maxit)
             use_local = opts.local_correction and len(lev.patch_dofs) > 0
             if use_local:
-                g = np.ones(lev.A.shape[0], dtype=bool)
-                for B in lev.patch_dofs:
-                    g[B] = False
-                lev.lam_adj, _ = lanczos_lmax(lev.A, g, opts.eig_tol, opts.eig_maxit)
                 lev.local = LocalCorrection(lev.A, lev.patch_dofs, lev.colours)
+            if intervals is not None:
+                lev.lo, lev.hi = intervals[l]
             else:
-                lev.lam_adj = lev.lam
-            lev.hi = lev.lam_adj if (use_local and opts.adjusted_eig) else lev.lam
-            lev.lo = opts.cheb_lo_frac * lev.hi
+                lev.lam, _ = lanczos_lmax(lev.A, None, opts.eig_tol, opts.eig_maxit)
+                if use_local:
+                    g = np.ones(lev.A.shape[0], dtype=bool)
+                    for B in lev.patch_dofs:
+                        g[B] = False
+                    lev.lam_adj, _ = lanczos_lmax(lev.A, g, opts.eig_tol, opts.eig_maxit)
+                else:
+                    lev.lam_adj = lev.lam
+                lev.hi = lev.lam_adj if (use_local and opts.adjusted_eig) else lev.lam
+                lev.lo = opts.cheb_lo_frac * lev.hi
             if opts.global_smoother == "sgs":
                 lev.sgs = SymmetricGaussSeidel(lev.A, matrix_colouring(lev.A))
+
+    def replace_coarse_operators(self, operators: list) -> None:
+        """Uses the given A_l (l = 1 .. L-1, sparse, canonical free-DOF order)
+        instead of the Galerkin products, with their diagonals, patch
+        factorisations and the coarsest Cholesky rebuilt; the Chebyshev
+        intervals are kept.  For checks that separate the cycle's arithmetic
+        from the rounding of the coarse operators (which are compared with the
+        Galerkin products themselves)."""
+        for l, A in enumerate(operators, start=1):
+            lev = self.levels[l]
+            lev.A = sp.csr_matrix(A)
+            lev.dinv = 1.0 / lev.A.diagonal()
+            if lev.local is not None:
+                lev.local = LocalCorrection(lev.A, lev.patch_dofs, lev.colours)
+            if l == len(self.levels) - 1:
+                lev.chol = sla.cho_factor(lev.A.toarray(), lower=True)
 
     # -- the method --------------------------------------------------------
     def smooth(self, l: int, b: np.ndarray, u: np.ndarray, nu: int) -> np.ndarray:

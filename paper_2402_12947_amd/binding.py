@@ -41,7 +41,8 @@ class MgOptions(C.Structure):
                 ("global_smoother", C.c_int32), ("problem", C.c_int32), ("young", C.c_double),
                 ("poisson_ratio", C.c_double), ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32),
                 ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32), ("use_initial_guess", C.c_int32),
-                ("sell_layout_levels", C.c_int32), ("sell_layout", C.POINTER(C.c_int32))]
+                ("sell_colform", C.c_int32), ("sell_layout_levels", C.c_int32),
+                ("sell_layout", C.POINTER(C.c_int32))]
 
 
 class MgSolveStats(C.Structure):
@@ -61,7 +62,8 @@ class MgLevelInfo(C.Structure):
                 ("sell_nnz16", C.c_int64), ("n_components", C.c_int32),
                 ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32), ("sell_rpl", C.c_int32),
                 ("patch_fused_colours", C.c_int32), ("sell_slices", C.c_int64),
-                ("sell_slices_multiwindow", C.c_int64), ("sell_slices_32bit", C.c_int64)]
+                ("sell_slices_multiwindow", C.c_int64), ("sell_slices_32bit", C.c_int64),
+                ("sell_slices_16window", C.c_int64)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -153,7 +155,8 @@ class Solver:
                  eig_tol: float = 1e-8, eig_maxit: int = 200, use_graph: bool = False, sell_sigma: int = 0,
                  global_smoother: str = "chebyshev", problem: str = "poisson", young: float = 6.9e10,
                  poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1, sell_rpl: int = 0,
-                 patch_fused: bool = True, use_initial_guess: bool = False, sell_layout=None):
+                 patch_fused: bool = True, use_initial_guess: bool = False, sell_layout=None,
+                 sell_colform: int = 0):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -182,6 +185,7 @@ class Solver:
         opt.sell_rpl = sell_rpl
         opt.patch_fused = int(bool(patch_fused))
         opt.use_initial_guess = int(bool(use_initial_guess))
+        opt.sell_colform = sell_colform
         keep: list = []
         if sell_layout:  # [(sigma, unroll, mask, rpl) per level]
             lay = np.ascontiguousarray(np.asarray(sell_layout, dtype=np.int32).reshape(-1, 4))

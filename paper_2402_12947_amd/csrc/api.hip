@@ -592,9 +592,10 @@ static double *resolve_noalloc(int device) {
 
 struct mg_ctx {
   Ctx impl;
-  // per level: slices of the operator's SELL layout in the eight/sixteen-window
-  // and in the 32-bit column forms (counted once at setup, for mg_get_level_info)
-  std::vector<std::array<int64_t, 2>> slice_forms;
+  // per level: slices of the operator's SELL layout in the eight/sixteen-window,
+  // the 32-bit and the sixteen-window column forms (counted once at setup, for
+  // mg_get_level_info)
+  std::vector<std::array<int64_t, 3>> slice_forms;
 };
 
 template <class T>
@@ -628,6 +629,7 @@ void mg_default_options(mg_options *o) {
   o->sell_rpl = 0;
   o->patch_fused = 1;
   o->use_initial_guess = 0;
+  o->sell_colform = 0;
   o->sell_layout_levels = 0;
   o->sell_layout = nullptr;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
@@ -692,6 +694,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       fail(MG_ERR_ARG, "sell_rpl must be 0, 1, 2, 4 or 8");
     if (o.patch_fused != 0 && o.patch_fused != 1) fail(MG_ERR_ARG, "patch_fused must be 0 or 1");
     if (o.use_initial_guess != 0 && o.use_initial_guess != 1) fail(MG_ERR_ARG, "use_initial_guess must be 0 or 1");
+    if (o.sell_colform < 0 || o.sell_colform > 3) fail(MG_ERR_ARG, "sell_colform must be 0, 1, 2 or 3");
     if (o.sell_layout_levels < 0 || (o.sell_layout_levels > 0 && !o.sell_layout))
       fail(MG_ERR_ARG, "sell_layout must hold 4 values for each of sell_layout_levels levels");
     for (int l = 0; l < o.sell_layout_levels; ++l) {
@@ -817,7 +820,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     // column form of each slice: cbase[2 s] >= 0 two windows, -1 32-bit,
     // below -1 eight or sixteen windows
     for (const Level &L : c.lv) {
-      std::array<int64_t, 2> f = {0, 0};
+      std::array<int64_t, 3> f = {0, 0, 0};
       if (L.S.nslices > 0) {
         std::vector<int32_t> cb(2 * L.S.nslices);
         MG_HIP(hipMemcpyAsync(cb.data(), L.S.cbase.p, cb.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -826,6 +829,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
         for (int64_t q = 0; q < L.S.nslices; ++q) {
           f[0] += cb[2 * q] < -1;
           f[1] += cb[2 * q] == -1;
+          f[2] += cb[2 * q] == -3;
         }
       }
       h->slice_forms.push_back(f);
@@ -1226,6 +1230,7 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   if (level < (int)h->slice_forms.size()) {
     o->sell_slices_multiwindow = h->slice_forms[level][0];
     o->sell_slices_32bit = h->slice_forms[level][1];
+    o->sell_slices_16window = h->slice_forms[level][2];
   }
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;

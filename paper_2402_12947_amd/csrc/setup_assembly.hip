@@ -529,9 +529,12 @@ __device__ int cover_windows(const int32_t *cp, int w, int bits, int *bases) {
 
 // One wavefront per slice: choose the narrowest 16-bit form that covers every
 // column of the slice (two windows of 32768, else eight of 8192, else sixteen
-// of 4096) and write it, or keep the slice at 32 bits.
+// of 4096) and write it, or keep the slice at 32 bits.  narrowest = 1, 2, 3
+// starts the search at the eight-window form, at the sixteen-window form, or
+// keeps every slice at 32 bits (a form that covers a slice also covers it in
+// every wider form, so this forces the form wherever the slice fits it).
 __global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const int64_t *sptr, const int32_t *col,
-                                                       const uint16_t *rlen, uint16_t *col16,
+                                                       const uint16_t *rlen, int narrowest, uint16_t *col16,
                                                        int32_t *cbase, int32_t *ctab, unsigned long long *nnz16) {
   const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (sl >= nslices) return;
@@ -542,7 +545,7 @@ __global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const in
   uint16_t *op = col16 + base + lane;
   int bases[16];
   int mode;
-  int nb = cover_windows<2>(cp, w, 15, bases);
+  int nb = narrowest == 0 ? cover_windows<2>(cp, w, 15, bases) : 0;
   if (nb > 0) {
     const int b0 = bases[0], b1 = nb > 1 ? bases[1] : bases[0];
     for (int j = 0; j < w; ++j) {
@@ -556,10 +559,10 @@ __global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const in
     mode = 2;
   } else {
     int bits = 13;
-    nb = cover_windows<8>(cp, w, 13, bases);
+    nb = narrowest <= 1 ? cover_windows<8>(cp, w, 13, bases) : 0;
     if (nb == 0) {
       bits = 12;
-      nb = cover_windows<16>(cp, w, 12, bases);
+      nb = narrowest <= 2 ? cover_windows<16>(cp, w, 12, bases) : 0;
     }
     if (nb == 0) {
       if (lane == 0) {
@@ -634,7 +637,8 @@ void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32, int rpl) 
   S.ctab.alloc(16 * S.nslices);
   if (S.nslices > 0) {
     k_compress_cols<<<(unsigned)((S.nslices + 3) / 4), 256, 0, s>>>(S.nslices, S.slice_ptr, S.col, S.rlen,
-                                                                    S.col16, S.cbase, S.ctab, cnt);
+                                                                    c.opt.sell_colform, S.col16, S.cbase, S.ctab,
+                                                                    cnt);
     MG_LAUNCH_CHECK();
   }
   unsigned long long h[2] = {0, 0};

@@ -67,6 +67,7 @@ def test_setup_rejects_bad_input_on_host():
     assert setup_status([mesh], sell_unroll=16)[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_mask=2)[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_rpl=3)[0] == MG_ERR_ARG
+    assert setup_status([mesh], sell_colform=4)[0] == MG_ERR_ARG
     # per-level layouts follow the same rules as the global layout options
     assert setup_status([mesh], sell_layout=[[100, 0, -1, 0]])[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_layout=[[0, 16, -1, 0]])[0] == MG_ERR_ARG

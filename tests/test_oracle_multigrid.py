@@ -180,3 +180,37 @@ def test_sgs_global_local_recovers_reference_cycles():
         cyc[name] = it
     assert cyc["gl"] <= cyc["ref"] + 2
     assert cyc["plain"] >= 2 * cyc["gl"]
+
+
+def test_given_prolongations_and_intervals_reproduce_the_hierarchy():
+    """The large-size checks build the oracle from given transfer operators
+    and Chebyshev intervals; given the oracle's own, the cycle is unchanged."""
+    meshes = meshgen.hierarchy("square_1025", seed=0, scale=32)
+    opts = Options(degree=2)
+    H = Hierarchy(meshes, tau=0.1, layers=1, opts=opts)
+    G = Hierarchy(meshes, tau=0.1, layers=1, opts=opts,
+                  prolongations=[lev.P for lev in H.levels[:-1]],
+                  intervals=[(lev.lo, lev.hi) for lev in H.levels[:-1]])
+    for a, b in zip(H.levels, G.levels):
+        assert (a.A != b.A).nnz == 0
+    n = H.levels[0].A.shape[0]
+    b = meshgen.random_rhs(n, 3)
+    assert np.array_equal(H.vcycle(b), G.vcycle(b))
+    # a different interval changes the cycle (the option is really used)
+    W = Hierarchy(meshes, tau=0.1, layers=1, opts=opts, prolongations=[lev.P for lev in H.levels[:-1]],
+                  intervals=[(lev.lo, 1.5 * lev.hi) for lev in H.levels[:-1]])
+    assert not np.allclose(H.vcycle(b), W.vcycle(b), rtol=1e-6, atol=0)
+
+
+def test_replaced_coarse_operators():
+    """Given its own Galerkin products, the cycle is unchanged; given perturbed
+    coarse operators, it changes."""
+    meshes = meshgen.hierarchy("square_1025", seed=0, scale=32)
+    H = Hierarchy(meshes, tau=0.1, layers=1, opts=Options(degree=2))
+    n = H.levels[0].A.shape[0]
+    b = meshgen.random_rhs(n, 3)
+    x = H.vcycle(b)
+    H.replace_coarse_operators([lev.A.copy() for lev in H.levels[1:]])
+    assert np.array_equal(x, H.vcycle(b))
+    H.replace_coarse_operators([1.01 * lev.A for lev in H.levels[1:]])
+    assert not np.allclose(x, H.vcycle(b), rtol=1e-6, atol=0)
