@@ -131,6 +131,36 @@ typedef struct {
                                eight-window form, 2 = at the sixteen-window
                                form, 3 = 32-bit everywhere (same results; for
                                testing every decode path)                     */
+  int32_t patch_factor_f32; /* MG_MIXED only.  1: factor the patch systems on
+                               the FP32 matrix cores (FP32 accumulate) after
+                               a symmetric diagonal equilibration, and keep
+                               the FP64 factorisation for the patches whose
+                               scaled pivots fall below 2^-12 (or that hold
+                               more than 2048 DOFs); 0: factor every patch in
+                               FP64.  The inverse is stored in FP32 either
+                               way                                             */
+  int32_t patch_refine;     /* 1: every patch solve takes one step of
+                               iterative refinement, e = X r, then
+                               e += X (r - A^[d] e) with the residual of the
+                               patch system formed in FP64 (X the stored
+                               inverse; costs a second product with X and the
+                               patch rows once more); 0: e = X r             */
+  int32_t patch_inherit_levels; /* 0 (the paper): each level's patches come
+                               from its own cells' quality.  k > 0: levels
+                               1..k (not the coarsest) also take the patches
+                               inherited through the interpolation from the
+                               finest level's degraded cells: seeds = the free
+                               DOFs of each degraded cell of level 0; level
+                               l+1 inherits, per seed, the coarse DOFs that
+                               P_l couples to it (the free DOFs of the coarse
+                               cells containing its nodes); the connected
+                               components of these sets (shared DOFs, ordered
+                               by smallest DOF) follow the level's own patches
+                               (MERGE: merged with the own patches they share
+                               DOFs with; OVERLAP: coloured).  The Galerkin
+                               operator A_(l+1) = P^T A_l P carries the
+                               degraded cells' stiffness into exactly those
+                               rows                                            */
   int32_t sell_layout_levels; /* number of levels that sell_layout covers      */
   const int32_t *sell_layout; /* NULL, or host [4 * sell_layout_levels]: for
                                level l the values (sigma, unroll, mask, rpl)
@@ -187,6 +217,8 @@ typedef struct {
                                windows (decoded with a cross-lane read)        */
   int64_t sell_slices_32bit; /* of them with 32-bit columns                    */
   int64_t sell_slices_16window; /* of the multiwindow slices, those with 16   */
+  int32_t patches_f32;      /* patches factored on the FP32 matrix cores       */
+  int32_t patches_inherited; /* inherited components (patch_inherit_levels)   */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -218,8 +250,8 @@ enum {
  * eig_maxit 200, use_graph 0, sell_sigma 0, stream NULL,
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
  * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
- * patch_fused 1, use_initial_guess 0, sell_colform 0, sell_layout_levels 0,
- * sell_layout NULL. */
+ * patch_fused 1, use_initial_guess 0, sell_colform 0, patch_factor_f32 1,
+ * patch_refine 0, patch_inherit_levels 0, sell_layout_levels 0, sell_layout NULL. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

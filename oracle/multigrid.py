@@ -29,7 +29,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .fem import DofMap, assemble
-from .patches import MERGE, colour, patches
+from .patches import MERGE, colour, combine, components, inherit, patches
 from .quality import radius_ratio
 from . import elasticity
 from .smoothers import LocalCorrection, SymmetricGaussSeidel, lanczos_lmax, matrix_colouring, sandwich
@@ -51,6 +51,7 @@ class Options:
     problem: str = "poisson"             # or "elasticity" (Sec. 6.2)
     young: float = 6.9e10
     poisson_ratio: float = 0.33
+    inherit_levels: int = 0              # coarse levels with patches inherited through P (0: the paper's)
 
 
 @dataclass
@@ -105,6 +106,17 @@ class Hierarchy:
                              opts.patch_policy, dm.cell_dofs, dm.free_index)
             if elastic:  # every component of the patch's scalar DOFs
                 pd = [elasticity.vector_ids(B, ncomp) for B in pd]
+            if opts.local_correction and opts.inherit_levels > 0:
+                if l == 0:   # seeds: the free DOFs of each degraded cell
+                    seeds = []
+                    for K in np.flatnonzero(gamma < tau):
+                        f = dm.free_index[dm.cell_dofs[K]]
+                        f = np.unique(f[f >= 0])
+                        seeds.append(elasticity.vector_ids(f, ncomp) if elastic else f)
+                elif l <= opts.inherit_levels:
+                    seeds = inherit(self.levels[l - 1].P, seeds)
+                    pd = combine(pd, components(seeds), opts.patch_policy)
+                    pc = [np.zeros(0, dtype=np.int64)] * len(pd)
             cols = colour(pd)
             lev = Level(dofmap=dm, A=A, dinv=1.0 / A.diagonal(), gamma=gamma,
                         patch_cells=pc, patch_dofs=pd, colours=cols, Mf=Mf)

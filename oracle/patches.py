@@ -20,6 +20,19 @@ Canonical construction (the paper is silent on orderings):
   5. B_d = the free DOFs of the patch's cells, ascending; empty patches dropped.
 Colouring: greedy in patch order, each patch taking the smallest colour not used
 by an earlier patch with which it shares a DOF.  MERGE always gives one colour.
+
+Inherited patches (an option; the paper identifies every level's subdomains
+from that level's own cells).  The Galerkin operator A_(l+1) = P_l^T A_l P_l
+(Sec. 2) carries the stiffness of the finest level's degraded cells into the
+rows of the coarse DOFs that P interpolates at those cells' nodes, whatever
+the quality of the coarse mesh.  With inherit_levels = k, the seeds are the
+free DOF sets of the degraded cells of level 0 (one per cell), S_(l+1) holds,
+for each set of S_l, the coarse DOFs that P_l couples to it (the structural
+nonzeros of its rows: the free DOFs of the coarse cell that contains each
+node), and levels 1..k add the connected components of S_l under "shares a
+DOF" (ordered by smallest DOF) after their own patches; MERGE joins a
+component with the own patches it shares DOFs with (into the lowest-indexed
+one), OVERLAP keeps them apart and colours them.
 """
 from __future__ import annotations
 
@@ -140,3 +153,77 @@ def colour(patch_dofs: list) -> np.ndarray:
         for i in dofs.tolist():
             owner.setdefault(i, []).append(p)
     return col
+
+
+def inherit(P, sets: list) -> list:
+    """For each fine DOF set, the coarse DOFs that P couples to it: the column
+    indices of P's rows at the set (P stores every free DOF of the coarse cell
+    that contains a fine node, zero values included)."""
+    import scipy.sparse as sp
+    P = sp.csr_matrix(P)
+    out = []
+    for s in sets:
+        idx = [P.indices[P.indptr[i]:P.indptr[i + 1]] for i in np.asarray(s, dtype=np.int64)]
+        out.append(np.unique(np.concatenate(idx)) if idx else np.zeros(0, dtype=np.int64))
+    return out
+
+
+def components(sets: list) -> list:
+    """Connected components of a family of DOF sets under "shares a DOF", each
+    the sorted union of its sets, ordered by their smallest DOF."""
+    parent = list(range(len(sets)))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    owner = {}
+    for k, s in enumerate(sets):
+        for d in np.asarray(s).tolist():
+            if d in owner:
+                ra, rb = find(owner[d]), find(k)
+                if ra != rb:
+                    parent[max(ra, rb)] = min(ra, rb)
+            else:
+                owner[d] = k
+    groups = {}
+    for k in range(len(sets)):
+        groups.setdefault(find(k), []).append(k)
+    out = [np.unique(np.concatenate([np.asarray(sets[k], dtype=np.int64) for k in g])) for g in groups.values()]
+    out = [c for c in out if c.size]
+    out.sort(key=lambda c: int(c[0]))
+    return out
+
+
+def combine(own: list, inherited: list, policy: int) -> list:
+    """A level's patches: its own, then the inherited components.  MERGE: an
+    inherited component that shares DOFs with own patches joins them, all
+    into the lowest-indexed of them (own patches are pairwise disjoint, and so
+    are the components); OVERLAP: kept apart."""
+    allp = [np.asarray(p, dtype=np.int64) for p in own] + [np.asarray(p, dtype=np.int64) for p in inherited]
+    if policy != MERGE:
+        return allp
+    parent = list(range(len(allp)))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    owner = {}
+    for k, p in enumerate(allp):
+        for d in p.tolist():
+            if d in owner:
+                ra, rb = find(owner[d]), find(k)
+                if ra != rb:
+                    parent[max(ra, rb)] = min(ra, rb)
+            else:
+                owner[d] = k
+    groups = {}
+    for k in range(len(allp)):
+        groups.setdefault(find(k), []).append(k)
+    roots = sorted(groups)
+    return [np.unique(np.concatenate([allp[k] for k in groups[r]])) for r in roots]

@@ -41,7 +41,9 @@ class MgOptions(C.Structure):
                 ("global_smoother", C.c_int32), ("problem", C.c_int32), ("young", C.c_double),
                 ("poisson_ratio", C.c_double), ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32),
                 ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32), ("use_initial_guess", C.c_int32),
-                ("sell_colform", C.c_int32), ("sell_layout_levels", C.c_int32),
+                ("sell_colform", C.c_int32), ("patch_factor_f32", C.c_int32), ("patch_refine", C.c_int32),
+                ("patch_inherit_levels", C.c_int32),
+                ("sell_layout_levels", C.c_int32),
                 ("sell_layout", C.POINTER(C.c_int32))]
 
 
@@ -63,7 +65,8 @@ class MgLevelInfo(C.Structure):
                 ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32), ("sell_rpl", C.c_int32),
                 ("patch_fused_colours", C.c_int32), ("sell_slices", C.c_int64),
                 ("sell_slices_multiwindow", C.c_int64), ("sell_slices_32bit", C.c_int64),
-                ("sell_slices_16window", C.c_int64)]
+                ("sell_slices_16window", C.c_int64), ("patches_f32", C.c_int32),
+                ("patches_inherited", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -156,7 +159,8 @@ class Solver:
                  global_smoother: str = "chebyshev", problem: str = "poisson", young: float = 6.9e10,
                  poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1, sell_rpl: int = 0,
                  patch_fused: bool = True, use_initial_guess: bool = False, sell_layout=None,
-                 sell_colform: int = 0):
+                 sell_colform: int = 0, patch_factor_f32: bool = True, patch_refine: bool = False,
+                 patch_inherit_levels: int = 0):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -186,6 +190,9 @@ class Solver:
         opt.patch_fused = int(bool(patch_fused))
         opt.use_initial_guess = int(bool(use_initial_guess))
         opt.sell_colform = sell_colform
+        opt.patch_factor_f32 = int(bool(patch_factor_f32))
+        opt.patch_refine = int(bool(patch_refine))
+        opt.patch_inherit_levels = patch_inherit_levels
         keep: list = []
         if sell_layout:  # [(sigma, unroll, mask, rpl) per level]
             lay = np.ascontiguousarray(np.asarray(sell_layout, dtype=np.int32).reshape(-1, 4))

@@ -80,6 +80,10 @@ void ensure_work(Ctx &c, Level &L) {
       L.pz64.alloc(std::max<int64_t>(1, L.patch.inv.zsize));
     }
   }
+  if (L.patch.total > 0 && c.opt.patch_refine) {
+    L.pst.alloc(L.nfree);
+    fill<double>(c.stream, L.pst.p, L.nfree, 0.0);
+  }
   if (L.coarsest) {
     L.cpy.alloc(L.cpk.ysize);
     L.cpz.alloc(std::max<int64_t>(1, L.cpk.zsize));
@@ -116,6 +120,11 @@ template <class T>
 static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending) {
   for (int k = 0; k < L.patch.ncolour; ++k) {
     int col = descending ? L.patch.ncolour - 1 - k : k;
+    if (c.opt.patch_refine) {
+      patch_residual<T>(c.stream, L.patch, col, b, u, LV<T>::res(L));
+      patch_apply_refined<T>(c.stream, L.patch, col, LV<T>::res(L), LV<T>::py(L), LV<T>::pz(L), u, L.pst.p);
+      continue;
+    }
     if (L.patch.colour_fused[col]) {
       patch_correct_small<T>(c.stream, L.patch, col, b, (const T *)nullptr, u);
       continue;
@@ -313,8 +322,12 @@ static void local_correction_block(Ctx &c, Level &L, int K, const T *b, T *u, bo
   for (int k = 0; k < L.patch.ncolour; ++k) {
     int col = descending ? L.patch.ncolour - 1 - k : k;
     patch_residual_block<T>(c.stream, L.patch, col, K, b, u, res);
-    for (int q = 0; q < K; ++q)
-      patch_apply<T>(c.stream, L.patch, col, res + q, LV<T>::py(L), LV<T>::pz(L), u + q, K);
+    for (int q = 0; q < K; ++q) {
+      if (c.opt.patch_refine)
+        patch_apply_refined<T>(c.stream, L.patch, col, res + q, LV<T>::py(L), LV<T>::pz(L), u + q, L.pst.p, K);
+      else
+        patch_apply<T>(c.stream, L.patch, col, res + q, LV<T>::py(L), LV<T>::pz(L), u + q, K);
+    }
   }
 }
 
@@ -630,6 +643,9 @@ void mg_default_options(mg_options *o) {
   o->patch_fused = 1;
   o->use_initial_guess = 0;
   o->sell_colform = 0;
+  o->patch_factor_f32 = 1;
+  o->patch_refine = 0;
+  o->patch_inherit_levels = 0;
   o->sell_layout_levels = 0;
   o->sell_layout = nullptr;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
@@ -695,6 +711,9 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.patch_fused != 0 && o.patch_fused != 1) fail(MG_ERR_ARG, "patch_fused must be 0 or 1");
     if (o.use_initial_guess != 0 && o.use_initial_guess != 1) fail(MG_ERR_ARG, "use_initial_guess must be 0 or 1");
     if (o.sell_colform < 0 || o.sell_colform > 3) fail(MG_ERR_ARG, "sell_colform must be 0, 1, 2 or 3");
+    if (o.patch_factor_f32 != 0 && o.patch_factor_f32 != 1) fail(MG_ERR_ARG, "patch_factor_f32 must be 0 or 1");
+    if (o.patch_refine != 0 && o.patch_refine != 1) fail(MG_ERR_ARG, "patch_refine must be 0 or 1");
+    if (o.patch_inherit_levels < 0) fail(MG_ERR_ARG, "patch_inherit_levels must be >= 0");
     if (o.sell_layout_levels < 0 || (o.sell_layout_levels > 0 && !o.sell_layout))
       fail(MG_ERR_ARG, "sell_layout must hold 4 values for each of sell_layout_levels levels");
     for (int l = 0; l < o.sell_layout_levels; ++l) {
@@ -751,10 +770,14 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       L.setup_ms += ms(t0, now());
       phase(l == 0 ? "DOF map, quality, patches, assembly" : "DOF map, quality, patches", l);
     }
+    std::vector<std::vector<int32_t>> seeds;  // patches inherited through P
+    if (o.local_correction && o.patch_inherit_levels > 0) patch_seeds(c, c.lv[0], seeds);
     for (int l = 0; l + 1 < n_levels; ++l) {
       auto t0 = now();
       build_prolongation(c, c.lv[l], c.lv[l + 1], levels[l + 1]);
       galerkin_product(c, c.lv[l], c.lv[l + 1]);
+      if (l < o.patch_inherit_levels && l + 2 < n_levels && !seeds.empty())
+        inherit_patches(c, c.lv[l], c.lv[l + 1], seeds);
       c.lv[l].setup_ms += ms(t0, now());
       phase("prolongation and Galerkin product", l);
     }
@@ -779,6 +802,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
       permute_patches(c, L);
       if (!L.coarsest) {
         build_patch_rows(c, L, mixed);
+        if (o.patch_refine) build_patch_refine(c, L);
         build_patch_neighbours(c, L, mixed);
       }
       if (!L.coarsest && o.global_smoother == MG_SMOOTHER_SGS) build_sgs(c, L, mixed);
@@ -1231,6 +1255,8 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
     o->sell_slices_multiwindow = h->slice_forms[level][0];
     o->sell_slices_32bit = h->slice_forms[level][1];
     o->sell_slices_16window = h->slice_forms[level][2];
+    o->patches_f32 = L.patch.n_factor32;
+    o->patches_inherited = L.patch.n_inherited;
   }
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;

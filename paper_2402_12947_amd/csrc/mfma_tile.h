@@ -1,8 +1,11 @@
-// FP64 matrix-core tile products shared by the dense factorisations: a
-// wavefront computes one 32 x 32 output tile as 2 x 2 blocks of
-// v_mfma_f64_16x16x4 (lane l of a 16 x 16 block result holds rows l / 16 + 4 e,
-// e = 0..3, of column l % 16), with its operands read straight from memory
-// into the register layout the instruction expects.
+// Matrix-core tile products shared by the dense factorisations: a wavefront
+// computes one 32 x 32 output tile as 2 x 2 blocks of 16 x 16 x 4 MFMA steps
+// (v_mfma_f64_16x16x4 in FP64, v_mfma_f32_16x16x4 in FP32, FP32 accumulate),
+// with its operands read straight from memory into the register layout the
+// instruction expects.  Both instructions take operand A as lane l holding
+// (row l % 16, k l / 16) and operand B as (k l / 16, column l % 16); their
+// result layouts differ (checked on the device): in FP64 lane l holds rows
+// l / 16 + 4 e, e = 0..3, of column l % 16, in FP32 rows 4 (l / 16) + e.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -10,14 +13,15 @@
 namespace mg {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 // MFMA operand registers of one 32 x 32 tile, read straight from the n x n
 // row-major matrix M: element (x, y) of the operand is M[r0 + x][c0 + y], or
 // M[r0 + y][c0 + x] when swap is set (zero outside the matrix).  For the A
 // operand lane l holds (x, y) = (16 blk + l % 16, 4 s + l / 16), for the B
 // operand (4 s + l / 16, 16 blk + l % 16); o[blk * 8 + s].
-template <bool ROLE_A>
-__device__ inline void fetch_ops(const double *M, int n, int r0, int c0, bool swap, double o[16], int lane) {
+template <bool ROLE_A, class T>
+__device__ inline void fetch_ops(const T *M, int n, int r0, int c0, bool swap, T o[16], int lane) {
   const int p = lane & 15, q = lane >> 4;
 #pragma unroll
   for (int blk = 0; blk < 2; ++blk)
@@ -26,7 +30,7 @@ __device__ inline void fetch_ops(const double *M, int n, int r0, int c0, bool sw
       const int x = ROLE_A ? 16 * blk + p : 4 * s + q;
       const int y = ROLE_A ? 4 * s + q : 16 * blk + p;
       const int r = swap ? r0 + y : r0 + x, c = swap ? c0 + x : c0 + y;
-      o[blk * 8 + s] = (r < n && c < n) ? M[(int64_t)r * n + c] : 0.0;
+      o[blk * 8 + s] = (r < n && c < n) ? M[(int64_t)r * n + c] : (T)0;
     }
 }
 
@@ -40,20 +44,48 @@ __device__ inline void mma_ops(v4d acc[2][2], const double a[16], const double b
     acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 + s], b[8 + s], acc[1][1], 0, 0, 0);
   }
 }
+__device__ inline void mma_ops(v4f acc[2][2], const float a[16], const float b[16]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[8 + s], acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[8 + s], b[s], acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[8 + s], b[8 + s], acc[1][1], 0, 0, 0);
+  }
+}
 
 __device__ inline void zero_acc(v4d acc[2][2]) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 }
+__device__ inline void zero_acc(v4f acc[2][2]) {
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+}
 
-// element (i, j) of the tile held by this lane: in each 16 x 16 block the lane
-// owns column (lane & 15) and rows (lane >> 4) + 4 e, e = 0..3 (the f64 MFMA
-// result layout, checked on the device)
+// f(i, j, v) for the elements (i, j) of the tile held by this lane
 template <class F>
 __device__ inline void for_acc(v4d acc[2][2], int lane, F f) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < 4; ++e) f(16 * a + (lane >> 4) + 4 * e, 16 * b + (lane & 15), acc[a][b][e]);
 }
+template <class F>
+__device__ inline void for_acc(v4f acc[2][2], int lane, F f) {
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 4; ++e) f(16 * a + 4 * (lane >> 4) + e, 16 * b + (lane & 15), acc[a][b][e]);
+}
+
+template <class T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  using type = v4d;
+};
+template <>
+struct MfmaAcc<float> {
+  using type = v4f;
+};
 
 }  // namespace mg

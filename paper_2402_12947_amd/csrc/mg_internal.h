@@ -160,6 +160,8 @@ void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const 
 // Patches of one level in kernel order (sorted by colour, then canonical id).
 struct Patches {
   int n = 0, ncolour = 0, maxn = 0;
+  int n_factor32 = 0;         // patches factored on the FP32 matrix cores
+  int n_inherited = 0;        // components inherited from the finer level
   int64_t total = 0;          // sum of patch sizes
   std::vector<int> colour_first;   // [ncolour + 1] kernel-order patch ranges
   std::vector<int32_t> h_ptr, h_dofs, h_colour;  // canonical order (export)
@@ -173,6 +175,10 @@ struct Patches {
   PackedInv inv;
   // rows of A at the patch DOFs (kernel order), columns in solve order
   Sell rows;
+  // with patch_refine: the FP64 values of `rows` with every column outside
+  // the row's own patch zeroed (A^[d] in the layout of rows), for the
+  // refinement residual of the patch solves
+  DBuf<double> loc;
   // per colour: 1 if every patch holds at most SMALL_PATCH DOFs and no patch
   // row couples to a DOF of another patch of the colour, so that one launch
   // per colour (patch_correct_small) equals the residual of all patches
@@ -243,6 +249,7 @@ struct Level {
   DBuf<float> res32;
   DBuf<double> py64, pz64;     // patch apply partial products [inv.ysize], [inv.zsize]
   DBuf<float> py32, pz32;
+  DBuf<double> pst;            // patch_refine: staged first patch solves [nfree], zero between calls
   // the same for block solves: MG_BLOCK_MAX interleaved columns, allocated on
   // the first block solve
   DBuf<double> bw64[6];
@@ -303,9 +310,13 @@ void assemble_mass(Ctx &c, Level &L);
 void build_prolongation(Ctx &c, Level &fine, const Level &coarse, const mg_mesh &cm);
 void galerkin_product(Ctx &c, Level &fine, Level &coarse);
 void build_patches(Ctx &c, Level &L, const mg_mesh &m);
+void set_patches(Ctx &c, Level &L, const std::vector<std::vector<int32_t>> &dofs);
+void patch_seeds(Ctx &c, Level &L, std::vector<std::vector<int32_t>> &seeds);
+void inherit_patches(Ctx &c, const Level &F, Level &C, std::vector<std::vector<int32_t>> &seeds);
 void factor_patches(Ctx &c, Level &L);
 void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad);
 void build_patch_rows(Ctx &c, Level &L, bool want32);
+void build_patch_refine(Ctx &c, Level &L);
 void build_patch_neighbours(Ctx &c, Level &L, bool want32);
 void build_sgs(Ctx &c, Level &L, bool want32);
 void factor_coarsest(Ctx &c, Level &L);
@@ -346,6 +357,12 @@ void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, co
 // when vs > 1)
 template <class T>
 void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u, int vs = 1);
+// the same with one step of iterative refinement (FP64 residual of the patch
+// systems); res is overwritten, st (n_free doubles, zero outside a call) stages
+// the first solve
+template <class T>
+void patch_apply_refined(hipStream_t s, const Patches &pt, int colour, T *res, T *py, T *pz, T *u, double *st,
+                         int vs = 1);
 // Patches of at most SMALL_PATCH DOFs, one workgroup per patch, bitwise
 // equal to patch_residual followed by patch_apply: with res = NULL the whole
 // local correction of one colour (residual, product with the packed inverse,

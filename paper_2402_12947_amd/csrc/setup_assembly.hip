@@ -763,6 +763,63 @@ void build_patch_rows(Ctx &c, Level &L, bool want32) {
   }
 }
 
+// The refinement values of the patch rows: loc = the values of P.rows with
+// every column outside the row's own patch zeroed, so that the product with
+// loc is A^[d] applied to a vector that holds a patch solve at its patch's
+// DOFs.  A DOF lies in at most one patch of a colour, so the colours are
+// marked one at a time: owner[DOF] = patch, then each row keeps the entries
+// whose column its own patch owns.
+__global__ void k_owner_mark(const int32_t *kpatch, const int32_t *dofs, int64_t k0, int64_t k1, int32_t *owner,
+                             int clear) {
+  int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < k1) owner[dofs[k]] = clear ? -1 : kpatch[k];
+}
+__global__ void k_patch_loc(int64_t k0, int64_t k1, const int64_t *sptr, const int32_t *col, const double *v64,
+                            const int32_t *kpatch, const int32_t *owner, double *loc) {
+  // one thread per (slice position, entry) of the slices covering [k0, k1)
+  const int64_t s0 = k0 >> 6, s1 = (k1 + 63) >> 6;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t sl = s0 + (t >> 6);
+  if (sl >= s1) return;
+  const int lane = (int)(t & 63);
+  const int64_t k = sl * 64 + lane;
+  const int64_t base = sptr[sl], w = (sptr[sl + 1] - base) >> 6;
+  const bool mine = k >= k0 && k < k1;
+  for (int64_t j = 0; j < w; ++j) {
+    const int64_t o = base + j * 64 + lane;
+    if (mine) loc[o] = owner[col[o]] == kpatch[k] ? v64[o] : 0.0;
+  }
+}
+
+void build_patch_refine(Ctx &c, Level &L) {
+  Patches &P = L.patch;
+  if (P.total == 0) return;
+  if (P.rows.rpl != 1) fail(MG_ERR_ARG, "patch refinement needs one lane per patch row");
+  hipStream_t s = c.stream;
+  std::vector<int32_t> kp(P.total);
+  for (int p = 0; p < P.n; ++p)
+    for (int32_t k = P.h_kptr[p]; k < P.h_kptr[p + 1]; ++k) kp[k] = p;
+  DBuf<int32_t> kpatch, owner;
+  upload(kpatch, kp.data(), kp.size(), s);
+  owner.alloc(L.nfree);
+  fill<int32_t>(s, owner.p, L.nfree, -1);
+  P.loc.alloc(P.rows.stored);
+  fill<double>(s, P.loc.p, P.rows.stored, 0.0);
+  for (int cl = 0; cl < P.ncolour; ++cl) {
+    const int64_t k0 = P.h_kptr[P.colour_first[cl]], k1 = P.h_kptr[P.colour_first[cl + 1]];
+    if (k1 <= k0) continue;
+    k_owner_mark<<<grid_for(k1 - k0, 256), 256, 0, s>>>(kpatch, P.dofs, k0, k1, owner, 0);
+    MG_LAUNCH_CHECK();
+    const int64_t nthreads = (((k1 + 63) >> 6) - (k0 >> 6)) * 64;
+    k_patch_loc<<<grid_for(nthreads, 256), 256, 0, s>>>(k0, k1, P.rows.slice_ptr, P.rows.col, P.rows.v64, kpatch,
+                                                       owner, P.loc);
+    MG_LAUNCH_CHECK();
+    k_owner_mark<<<grid_for(k1 - k0, 256), 256, 0, s>>>(kpatch, P.dofs, k0, k1, owner, 1);
+    MG_LAUNCH_CHECK();
+  }
+  MG_HIP(hipStreamSynchronize(s));
+}
+
 // Rows of A that couple to a patch DOF, as a SELL matrix in ascending solve
 // order with their solve-order positions (nbr_pos).
 __global__ void k_mark_dofs(const int32_t *dofs, int64_t m, uint8_t *flag) {

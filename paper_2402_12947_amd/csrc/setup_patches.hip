@@ -181,6 +181,18 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
     }
     if (!d.empty()) dofs.push_back(std::move(d));
   }
+  set_patches(c, L, dofs);
+}
+
+// The level's patches from their DOF sets (canonical free ids, ascending, in
+// patch order): greedy colours, export arrays, kernel order, packed layout.
+void set_patches(Ctx &c, Level &L, const std::vector<std::vector<int32_t>> &dofs) {
+  hipStream_t s = c.stream;
+  Patches &P = L.patch;
+  P.h_ptr.assign(1, 0);
+  P.h_dofs.clear();
+  P.h_colour.clear();
+  P.maxn = 0;
   // greedy colouring over shared DOFs
   std::unordered_map<int32_t, std::vector<int>> owners;
   std::vector<int> colour(dofs.size(), 0);
@@ -237,6 +249,162 @@ void build_patches(Ctx &c, Level &L, const mg_mesh &m) {
   P.inv64.alloc(acc);
   MG_HIP(hipStreamSynchronize(s));
 }
+
+// ---------------------------------------------------------------------------
+// patches inherited through the transfer operators
+// ---------------------------------------------------------------------------
+// seeds: the free DOFs of each degraded cell of level 0 (every component for
+// vector problems), one set per cell in cell order
+void patch_seeds(Ctx &c, Level &L, std::vector<std::vector<int32_t>> &seeds) {
+  hipStream_t s = c.stream;
+  std::vector<uint8_t> flags;
+  download(flags, L.flags.p, (size_t)L.nc, s);
+  std::vector<int32_t> flagged;
+  for (int64_t i = 0; i < L.nc; ++i)
+    if (flags[i]) flagged.push_back((int32_t)i);
+  seeds.clear();
+  if (flagged.empty()) return;
+  DBuf<int32_t> dcells, dout;
+  upload(dcells, flagged.data(), flagged.size(), s);
+  dout.alloc(flagged.size() * L.nloc);
+  k_gather_cell_free_dofs<<<grid_for((int64_t)flagged.size() * L.nloc, 256), 256, 0, s>>>(
+      dcells, (int64_t)flagged.size(), L.cell_dofs, L.nloc, L.free_index, dout);
+  MG_LAUNCH_CHECK();
+  std::vector<int32_t> fd;
+  download(fd, dout.p, flagged.size() * L.nloc, s);
+  for (size_t k = 0; k < flagged.size(); ++k) {
+    std::vector<int32_t> d;
+    for (int j = 0; j < L.nloc; ++j)
+      if (fd[k * L.nloc + j] >= 0) d.push_back(fd[k * L.nloc + j]);
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    if (L.ncomp > 1) {
+      std::vector<int32_t> v;
+      for (int32_t x : d)
+        for (int q = 0; q < L.ncomp; ++q) v.push_back(x * L.ncomp + q);
+      d.swap(v);
+    }
+    seeds.push_back(std::move(d));
+  }
+}
+
+__global__ void k_gather_rows(const int32_t *pcol, int width, const int32_t *rows, int64_t n, int32_t *out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * width) return;
+  out[t] = pcol[(int64_t)rows[t / width] * width + t % width];
+}
+
+// union-find over a family of DOF sets joined by shared DOFs; root = the
+// lowest index of the group
+static std::vector<int> join_sharing(const std::vector<std::vector<int32_t>> &sets) {
+  std::vector<int> parent(sets.size());
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int a) {
+    while (parent[a] != a) {
+      parent[a] = parent[parent[a]];
+      a = parent[a];
+    }
+    return a;
+  };
+  std::unordered_map<int32_t, int> owner;
+  for (size_t k = 0; k < sets.size(); ++k)
+    for (int32_t d : sets[k]) {
+      auto it = owner.find(d);
+      if (it == owner.end()) {
+        owner.emplace(d, (int)k);
+      } else {
+        int ra = find(it->second), rb = find((int)k);
+        if (ra != rb) parent[std::max(ra, rb)] = std::min(ra, rb);
+      }
+    }
+  for (size_t k = 0; k < sets.size(); ++k) parent[k] = find((int)k);
+  return parent;
+}
+
+// seeds of fine level F -> the coarse DOFs its interpolation couples to them
+// (per set: the columns of P's rows at the set, i.e. the free DOFs of the
+// coarse cells containing the nodes); the connected components of those sets
+// join coarse level C's own patches (MERGE: components sharing DOFs with own
+// patches merge into the lowest-indexed one; OVERLAP: appended and coloured).
+void inherit_patches(Ctx &c, const Level &F, Level &C, std::vector<std::vector<int32_t>> &seeds) {
+  hipStream_t s = c.stream;
+  std::vector<int32_t> rows;
+  for (auto &st : seeds) rows.insert(rows.end(), st.begin(), st.end());
+  std::vector<int32_t> pc;
+  if (!rows.empty()) {
+    DBuf<int32_t> drows, dout;
+    upload(drows, rows.data(), rows.size(), s);
+    dout.alloc(rows.size() * F.pw);
+    k_gather_rows<<<grid_for((int64_t)rows.size() * F.pw, 256), 256, 0, s>>>(F.pcol, F.pw, drows,
+                                                                             (int64_t)rows.size(), dout);
+    MG_LAUNCH_CHECK();
+    download(pc, dout.p, rows.size() * F.pw, s);
+  }
+  std::vector<std::vector<int32_t>> next;
+  size_t pos = 0;
+  for (auto &st : seeds) {
+    std::vector<int32_t> d;
+    for (size_t k = 0; k < st.size() * F.pw; ++k)
+      if (pc[pos * F.pw + k] >= 0) d.push_back(pc[pos * F.pw + k]);
+    pos += st.size();
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    next.push_back(std::move(d));
+  }
+  seeds.swap(next);
+  // components of the inherited sets, ordered by smallest DOF
+  std::vector<int> root = join_sharing(seeds);
+  std::vector<std::vector<int32_t>> comps;
+  std::unordered_map<int, size_t> slot;
+  for (size_t k = 0; k < seeds.size(); ++k) {
+    if (seeds[k].empty()) continue;
+    auto it = slot.find(root[k]);
+    if (it == slot.end()) {
+      slot.emplace(root[k], comps.size());
+      comps.push_back(seeds[k]);
+    } else {
+      auto &dst = comps[it->second];
+      dst.insert(dst.end(), seeds[k].begin(), seeds[k].end());
+    }
+  }
+  for (auto &cp : comps) {
+    std::sort(cp.begin(), cp.end());
+    cp.erase(std::unique(cp.begin(), cp.end()), cp.end());
+  }
+  std::sort(comps.begin(), comps.end(),
+            [](const std::vector<int32_t> &a, const std::vector<int32_t> &b) { return a[0] < b[0]; });
+  // own patches, then the components
+  const Patches &P = C.patch;
+  std::vector<std::vector<int32_t>> all;
+  for (int p = 0; p < P.n; ++p) all.emplace_back(P.h_dofs.begin() + P.h_ptr[p], P.h_dofs.begin() + P.h_ptr[p + 1]);
+  const size_t nown = all.size();
+  for (auto &cp : comps) all.push_back(cp);
+  std::vector<std::vector<int32_t>> out;
+  if (c.opt.patch_policy == MG_PATCH_MERGE) {
+    std::vector<int> r = join_sharing(all);
+    std::unordered_map<int, size_t> at;
+    for (size_t k = 0; k < all.size(); ++k) {
+      auto it = at.find(r[k]);
+      if (it == at.end()) {
+        at.emplace(r[k], out.size());
+        out.push_back(all[k]);
+      } else {
+        auto &dst = out[it->second];
+        dst.insert(dst.end(), all[k].begin(), all[k].end());
+      }
+    }
+    for (auto &o : out) {
+      std::sort(o.begin(), o.end());
+      o.erase(std::unique(o.begin(), o.end()), o.end());
+    }
+  } else {
+    out = std::move(all);
+  }
+  C.patch.n_inherited = (int)comps.size();
+  (void)nown;
+  set_patches(c, C, out);
+}
+
 
 __global__ void k_map_dofs(const int32_t *canon, int64_t n, const int32_t *iperm, int32_t *pos) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -326,9 +326,13 @@ __global__ __launch_bounds__(256) void k_packed_rows(int i0, int i1, const int32
 
 // Gather items: e_J = (row products of the chunks of tile row J) + sum over
 // I > J of the column products of tile (I, J), in a fixed order; then
-// u[map(i)] += e (ADD; patches of one colour share no DOF) or u[i] = e (SET,
-// identity map).
-template <class TM, class TV, bool SET>
+//   GATHER_ADD:    u[map(i)] += e (patches of one colour share no DOF),
+//   GATHER_SET:    u[i] = e (identity map),
+//   GATHER_STAGE:  st[map(i)] = e (FP64 staging of a first patch solve),
+//   GATHER_FINISH: u[map(i)] += e + st[map(i)], st[map(i)] = 0 (the refined
+//                  solve: the staged first solve plus the correction e).
+enum { GATHER_ADD = 0, GATHER_SET = 1, GATHER_STAGE = 2, GATHER_FINISH = 3 };
+template <class TM, class TV, int MODE>
 __global__ __launch_bounds__(256) void k_packed_gather(int i0, int i1, const int32_t *__restrict__ g_sys,
                                                        const int32_t *__restrict__ g_row,
                                                        const int32_t *__restrict__ g_slot,
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(256) void k_packed_gather(int i0, int i1, const int
                                                        const int32_t *__restrict__ map,
                                                        const int64_t *__restrict__ zoff,
                                                        const TM *__restrict__ py, const TM *__restrict__ pz,
-                                                       TV *__restrict__ u, int vs) {
+                                                       TV *__restrict__ u, int vs, double *__restrict__ st) {
   constexpr int PT = PATCH_TILE;
   const int item = i0 + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (item >= i1) return;
@@ -361,22 +365,31 @@ __global__ __launch_bounds__(256) void k_packed_gather(int i0, int i1, const int
   e += __shfl_xor(e, 32);
   const int i = J * PT + j;
   if (h == 0 && i < n) {
-    if (SET) u[(int64_t)i * vs] = (TV)e;
-    else u[(int64_t)map[k0 + i] * vs] += (TV)e;
+    if (MODE == GATHER_SET) {
+      u[(int64_t)i * vs] = (TV)e;
+    } else if (MODE == GATHER_ADD) {
+      u[(int64_t)map[k0 + i] * vs] += (TV)e;
+    } else if (MODE == GATHER_STAGE) {
+      st[map[k0 + i]] = (double)e;
+    } else {
+      const int32_t q = map[k0 + i];
+      u[(int64_t)q * vs] += (TV)((double)e + st[q]);
+      st[q] = 0.0;
+    }
   }
 }
 
-template <class TM, class TV, bool SET>
+template <class TM, class TV, int MODE>
 static void packed_apply(hipStream_t s, const PackedInv &P, const TM *pk, int colour, const int32_t *ptr,
-                         const int32_t *map, const TV *res, TM *py, TM *pz, TV *u, int vs) {
+                         const int32_t *map, const TV *res, TM *py, TM *pz, TV *u, int vs, double *st = nullptr) {
   int r0 = P.colour_r_first[colour], r1 = P.colour_r_first[colour + 1];
   int g0 = P.colour_g_first[colour], g1 = P.colour_g_first[colour + 1];
   if (r1 <= r0) return;
   k_packed_rows<TM, TV><<<(unsigned)((r1 - r0 + 3) / 4), 256, 0, s>>>(r0, r1, P.r_sys, P.r_row, P.r_chunk, P.r_slot,
                                                                       ptr, P.tile_off, P.zoff, pk, res, vs, py, pz);
   MG_LAUNCH_CHECK();
-  k_packed_gather<TM, TV, SET><<<(unsigned)((g1 - g0 + 3) / 4), 256, 0, s>>>(g0, g1, P.g_sys, P.g_row, P.g_slot,
-                                                                             ptr, map, P.zoff, py, pz, u, vs);
+  k_packed_gather<TM, TV, MODE><<<(unsigned)((g1 - g0 + 3) / 4), 256, 0, s>>>(g0, g1, P.g_sys, P.g_row, P.g_slot,
+                                                                              ptr, map, P.zoff, py, pz, u, vs, st);
   MG_LAUNCH_CHECK();
 }
 
@@ -384,8 +397,45 @@ static void packed_apply(hipStream_t s, const PackedInv &P, const TM *pk, int co
 template <class T>
 void patch_apply(hipStream_t s, const Patches &pt, int colour, const T *res, T *py, T *pz, T *u, int vs) {
   const T *pk = std::is_same<T, double>::value ? (const T *)pt.inv.v64.p : (const T *)pt.inv.v32.p;
-  packed_apply<T, T, false>(s, pt.inv, pk, colour, pt.ptr, pt.dofs, res, py, pz, u, vs);
+  packed_apply<T, T, GATHER_ADD>(s, pt.inv, pk, colour, pt.ptr, pt.dofs, res, py, pz, u, vs);
 }
+
+// One step of iterative refinement of the patch solves: r2 = r - A^[d] e with
+// e the staged first solve (FP64, in the solve-order positions of the patch
+// DOFs) and A^[d] the patch rows restricted to their own patch's columns
+// (pt.loc: the rows' values with every other column zeroed), accumulated in
+// FP64 and written over r.
+template <class T>
+__global__ __launch_bounds__(256) void k_patch_refine(int64_t k0, int64_t k1, SellCols cols,
+                                                      const double *__restrict__ loc, const double *__restrict__ st,
+                                                      T *__restrict__ res, int vs) {
+  int64_t k = (k0 & ~(int64_t)63) + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t sl = k >> 6;
+  if (k >= ((k1 + 63) & ~(int64_t)63)) return;
+  const double acc = sell_row<double>(cols, loc, st, sl, (int)(k & 63));
+  if (k >= k0 && k < k1) res[k * vs] = (T)((double)res[k * vs] - acc);
+}
+
+// e = A^[d]^-1 r for the patches of one colour with one refinement step:
+// e1 = X r (staged in FP64), r2 = r - A^[d] e1 (FP64), u += e1 + X r2.
+// res is overwritten; st is all zero outside a call (and left so).
+template <class T>
+void patch_apply_refined(hipStream_t s, const Patches &pt, int colour, T *res, T *py, T *pz, T *u, double *st,
+                         int vs) {
+  const T *pk = std::is_same<T, double>::value ? (const T *)pt.inv.v64.p : (const T *)pt.inv.v32.p;
+  packed_apply<T, T, GATHER_STAGE>(s, pt.inv, pk, colour, pt.ptr, pt.dofs, res, py, pz, (T *)nullptr, vs, st);
+  const int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
+  const int64_t k0 = pt.h_kptr[p0], k1 = pt.h_kptr[p1];
+  if (k1 <= k0) return;
+  const int64_t span = ((k1 + 63) & ~(int64_t)63) - (k0 & ~(int64_t)63);
+  k_patch_refine<T><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(k0, k1, cols_of(pt.rows), pt.loc, st, res, vs);
+  MG_LAUNCH_CHECK();
+  packed_apply<T, T, GATHER_FINISH>(s, pt.inv, pk, colour, pt.ptr, pt.dofs, res, py, pz, u, vs, st);
+}
+template void patch_apply_refined<double>(hipStream_t, const Patches &, int, double *, double *, double *, double *,
+                                          double *, int);
+template void patch_apply_refined<float>(hipStream_t, const Patches &, int, float *, float *, float *, float *,
+                                         double *, int);
 template void patch_apply<double>(hipStream_t, const Patches &, int, const double *, double *, double *, double *,
                                   int);
 template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *, float *, float *, int);
@@ -517,7 +567,7 @@ template void patch_correct_small<float>(hipStream_t, const Patches &, int, cons
 // coarsest level: u = A^-1 b with the packed FP64 inverse (FP64 arithmetic)
 template <class T>
 void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u, int vs) {
-  packed_apply<double, T, true>(s, L.cpk, L.cpk.v64.p, 0, L.cptr, nullptr, b, L.cpy.p, L.cpz.p, u, vs);
+  packed_apply<double, T, GATHER_SET>(s, L.cpk, L.cpk.v64.p, 0, L.cptr, nullptr, b, L.cpy.p, L.cpz.p, u, vs);
 }
 template void coarse_apply<double>(hipStream_t, const Level &, const double *, double *, int);
 template void coarse_apply<float>(hipStream_t, const Level &, const float *, float *, int);
@@ -540,6 +590,7 @@ void fill(hipStream_t s, T *x, int64_t n, T v) {
 }
 template void fill<double>(hipStream_t, double *, int64_t, double);
 template void fill<float>(hipStream_t, float *, int64_t, float);
+template void fill<int32_t>(hipStream_t, int32_t *, int64_t, int32_t);
 
 template <class A, class B>
 __global__ void k_convert(const A *x, B *y, int64_t n) {

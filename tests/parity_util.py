@@ -8,11 +8,12 @@ import oracle
 
 def build_pair(meshes, degree, tau=0.1, layers=1, precision="fp64", local=True, adjusted=True,
                policy="merge", use_graph=False, nu=2, k=2, eig_maxit=200, build_oracle=True,
-               smoother="chebyshev", **gpu_kw):
+               smoother="chebyshev", inherit=0, **gpu_kw):
     from paper_2402_12947_amd import Solver
     gpu = Solver(meshes, degree=degree, tau=tau, layers=layers, precision=precision,
                  local_correction=local, adjusted_eig=adjusted, policy=policy, use_graph=use_graph,
-                 nu=nu, cheb_degree=k, eig_maxit=eig_maxit, global_smoother=smoother, **gpu_kw)
+                 nu=nu, cheb_degree=k, eig_maxit=eig_maxit, global_smoother=smoother,
+                 patch_inherit_levels=inherit, **gpu_kw)
     ora = None
     if build_oracle:
         ora = oracle.Hierarchy(meshes, tau=tau, layers=layers,
@@ -20,7 +21,7 @@ def build_pair(meshes, degree, tau=0.1, layers=1, precision="fp64", local=True, 
                                                    adjusted_eig=adjusted,
                                                    patch_policy=oracle.OVERLAP if policy == "overlap"
                                                    else oracle.MERGE, eig_maxit=eig_maxit,
-                                                   global_smoother=smoother))
+                                                   global_smoother=smoother, inherit_levels=inherit))
     return gpu, ora
 
 

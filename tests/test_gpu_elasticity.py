@@ -1,16 +1,22 @@
 """GPU parity for linear elasticity (Sec. 6.2): vector P1/P2 on the 3D lattice
 and plane strain on the square, against the oracle: operators 1e-12 (fine) /
 1e-11 (Galerkin) relative, P (x) I transfers 1e-12, patch membership bit-exact,
-one sandwich and one V-cycle within 1e-10 + m eps kappa_max, PCG iterations
-within one and the solution 1e-8 (FP64) or 1e-6 (mixed, against the converged
-FP64 solution).
+one sandwich and one V-cycle within 1e-10 with refined patch solves
+(patch_refine), PCG iterations within one and the solution 1e-8 (FP64) or 1e-6
+(mixed, against the converged FP64 solution).
 
-The smoother and V-cycle bars: each patch solve applies the inverse of A^[d],
-whose computed result carries a relative rounding error of order
-eps kappa(A^[d]); the elasticity patches reach kappa = 1.6e5 (Poisson patches
-about 3e3), so m solves (2 per sandwich, 8 per level in a V(2,2) cycle) can
-differ from the oracle's by m eps kappa_max on top of the 1e-10 of the other
-steps."""
+Without refinement each patch solve applies the stored inverse of A^[d], whose
+result carries a relative rounding error of order eps kappa(A^[d]); the
+elasticity patches reach kappa = 1.6e5 (Poisson patches about 3e3), and the
+sandwich and V-cycle were measured 0.9-1.1e-10 from the oracle's; that case
+keeps a bar of 2.2e-10 (twice the measurement).  One refinement step of the
+patch solves brings the sandwich to 4e-13.  A whole cycle also carries the
+rounding of the coarse operators (the GPU's Galerkin products agree with the
+oracle's to 1e-11 and store no entries that vanish identically), amplified by
+the coarsest solve: 1.0e-10 on the P2 lattice against the oracle's own
+products, so that comparison keeps 2.2e-10 and the 1e-10 bar applies to the
+oracle's cycle on the GPU's coarse operators."""
+import copy
 import functools
 
 import numpy as np
@@ -31,15 +37,15 @@ CASES = {
 
 
 @functools.lru_cache(maxsize=None)
-def pair(name, precision="fp64", smoother="chebyshev"):
+def pair(name, precision="fp64", smoother="chebyshev", refine=False):
     from paper_2402_12947_amd import Solver
     wl, scale, degree = CASES[name]
     meshes = meshgen.hierarchy(wl, seed=0, scale=scale)
-    print(f"[elasticity {name} {precision} {smoother}]", flush=True)
+    print(f"[elasticity {name} {precision} {smoother} refine={refine}]", flush=True)
     gpu = Solver(meshes, degree=degree, tau=0.1, layers=1, precision=precision, problem="elasticity",
-                 global_smoother=smoother)
+                 global_smoother=smoother, patch_refine=refine)
     ora = None
-    if precision == "fp64":
+    if precision == "fp64" and not refine:
         ora = oracle.Hierarchy(meshes, tau=0.1, layers=1,
                                opts=oracle.Options(degree=degree, problem="elasticity", global_smoother=smoother))
     return gpu, ora
@@ -71,19 +77,30 @@ def patch_kappa(ora):
     return kappa, levels
 
 
+@pytest.mark.parametrize("refine", [True, False])
 @pytest.mark.parametrize("name", list(CASES))
-def test_smoother_vcycle_pcg(name):
-    gpu, ora = pair(name)
+def test_smoother_vcycle_pcg(name, refine):
+    gpu, _ = pair(name, refine=refine)
+    _, ora = pair(name)
     n = ora.levels[0].A.shape[0]
-    kappa, plevels = patch_kappa(ora)
-    eps = np.finfo(np.float64).eps
+    kappa, _ = patch_kappa(ora)
+    bar = 1e-10 if refine else 2.2e-10
     b, u0 = meshgen.random_rhs(n, 1), meshgen.random_rhs(n, 2)
     u = to_dev(u0)
     gpu.smooth(0, to_dev(b), u, 1)
-    assert rel_err(from_dev(u), ora.smooth(0, b, u0.copy(), 1)) < 1e-10 + 2 * eps * kappa
+    d_s = rel_err(from_dev(u), ora.smooth(0, b, u0.copy(), 1))
     u = to_dev(u0)
     gpu.vcycle(to_dev(b), u)
-    assert rel_err(from_dev(u), ora.vcycle(b, u0.copy())) < 1e-10 + 8 * max(plevels, 1) * eps * kappa
+    d_v = rel_err(from_dev(u), ora.vcycle(b, u0.copy()))
+    # the same cycle on the GPU's coarse operators: they agree with the
+    # oracle's Galerkin products to rounding (1e-11, test above), which the
+    # coarsest solve amplifies by its condition number in a whole cycle
+    same = copy.deepcopy(ora)
+    same.replace_coarse_operators([gpu.matrix(l) for l in range(1, gpu.n_levels)])
+    d_same = rel_err(from_dev(u), same.vcycle(b, u0.copy()))
+    print(f"[elasticity {name} refine={refine}] kappa_max {kappa:.2e}: sandwich {d_s:.2e}, V-cycle {d_v:.2e}, "
+          f"V-cycle on the GPU's coarse operators {d_same:.2e}", flush=True)
+    assert d_s < bar and d_same < bar and d_v < 2.2e-10
     x_o, it_o, conv_o, _ = ora.pcg(b, 1e-10, 300)
     u = to_dev(np.zeros(n))
     st = gpu.pcg(to_dev(b), u, 1e-10, 300)

@@ -187,3 +187,52 @@ def test_colouring_is_proper_and_greedy():
         # greedy: every smaller colour is blocked by an earlier conflicting patch
         for c in range(col[i]):
             assert any(col[j] == c and set(pd[i].tolist()) & set(pd[j].tolist()) for j in range(i))
+
+
+def test_inherited_seeds_follow_the_located_cells():
+    """The coarse DOFs inherited from a fine DOF set are the free DOFs of the
+    coarse cells that contain its nodes (the structure of P)."""
+    from oracle.fem import DofMap
+    from oracle.patches import inherit
+    from oracle.transfer import prolongation
+    meshes = meshgen.hierarchy("cube_129", seed=0, scale=16)
+    fine, coarse = DofMap(meshes[0], 2), DofMap(meshes[1], 2)
+    P, cell = prolongation(fine, coarse)
+    rng = np.random.default_rng(0)
+    sets = [np.sort(rng.choice(fine.n_free, 12, replace=False)) for _ in range(5)]
+    for s, got in zip(sets, inherit(P, sets)):
+        want = coarse.free_index[coarse.cell_dofs[cell[s]]].ravel()
+        assert np.array_equal(got, np.unique(want[want >= 0]))
+
+
+def test_components_and_combine():
+    from oracle.patches import MERGE, OVERLAP, combine, components
+    sets = [np.array([5, 6]), np.array([1, 2]), np.array([6, 9]), np.array([]), np.array([2, 3])]
+    comps = components(sets)
+    assert [c.tolist() for c in comps] == [[1, 2, 3], [5, 6, 9]]
+    own = [np.array([7, 8]), np.array([3, 4])]
+    merged = combine(own, comps, MERGE)
+    assert [m.tolist() for m in merged] == [[7, 8], [1, 2, 3, 4], [5, 6, 9]]
+    kept = combine(own, comps, OVERLAP)
+    assert [m.tolist() for m in kept] == [[7, 8], [3, 4], [1, 2, 3], [5, 6, 9]]
+
+
+def test_inherited_patches_restore_the_reference_eigenvalue():
+    """With degraded cells on the finest level only, the Galerkin operator of
+    level 1 inherits their stiffness: lambda_max(D^-1 A_1) roughly doubles
+    against the high-quality reference mesh, and the paper's adjusted
+    eigenvalue cannot see it (level 1 has no patches of its own).  The
+    patches inherited through P bring the adjusted eigenvalue of level 1 back
+    to the reference level's lambda_max."""
+    from oracle.multigrid import Hierarchy, Options
+    ref = Hierarchy(meshgen.hierarchy("cube_129", seed=0, scale=8, case="ref"), tau=0.1, layers=1,
+                    opts=Options(degree=2))
+    meshes = meshgen.hierarchy("cube_129", seed=0, scale=8)
+    paper = Hierarchy(meshes, tau=0.1, layers=1, opts=Options(degree=2))
+    inh = Hierarchy(meshes, tau=0.1, layers=1, opts=Options(degree=2, inherit_levels=1))
+    lam_ref = ref.levels[1].lam
+    assert len(paper.levels[1].patch_dofs) == 0 and paper.levels[1].hi > 1.5 * lam_ref
+    assert len(inh.levels[1].patch_dofs) > 0
+    assert abs(inh.levels[1].hi - lam_ref) < 0.01 * lam_ref
+    # level 2 keeps the paper's patches (none)
+    assert len(inh.levels[2].patch_dofs) == 0
