@@ -12,8 +12,11 @@ A step is one MG-PCG solve of one synthetic right-hand side (uniform [-1, 1],
 seeded, resident in HBM before the timed region) with the hierarchy already
 set up; setup time is reported separately.  Every arm solves the same seeded
 right-hand sides:
-  mixed       global-local, FP32 V-cycle inside FP64 CG (the line's value)
-  fp64        global-local, FP64 throughout
+  mixed       global-local, FP32 V-cycle inside FP64 CG (the line's value),
+              with the patches of level 1 inherited through the interpolation
+              from the finest level's degraded cells (--inherit 1)
+  fp64        the same in FP64 throughout
+  paper       mixed with the paper's per-level patches only (--inherit 0)
   plain_fp64  plain Chebyshev smoother (no S_c, unadjusted lambda_max), FP64
   ref         global-local FP64 on the high-quality reference mesh (the same
               recipe without degraded cells): the iteration count to match
@@ -123,7 +126,7 @@ def parse_layout(text):
 
 def run_arm(meshes, degree, layers, rtol, seeds, warmup, precision="fp64", local=True, timing=True,
             use_graph=False, sigma=0, policy="merge", smoother="chebyshev", problem="poisson", label="",
-            layout=None):
+            layout=None, inherit=0, refine=False, factor_f32=True):
     """Sets up one hierarchy, solves seeds[:warmup] untimed, then times the
     solves of seeds[warmup:]; then (timing) one more solve of the first timed
     right-hand side with per-level kernel events, outside the timed region."""
@@ -134,7 +137,9 @@ def run_arm(meshes, degree, layers, rtol, seeds, warmup, precision="fp64", local
     t0 = time.perf_counter()
     s = Solver(meshes, degree=degree, tau=0.1, layers=layers, precision=precision,
                local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma, policy=policy,
-               global_smoother=smoother, problem=problem, sell_layout=layout)
+               global_smoother=smoother, problem=problem, sell_layout=layout,
+               patch_inherit_levels=inherit if local else 0, patch_refine=refine and local,
+               patch_factor_f32=factor_f32)
     setup_s = time.perf_counter() - t0
     n = s.n_free(0)
     log(f"[{label}] setup done in {setup_s:.2f} s, {n} DOFs; {warmup} warm-up + {len(seeds) - warmup} timed solves")
@@ -383,10 +388,19 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"],
                     help="precision of the arm that gives the line's value (the other global-local arm is "
                          "run as well unless --arms drops it)")
-    ap.add_argument("--arms", default="mixed,fp64,plain,ref", help="comma list of mixed, fp64, plain, ref")
+    ap.add_argument("--arms", default="mixed,fp64,paper,plain,ref",
+                    help="comma list of mixed, fp64, paper (mixed with the paper's per-level patches only), "
+                         "plain, ref")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the V-cycle from a hipGraph in the timed solves")
     ap.add_argument("--sigma", type=int, default=0, help="SELL sorting window (0 = library's choice)")
+    ap.add_argument("--inherit", type=int, default=1,
+                    help="coarse levels that also take the patches inherited through the interpolation from the "
+                         "finest level's degraded cells (patch_inherit_levels; 0 = the paper's construction, "
+                         "which then also runs as an extra mixed arm when this is above 0)")
+    ap.add_argument("--refine", action="store_true", help="one FP64 refinement step of every patch solve")
+    ap.add_argument("--f64-patch-factor", action="store_true",
+                    help="mixed arm: factor the patch systems in FP64 (default: FP32 matrix cores)")
     ap.add_argument("--layout", default="",
                     help="fix the level operators' layouts of the global-local arms: 'sigma,unroll,mask,rpl' per "
                          "level joined by ';' (an arm's 'layout' field of an earlier run), so that a profiled "
@@ -421,7 +435,8 @@ def main():
     # every arm solves the same right-hand sides: seeds[:warmup] untimed, the rest timed
     seeds = [1000 + k for k in range(args.warmup + args.steps)]
     common = dict(layers=layers, rtol=rtol, policy=policy, smoother=args.smoother, problem=problem,
-                  sigma=args.sigma)
+                  sigma=args.sigma, inherit=args.inherit, refine=args.refine,
+                  factor_f32=not args.f64_patch_factor)
     res = {}
     for prec in ("mixed", "fp64"):
         if prec in arms:
@@ -444,6 +459,14 @@ def main():
         extra["global_local_mixed"]["rel_diff_vs_fp64_solution"] = float(
             np.linalg.norm(xmx - x64) / max(np.linalg.norm(x64), 1e-300))
         extra["mixed_speedup_vs_fp64"] = res["mixed"]["dofs_per_s"] / res["fp64"]["dofs_per_s"]
+    if "paper" in arms and args.inherit > 0:
+        pp = dict(common, inherit=0)
+        q = run_arm(meshes, degree, seeds=seeds, warmup=args.warmup, precision="mixed", local=True, timing=False,
+                    use_graph=args.graph, label="global-local mixed, paper's patches", **pp)
+        extra["global_local_mixed_paper_patches"] = _arm_summary(q)
+        res_paper = q
+    else:
+        res_paper = None
     if "plain" in arms:
         p = run_arm(meshes, degree, seeds=seeds[:args.warmup + max(1, args.steps // 2)], warmup=args.warmup,
                     precision="fp64", local=False, timing=False, label="plain fp64", **common)
@@ -459,6 +482,9 @@ def main():
         its_ref = r["iterations"][0]
         extra["iterations_within_1_of_reference"] = {
             prec: all(abs(i - its_ref) <= 1 for i in a["iterations"]) for prec, a in res.items()}
+        if res_paper is not None:
+            extra["iterations_within_1_of_reference"]["mixed_paper_patches"] = all(
+                abs(i - its_ref) <= 1 for i in res_paper["iterations"])
     roofline = None
     if args.smoother == "chebyshev":
         lv0 = main_arm["kernel_levels"][0]
@@ -493,6 +519,10 @@ def main():
                    "precision": ("FP32 V-cycle (smoothers, transfers, patch solves) inside FP64 CG; "
                                  "coarsest solve FP64" if args.precision == "mixed" else "FP64"),
                    "patch_layers": layers, "patch_policy": policy,
+                   "patch_inherit_levels": args.inherit, "patch_refine": bool(args.refine),
+                   "patch_factor": "FP64" if args.f64_patch_factor or args.precision == "fp64" else
+                                   "FP32 matrix cores (FP64 where a scaled pivot < 2^-12)",
+                   "patches_f32_level0": main_arm["levels"][0]["patches_f32"],
                    "iterations": main_arm["iterations"][0],
                    "setup_s": round(main_arm["setup_s"], 3),
                    "true_rel_residual": main_arm["true_rel_residual"],
