@@ -116,10 +116,12 @@ typedef struct {
   int32_t sell_rpl;         /* lanes per row of the level operators' sparse
                                products: 0 = chosen per level by timing,
                                1, 2, 4 or 8                                    */
-  int32_t patch_fused;      /* 1: a colour whose patches hold at most 256 DOFs
-                               and do not couple to each other runs its local
-                               correction as one launch; 0: always three
-                               launches (same result bitwise)                 */
+  int32_t patch_fused;      /* 1: a colour whose patches fit the level's
+                               one-workgroup class (patch_small_bound) and do
+                               not couple to each other runs its local
+                               correction as one launch, a coupled colour as
+                               two; 0: always three launches (the same result
+                               bitwise where a tile row fits one chunk)       */
   int32_t use_initial_guess; /* 0: the solvers (mg_pcg_solve and its block and
                                batch forms, mg_vcycle_solve) start from u = 0
                                and ignore u on entry; 1: they start from the u
@@ -161,6 +163,16 @@ typedef struct {
                                operator A_(l+1) = P^T A_l P carries the
                                degraded cells' stiffness into exactly those
                                rows                                            */
+  int32_t patch_chunk;      /* tiles per row item of the packed patch and
+                               coarsest inverses: 0 = chosen per level by
+                               timing (16, 8 or 32), else 8, 16 or 32        */
+  int32_t patch_small_bound; /* one-workgroup local correction (patches of up
+                               to this many DOFs in one launch per colour):
+                               0 = size class chosen per level by timing among
+                               128, 256 and 384 (and the three-launch path),
+                               128, 256 or 384 = that class where every patch
+                               fits it, -1 = always the three-launch path.
+                               Needs patch_fused = 1 and patch_refine = 0     */
   int32_t sell_layout_levels; /* number of levels that sell_layout covers      */
   const int32_t *sell_layout; /* NULL, or host [4 * sell_layout_levels]: for
                                level l the values (sigma, unroll, mask, rpl)
@@ -219,6 +231,11 @@ typedef struct {
   int64_t sell_slices_16window; /* of the multiwindow slices, those with 16   */
   int32_t patches_f32;      /* patches factored on the FP32 matrix cores       */
   int32_t patches_inherited; /* inherited components (patch_inherit_levels)   */
+  int32_t patch_small_bound; /* one-workgroup class used (128, 256, 384), 0 =
+                               the three-launch path                          */
+  int32_t patch_chunk;      /* tiles per row item of the level's packed
+                               inverses (patches; the coarsest level: its
+                               inverse)                                        */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -251,7 +268,8 @@ enum {
  * global_smoother MG_SMOOTHER_CHEBYSHEV, problem MG_PROBLEM_POISSON,
  * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
  * patch_fused 1, use_initial_guess 0, sell_colform 0, patch_factor_f32 1,
- * patch_refine 0, patch_inherit_levels 0, sell_layout_levels 0, sell_layout NULL. */
+ * patch_refine 0, patch_inherit_levels 0, patch_chunk 0, patch_small_bound 0,
+ * sell_layout_levels 0, sell_layout NULL. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

@@ -42,7 +42,8 @@ class MgOptions(C.Structure):
                 ("poisson_ratio", C.c_double), ("sell_unroll", C.c_int32), ("sell_mask", C.c_int32),
                 ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32), ("use_initial_guess", C.c_int32),
                 ("sell_colform", C.c_int32), ("patch_factor_f32", C.c_int32), ("patch_refine", C.c_int32),
-                ("patch_inherit_levels", C.c_int32),
+                ("patch_inherit_levels", C.c_int32), ("patch_chunk", C.c_int32),
+                ("patch_small_bound", C.c_int32),
                 ("sell_layout_levels", C.c_int32),
                 ("sell_layout", C.POINTER(C.c_int32))]
 
@@ -66,7 +67,8 @@ class MgLevelInfo(C.Structure):
                 ("patch_fused_colours", C.c_int32), ("sell_slices", C.c_int64),
                 ("sell_slices_multiwindow", C.c_int64), ("sell_slices_32bit", C.c_int64),
                 ("sell_slices_16window", C.c_int64), ("patches_f32", C.c_int32),
-                ("patches_inherited", C.c_int32)]
+                ("patches_inherited", C.c_int32), ("patch_small_bound", C.c_int32),
+                ("patch_chunk", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -160,7 +162,7 @@ class Solver:
                  poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1, sell_rpl: int = 0,
                  patch_fused: bool = True, use_initial_guess: bool = False, sell_layout=None,
                  sell_colform: int = 0, patch_factor_f32: bool = True, patch_refine: bool = False,
-                 patch_inherit_levels: int = 0):
+                 patch_inherit_levels: int = 0, patch_chunk: int = 0, patch_small_bound: int = 0):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -193,6 +195,8 @@ class Solver:
         opt.patch_factor_f32 = int(bool(patch_factor_f32))
         opt.patch_refine = int(bool(patch_refine))
         opt.patch_inherit_levels = patch_inherit_levels
+        opt.patch_chunk = patch_chunk
+        opt.patch_small_bound = patch_small_bound
         keep: list = []
         if sell_layout:  # [(sigma, unroll, mask, rpl) per level]
             lay = np.ascontiguousarray(np.asarray(sell_layout, dtype=np.int32).reshape(-1, 4))

@@ -93,6 +93,138 @@ void ensure_work(Ctx &c, Level &L) {
 // ---------------------------------------------------------------------------
 // smoother and V-cycle
 // ---------------------------------------------------------------------------
+template <class T>
+static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending);
+
+// device time (ms) of f() on the context's stream: the average launch of the
+// fastest of three batches of five (clock and boost changes only slow a batch)
+template <class F>
+static double time_on_stream(Ctx &c, F f) {
+  hipEvent_t e0, e1;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  struct G {
+    hipEvent_t a, b;
+    ~G() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } g{e0, e1};
+  f();
+  float best = -1;
+  for (int batch = 0; batch < 3; ++batch) {
+    MG_HIP(hipEventRecord(e0, c.stream));
+    for (int r = 0; r < 5; ++r) f();
+    MG_HIP(hipEventRecord(e1, c.stream));
+    MG_HIP(hipEventSynchronize(e1));
+    float t = 0;
+    MG_HIP(hipEventElapsedTime(&t, e0, e1));
+    if (best < 0 || t < best) best = t;
+  }
+  return best / 5.0;
+}
+
+// Patch-path autotuner of a level (setup): the packed-row chunk of the patch
+// inverses (8, 16 or 32 tiles per row item) and the one-workgroup size class
+// of the local correction (patches of up to 128, 256 or 384 DOFs, or the
+// three-launch path), each timed on the level's whole local correction; of
+// the candidates within 2 % of the fastest the first of the order (chunk 16,
+// then 8, 32; the smallest one-workgroup class, then the larger ones, then the
+// three-launch path) is kept, so that timing noise rarely changes the choice.
+// The chunk sets the order in which a tile row's products are summed; the
+// size class changes no result.  Levels whose patch inverses hold fewer than
+// 4096 tiles keep chunk 16 and the smallest class (launch latency decides
+// there).  The coarsest inverse's chunk is timed the same way (n >= 2048).
+static void tune_patches(Ctx &c, Level &L) {
+  const bool mixed = c.opt.precision == MG_MIXED;
+  if (L.coarsest) {
+    const int64_t n = L.nfree;
+    const int fixed = c.opt.patch_chunk;
+    if (fixed == 0 && n < 2048) return;
+    std::vector<int32_t> kptr = {0, (int32_t)n};
+    std::vector<int> cf = {0, 1};
+    std::vector<int> cand = fixed ? std::vector<int>{fixed} : std::vector<int>{16, 8, 32};
+    if (cand.size() == 1 && cand[0] == L.cpk.chunk) return;
+    DBuf<double> b, u;
+    b.alloc(n);
+    u.alloc(n);
+    fill<double>(c.stream, b.p, n, 0.5);
+    double best = -1;
+    int pick = cand[0];
+    for (int ch : cand) {
+      build_packed_layout(c.stream, kptr, cf, L.cpk, ch);
+      L.cpy.alloc(L.cpk.ysize);
+      const double t = time_on_stream(c, [&] { coarse_apply<double>(c.stream, L, b.p, u.p); });
+      if (best < 0 || t < 0.98 * best) {
+        if (best < 0 || t < best) best = t;
+        pick = ch;
+      }
+    }
+    if (L.cpk.chunk != pick) {
+      build_packed_layout(c.stream, kptr, cf, L.cpk, pick);
+      L.cpy.alloc(L.cpk.ysize);
+    }
+    return;
+  }
+  Patches &P = L.patch;
+  P.small_nb = 0;
+  if (P.n == 0 || !c.opt.local_correction) return;
+  // size classes that take every patch of the level
+  std::vector<int> nbs;
+  if (c.opt.patch_fused && !c.opt.patch_refine && P.rows.rpl == 1) {
+    if (c.opt.patch_small_bound > 0) {
+      if (c.opt.patch_small_bound >= P.maxn) nbs.push_back(c.opt.patch_small_bound / PATCH_TILE);
+    } else if (c.opt.patch_small_bound == 0) {
+      for (int nb : {4, 8, 12})
+        if (nb * PATCH_TILE >= P.maxn) nbs.push_back(nb);
+    }
+  }
+  std::vector<int> chunks = c.opt.patch_chunk ? std::vector<int>{c.opt.patch_chunk} : std::vector<int>{16, 8, 32};
+  const int64_t tiles = P.inv.packed / (PATCH_TILE * PATCH_TILE);
+  const bool timed = tiles >= 4096;
+  auto relayout = [&](int ch) {
+    if (P.inv.chunk == ch) return;
+    build_packed_layout(c.stream, P.h_kptr, P.colour_first, P.inv, ch);
+    if (mixed) L.py32.alloc(P.inv.ysize); else L.py64.alloc(P.inv.ysize);
+  };
+  if (!timed) {
+    relayout(chunks[0]);
+    if (!nbs.empty()) P.small_nb = nbs[0];
+    return;
+  }
+  auto run = [&] {
+    if (mixed) local_correction<float>(c, L, L.w32[0], L.w32[1], false);
+    else local_correction<double>(c, L, L.w64[0], L.w64[1], false);
+  };
+  if (mixed) {
+    fill<float>(c.stream, L.w32[0], L.nfree, 0.5f);
+    fill<float>(c.stream, L.w32[1], L.nfree, 0.5f);
+  } else {
+    fill<double>(c.stream, L.w64[0], L.nfree, 0.5);
+    fill<double>(c.stream, L.w64[1], L.nfree, 0.5);
+  }
+  // the chunk, on the three-launch path
+  double best = -1;
+  int pick = chunks[0];
+  for (int ch : chunks) {
+    relayout(ch);
+    const double t = time_on_stream(c, run);
+    if (best < 0 || t < 0.98 * best) {
+      if (best < 0 || t < best) best = t;
+      pick = ch;
+    }
+  }
+  relayout(pick);
+  // the size class (or the three-launch path, timed above)
+  double best_nb = -1;
+  int pick_nb = 0;
+  for (int nb : nbs) {
+    P.small_nb = nb;
+    const double t = time_on_stream(c, run);
+    if (best_nb < 0 || t < 0.98 * best_nb) {
+      if (best_nb < 0 || t < best_nb) best_nb = t;
+      pick_nb = nb;
+    }
+  }
+  P.small_nb = (best_nb >= 0 && best_nb <= 1.02 * best) ? pick_nb : 0;
+}
 // slot: the level of a full Chebyshev step, or the coarsest level's index
 // for the coarsest solve
 static void time_begin(Ctx &c, int slot) {
@@ -125,12 +257,12 @@ static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending
       patch_apply_refined<T>(c.stream, L.patch, col, LV<T>::res(L), LV<T>::py(L), LV<T>::pz(L), u, L.pst.p);
       continue;
     }
-    if (L.patch.colour_fused[col]) {
+    if (L.patch.small_nb && L.patch.colour_fused[col]) {
       patch_correct_small<T>(c.stream, L.patch, col, b, (const T *)nullptr, u);
       continue;
     }
     patch_residual<T>(c.stream, L.patch, col, b, u, LV<T>::res(L));
-    if (c.opt.patch_fused && L.patch.maxn <= SMALL_PATCH) {
+    if (L.patch.small_nb) {
       patch_correct_small<T>(c.stream, L.patch, col, b, LV<T>::res(L), u);
       continue;
     }
@@ -646,6 +778,8 @@ void mg_default_options(mg_options *o) {
   o->patch_factor_f32 = 1;
   o->patch_refine = 0;
   o->patch_inherit_levels = 0;
+  o->patch_chunk = 0;
+  o->patch_small_bound = 0;
   o->sell_layout_levels = 0;
   o->sell_layout = nullptr;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
@@ -714,6 +848,11 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.patch_factor_f32 != 0 && o.patch_factor_f32 != 1) fail(MG_ERR_ARG, "patch_factor_f32 must be 0 or 1");
     if (o.patch_refine != 0 && o.patch_refine != 1) fail(MG_ERR_ARG, "patch_refine must be 0 or 1");
     if (o.patch_inherit_levels < 0) fail(MG_ERR_ARG, "patch_inherit_levels must be >= 0");
+    if (o.patch_chunk != 0 && o.patch_chunk != 8 && o.patch_chunk != 16 && o.patch_chunk != 32)
+      fail(MG_ERR_ARG, "patch_chunk must be 0, 8, 16 or 32");
+    if (o.patch_small_bound != 0 && o.patch_small_bound != -1 && o.patch_small_bound != 128 &&
+        o.patch_small_bound != 256 && o.patch_small_bound != 384)
+      fail(MG_ERR_ARG, "patch_small_bound must be 0, -1, 128, 256 or 384");
     if (o.sell_layout_levels < 0 || (o.sell_layout_levels > 0 && !o.sell_layout))
       fail(MG_ERR_ARG, "sell_layout must hold 4 values for each of sell_layout_levels levels");
     for (int l = 0; l < o.sell_layout_levels; ++l) {
@@ -827,6 +966,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
         phase("coarsest factorisation", l);
       }
       ensure_work(c, L);
+      tune_patches(c, L);
       L.setup_ms += ms(t0, now());
     }
     int64_t n0 = c.lv[0].nfree;
@@ -1249,7 +1389,8 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
   o->sell_mask = L.S.mask;
   o->sell_rpl = L.S.rpl;
   o->patch_fused_colours = 0;
-  for (uint8_t f : L.patch.colour_fused) o->patch_fused_colours += f;
+  if (L.patch.small_nb)
+    for (uint8_t f : L.patch.colour_fused) o->patch_fused_colours += f;
   o->sell_slices = L.S.nslices;
   if (level < (int)h->slice_forms.size()) {
     o->sell_slices_multiwindow = h->slice_forms[level][0];
@@ -1257,6 +1398,8 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
     o->sell_slices_16window = h->slice_forms[level][2];
     o->patches_f32 = L.patch.n_factor32;
     o->patches_inherited = L.patch.n_inherited;
+    o->patch_small_bound = L.patch.small_nb * PATCH_TILE;
+    o->patch_chunk = L.coarsest ? L.cpk.chunk : L.patch.inv.chunk;
   }
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;

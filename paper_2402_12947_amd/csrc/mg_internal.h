@@ -144,9 +144,10 @@ struct Csr {
 // I at zoff[k] + 32 (J nb - J (J + 1) / 2) + 32 (I - J - 1)), then over gather
 // items (system, tile row J) that add them up in a fixed order.
 constexpr int PATCH_TILE = 32;
-constexpr int PACK_CHUNK = 16;
+constexpr int PACK_CHUNK = 16;  // default tiles per row item (chosen per level by timing)
 struct PackedInv {
   int64_t packed = 0, ysize = 0, zsize = 0;
+  int chunk = PACK_CHUNK;                       // tiles per row item: 8, 16 or 32
   DBuf<int64_t> tile_off, zoff;                 // [systems]
   DBuf<int32_t> r_sys, r_row, r_chunk, r_slot;  // row items
   DBuf<int32_t> g_sys, g_row, g_slot;           // gather items (first slot of the row)
@@ -155,7 +156,7 @@ struct PackedInv {
   DBuf<float> v32;
 };
 void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const std::vector<int> &colour_first,
-                         PackedInv &P);
+                         PackedInv &P, int chunk = PACK_CHUNK);
 
 // Patches of one level in kernel order (sorted by colour, then canonical id).
 struct Patches {
@@ -179,10 +180,13 @@ struct Patches {
   // the row's own patch zeroed (A^[d] in the layout of rows), for the
   // refinement residual of the patch solves
   DBuf<double> loc;
-  // per colour: 1 if every patch holds at most SMALL_PATCH DOFs and no patch
-  // row couples to a DOF of another patch of the colour, so that one launch
-  // per colour (patch_correct_small) equals the residual of all patches
-  // followed by all corrections
+  // tile rows per patch of the one-workgroup local correction
+  // (patch_correct_small: 4, 8 or 12, i.e. patches of up to 128, 256 or 384
+  // DOFs), 0 = the three-launch path; chosen per level by timing
+  int small_nb = 0;
+  // per colour: 1 if no patch row couples to a DOF of another patch of the
+  // colour, so that one launch per colour (patch_correct_small without a
+  // residual) equals the residual of all patches followed by all corrections
   std::vector<uint8_t> colour_fused;
   // the rows of A that couple to a patch DOF (ascending solve order) and their
   // solve-order positions: after the local correction from u = 0, u vanishes
@@ -368,7 +372,7 @@ void patch_apply_refined(hipStream_t s, const Patches &pt, int colour, T *res, T
 // local correction of one colour (residual, product with the packed inverse,
 // update of u) in one launch (colour_fused colours only); else the product
 // and the update, from the residual res of patch_residual.
-constexpr int SMALL_PATCH = 256;
+constexpr int SMALL_PATCH = 384;  // largest patch of the one-workgroup path (12 tile rows)
 template <class T>
 void patch_correct_small(hipStream_t s, const Patches &pt, int colour, const T *b, const T *res, T *u);
 template <class T>

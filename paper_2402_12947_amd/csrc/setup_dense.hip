@@ -2,20 +2,23 @@
 // the local correction (paper Sec. 4.1, eqs. local_system and local) and the
 // coarsest-level system (Sec. 2, direct solver on the coarsest grid).
 //
-// Each system is factored A = L L^T (Cholesky, FP64) and the factor is turned
-// into the explicit inverse A^-1 = L^-T L^-1, which the solve phase applies as
-// a dense matrix-vector product: that product is fully parallel, whereas a
-// triangular substitution is a chain of n dependent steps.
+// Each system is factored A = L L^T (Cholesky) and the factor is turned into
+// the explicit inverse A^-1 = L^-T L^-1, which the solve phase applies as a
+// dense matrix-vector product over packed lower 32 x 32 tiles: that product is
+// fully parallel, whereas a triangular substitution is a chain of n dependent
+// steps.
 //
-// * Patches: one workgroup per patch of up to 384 DOFs.  The patch matrix is
-//   gathered from the CSR operator, factored by a right-looking column sweep,
-//   and inverted by forward/backward substitution with one thread per column
-//   of the identity.  Larger patches go one at a time through the blocked path
-//   below.
-// * Coarsest level (large n): blocked right-looking Cholesky with 64x64 tiles
-//   (diagonal factor, panel triangular solve, trailing symmetric update), then
-//   W = L^-1 by a right-looking block solve of L W = I, and A^-1 = W^T W, all
-//   from 64x64x64 LDS-tiled FP64 products.
+// * Patches of up to BATCH_MAX DOFs: one workgroup per patch on the matrix
+//   cores (setup_patchfactor.hip; FP64, or FP32 after equilibration in the
+//   mixed cycle).  Larger patches go one at a time through the blocked path
+//   below.  factor_patches packs every inverse in the cycle's precision.
+// * Coarsest level (n above 512; smaller ones in one workgroup): blocked
+//   right-looking Cholesky with 64 x 64 tiles (diagonal tile factored in LDS,
+//   panel triangular solve, trailing symmetric update), then W = L^-1 by a
+//   right-looking block solve of L W = I, and A^-1 = W^T W.  The 64 x 64 x 64
+//   tile products (trailing update, block solve, W^T W) run on the FP64
+//   matrix cores (v_mfma_f64_16x16x4, mfma_tile.h); the diagonal tiles are
+//   factored and inverted in LDS on the vector units.
 #include <cmath>
 
 #include "devutil.h"

@@ -414,7 +414,8 @@ __global__ void k_map_dofs(const int32_t *canon, int64_t n, const int32_t *iperm
 // Item lists and offsets of a set of packed symmetric inverses; kptr[k]..kptr[k+1]
 // is the index range of system k, colour_first the system ranges per colour.
 void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const std::vector<int> &colour_first,
-                         PackedInv &P) {
+                         PackedInv &P, int chunk) {
+  P.chunk = chunk;
   const int ns = (int)kptr.size() - 1, ncol = (int)colour_first.size() - 1;
   std::vector<int64_t> toff(ns), zoff(ns);
   std::vector<int32_t> rs, rr, rc, rslot, gs, gr, gslot;
@@ -435,7 +436,7 @@ void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const 
         gs.push_back(k);
         gr.push_back((int32_t)I);
         gslot.push_back(slot);
-        for (int64_t c = 0; c * PACK_CHUNK <= I; ++c) {
+        for (int64_t c = 0; c * chunk <= I; ++c) {
           rs.push_back(k);
           rr.push_back((int32_t)I);
           rc.push_back((int32_t)c);
@@ -454,7 +455,7 @@ void build_packed_layout(hipStream_t s, const std::vector<int32_t> &kptr, const 
     const int a = P.colour_r_first[col], b = P.colour_r_first[col + 1];
     std::vector<int> ord(b - a);
     for (int q = 0; q < b - a; ++q) ord[q] = a + q;
-    auto tiles = [&](int q) { return std::min(rr[q] + 1, (rc[q] + 1) * PACK_CHUNK) - rc[q] * PACK_CHUNK; };
+    auto tiles = [&](int q) { return std::min(rr[q] + 1, (rc[q] + 1) * chunk) - rc[q] * chunk; };
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return tiles(x) > tiles(y); });
     std::vector<int32_t> t0(b - a), t1(b - a), t2(b - a), t3(b - a);
     for (int q = 0; q < b - a; ++q) {

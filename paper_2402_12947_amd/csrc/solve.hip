@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_packed_rows(int i0, int i1, const int32
                                                      const int64_t *__restrict__ toff,
                                                      const int64_t *__restrict__ zoff, const TM *__restrict__ pk,
                                                      const TV *__restrict__ res, int vs, TM *__restrict__ py,
-                                                     TM *__restrict__ pz) {
+                                                     TM *__restrict__ pz, int chunk) {
   constexpr int PT = PATCH_TILE;
   __shared__ TM tl[4][PT][PT + 1];
   __shared__ TM rl[4][PT];
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_packed_rows(int i0, int i1, const int32
   TM(*Ts)[PT + 1] = tl[wave];
   TM *Rs = rl[wave];
   const int k = r_sys[item], I = r_row[item];
-  const int J0 = r_chunk[item] * PACK_CHUNK, J1 = min(I + 1, J0 + PACK_CHUNK);
+  const int J0 = r_chunk[item] * chunk, J1 = min(I + 1, J0 + chunk);
   const int k0 = ptr[k], n = ptr[k + 1] - k0, nb = (n + PT - 1) / PT;
   const TV *r = res + (int64_t)k0 * vs;  // entry i of the system at r[i vs]
   TM rI[16];
@@ -340,14 +340,15 @@ __global__ __launch_bounds__(256) void k_packed_gather(int i0, int i1, const int
                                                        const int32_t *__restrict__ map,
                                                        const int64_t *__restrict__ zoff,
                                                        const TM *__restrict__ py, const TM *__restrict__ pz,
-                                                       TV *__restrict__ u, int vs, double *__restrict__ st) {
+                                                       TV *__restrict__ u, int vs, double *__restrict__ st,
+                                                       int chunk) {
   constexpr int PT = PATCH_TILE;
   const int item = i0 + (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (item >= i1) return;
   const int lane = threadIdx.x & 63, h = lane >> 5, j = lane & 31;
   const int k = g_sys[item], J = g_row[item];
   const int k0 = ptr[k], n = ptr[k + 1] - k0, nb = (n + PT - 1) / PT;
-  const int nch = J / PACK_CHUNK + 1;
+  const int nch = J / chunk + 1;
   TM e0 = 0, e1 = 0, e2 = 0, e3 = 0;
   const TM *y = py + (int64_t)g_slot[item] * PT + j;
   for (int c = h; c < nch; c += 2) e0 += y[(int64_t)c * PT];
@@ -386,10 +387,12 @@ static void packed_apply(hipStream_t s, const PackedInv &P, const TM *pk, int co
   int g0 = P.colour_g_first[colour], g1 = P.colour_g_first[colour + 1];
   if (r1 <= r0) return;
   k_packed_rows<TM, TV><<<(unsigned)((r1 - r0 + 3) / 4), 256, 0, s>>>(r0, r1, P.r_sys, P.r_row, P.r_chunk, P.r_slot,
-                                                                      ptr, P.tile_off, P.zoff, pk, res, vs, py, pz);
+                                                                      ptr, P.tile_off, P.zoff, pk, res, vs, py, pz,
+                                                                      P.chunk);
   MG_LAUNCH_CHECK();
   k_packed_gather<TM, TV, MODE><<<(unsigned)((g1 - g0 + 3) / 4), 256, 0, s>>>(g0, g1, P.g_sys, P.g_row, P.g_slot,
-                                                                              ptr, map, P.zoff, py, pz, u, vs, st);
+                                                                              ptr, map, P.zoff, py, pz, u, vs, st,
+                                                                              P.chunk);
   MG_LAUNCH_CHECK();
 }
 
@@ -440,29 +443,29 @@ template void patch_apply<double>(hipStream_t, const Patches &, int, const doubl
                                   int);
 template void patch_apply<float>(hipStream_t, const Patches &, int, const float *, float *, float *, float *, int);
 
-// The local correction of one colour whose patches all hold at most
-// SMALL_PATCH DOFs, one workgroup per patch, in one launch instead of three:
-// the patch-row residual (whole SELL slices per wavefront, as in
-// k_patch_residual), then one wavefront per tile row I of the packed inverse
-// (the tile row is a single chunk, as nb <= PACK_CHUNK, and the steps are
-// those of k_packed_rows), then one wavefront per tile row J adding the row
-// products and the column products of the tiles below in k_packed_gather's
-// order.  The residual, the row products and the column products stay in LDS;
-// every sum is formed as in the three-kernel path, so the result is bitwise
-// the same.  With res given, the residual of the colour's patch rows comes
+// The local correction of one colour whose patches all hold at most NB tile
+// rows (NB = 4, 8 or 12: 128, 256 or 384 DOFs), one workgroup per patch, in
+// one launch instead of three: the patch-row residual (whole SELL slices per
+// wavefront, as in k_patch_residual), then one wavefront per tile row I of
+// the packed inverse (the steps of k_packed_rows with the whole tile row as
+// one chunk), then one wavefront per tile row J adding the row products and
+// the column products of the tiles below in k_packed_gather's order.  The
+// residual, the row products and the column products stay in LDS; every sum
+// is formed as in the three-kernel path whenever a tile row fits one chunk of
+// the packed layout, so the result is then bitwise the same (and the same for
+// every NB).  With res given, the residual of the colour's patch rows comes
 // from k_patch_residual (patches whose rows read DOFs of other patches of the
 // colour need every residual before any update) and the launch replaces the
 // two launches of the packed product.
-template <class T>
+template <class T, int NB>
 __global__ __launch_bounds__(256) void k_patch_small(int p0, SellCols cols, const T *__restrict__ val,
                                                      const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ dofs,
                                                      const int64_t *__restrict__ toff, const T *__restrict__ pk,
                                                      const T *__restrict__ b, const T *__restrict__ res,
                                                      T *__restrict__ u) {
-  constexpr int PT = PATCH_TILE, NB = SMALL_PATCH / PATCH_TILE;
-  static_assert(NB <= PACK_CHUNK, "a tile row of a small patch is one chunk");
-  __shared__ T rs[SMALL_PATCH];
+  constexpr int PT = PATCH_TILE;
+  __shared__ T rs[NB * PT];
   __shared__ T ys[NB][PT];
   __shared__ T zs[NB * (NB - 1) / 2][PT];
   __shared__ T tl[4][PT][PT + 1];
@@ -484,9 +487,10 @@ __global__ __launch_bounds__(256) void k_patch_small(int p0, SellCols cols, cons
   __syncthreads();
   const int h = lane >> 5, j = lane & 31;
   // 2. tile rows: row products into ys, column products into zs; tile row I
-  // holds I + 1 tiles, so wavefront w takes rows w and nb - 1 - w (nb <= 8)
+  // holds I + 1 tiles, so rows I and nb - 1 - I form a pair of nb + 1 tiles
+  // and wavefront w takes the pairs w, w + 4, ...
   for (int I = 0; I < nb; ++I) {
-    if (min(I, nb - 1 - I) != wave) continue;
+    if (min(I, nb - 1 - I) % 4 != wave) continue;
     T(*Ts)[PT + 1] = tl[wave];
     T *Rs = rl[wave];
     T rI[16];
@@ -554,10 +558,21 @@ template <class T>
 void patch_correct_small(hipStream_t s, const Patches &pt, int colour, const T *b, const T *res, T *u) {
   const int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
   if (p1 <= p0) return;
-  if (pt.maxn > SMALL_PATCH || pt.rows.rpl != 1) fail(MG_ERR_ARG, "patch_correct_small: patches too large");
+  if (pt.small_nb * PATCH_TILE < pt.maxn || pt.rows.rpl != 1)
+    fail(MG_ERR_ARG, "patch_correct_small: patches too large");
   const T *pk = std::is_same<T, double>::value ? (const T *)pt.inv.v64.p : (const T *)pt.inv.v32.p;
-  k_patch_small<T><<<(unsigned)(p1 - p0), 256, 0, s>>>(p0, cols_of(pt.rows), sell_vals<T>(pt.rows), pt.ptr,
-                                                      pt.dofs, pt.inv.tile_off, pk, b, res, u);
+  const unsigned g = (unsigned)(p1 - p0);
+  if (pt.small_nb == 4)
+    k_patch_small<T, 4><<<g, 256, 0, s>>>(p0, cols_of(pt.rows), sell_vals<T>(pt.rows), pt.ptr, pt.dofs,
+                                         pt.inv.tile_off, pk, b, res, u);
+  else if (pt.small_nb == 8)
+    k_patch_small<T, 8><<<g, 256, 0, s>>>(p0, cols_of(pt.rows), sell_vals<T>(pt.rows), pt.ptr, pt.dofs,
+                                         pt.inv.tile_off, pk, b, res, u);
+  else if (pt.small_nb == 12)
+    k_patch_small<T, 12><<<g, 256, 0, s>>>(p0, cols_of(pt.rows), sell_vals<T>(pt.rows), pt.ptr, pt.dofs,
+                                          pt.inv.tile_off, pk, b, res, u);
+  else
+    fail(MG_ERR_ARG, "patch_correct_small: no one-workgroup size class");
   MG_LAUNCH_CHECK();
 }
 template void patch_correct_small<double>(hipStream_t, const Patches &, int, const double *, const double *,

@@ -89,7 +89,8 @@ def test_fused_patch_correction_agrees_bitwise(precision, scale, one_launch):
     out = {}
     for fused in (True, False):
         s = Solver(meshes, degree=2, layers=1, precision=precision, sell_sigma=128, sell_unroll=8,
-                   sell_mask=0, sell_rpl=1, patch_fused=fused)
+                   sell_mask=0, sell_rpl=1, patch_fused=fused, patch_chunk=16,
+                   patch_small_bound=256 if fused else -1)
         info = s.level_info(0)
         assert info["max_patch"] <= 256
         assert info["patch_fused_colours"] == (int(one_launch) if fused else 0)
