@@ -106,13 +106,6 @@ def level_bytes(info, precision, cheb_degree=2):
     return s8d, compressed
 
 
-def coarse_bytes(n):
-    """Bytes of one coarsest solve: the packed lower 32x32 tiles of the FP64
-    inverse once, the right-hand side and solution vectors."""
-    t = (n + 31) // 32
-    return 8.0 * 1024 * t * (t + 1) // 2 + 16.0 * n
-
-
 def layout_string(levels):
     """The level operators' layout choices as 'sigma,unroll,mask,rpl' per
     level, joined by ';' (what --layout takes to repeat them)."""
@@ -126,7 +119,7 @@ def parse_layout(text):
 
 def run_arm(meshes, degree, layers, rtol, seeds, warmup, precision="fp64", local=True, timing=True,
             use_graph=False, sigma=0, policy="merge", smoother="chebyshev", problem="poisson", label="",
-            layout=None, inherit=0, refine=False, factor_f32=True):
+            layout=None, inherit=0, refine=False, factor_f32=True, coarse_solver=0, coarse_leaf=1024):
     """Sets up one hierarchy, solves seeds[:warmup] untimed, then times the
     solves of seeds[warmup:]; then (timing) one more solve of the first timed
     right-hand side with per-level kernel events, outside the timed region."""
@@ -139,7 +132,7 @@ def run_arm(meshes, degree, layers, rtol, seeds, warmup, precision="fp64", local
                local_correction=local, adjusted_eig=local, use_graph=use_graph, sell_sigma=sigma, policy=policy,
                global_smoother=smoother, problem=problem, sell_layout=layout,
                patch_inherit_levels=inherit if local else 0, patch_refine=refine and local,
-               patch_factor_f32=factor_f32)
+               patch_factor_f32=factor_f32, coarse_solver=coarse_solver, coarse_nd_leaf=coarse_leaf)
     setup_s = time.perf_counter() - t0
     n = s.n_free(0)
     log(f"[{label}] setup done in {setup_s:.2f} s, {n} DOFs; {warmup} warm-up + {len(seeds) - warmup} timed solves")
@@ -174,8 +167,10 @@ def run_arm(meshes, degree, layers, rtol, seeds, warmup, precision="fp64", local
                 continue
             avg_ms = total_ms / launches
             if info["is_coarsest"]:
-                cb = coarse_bytes(info["n_free"])
-                per.append({"level": l, "kernel": "coarsest solve (packed FP64 inverse)", "n": info["n_free"],
+                cb = info["coarse_solve_bytes"]
+                kind = (f"coarsest solve (nested dissection, {info['coarse_nd_supernodes']} supernodes)"
+                        if info["coarse_nd_supernodes"] else "coarsest solve (packed FP64 inverse)")
+                per.append({"level": l, "kernel": kind, "n": info["n_free"],
                             "launches": launches, "avg_us": round(1e3 * avg_ms, 2), "bytes": cb,
                             "gbs": round(cb / (avg_ms * 1e-3) / 1e9, 1), "total_ms": round(total_ms, 3)})
                 continue
@@ -401,6 +396,9 @@ def main():
     ap.add_argument("--refine", action="store_true", help="one FP64 refinement step of every patch solve")
     ap.add_argument("--f64-patch-factor", action="store_true",
                     help="mixed arm: factor the patch systems in FP64 (default: FP32 matrix cores)")
+    ap.add_argument("--coarse-solver", type=int, default=0, choices=[0, 1, 2],
+                    help="coarsest solve: 0 = library's choice, 1 = dense inverse, 2 = nested dissection")
+    ap.add_argument("--coarse-leaf", type=int, default=1024, help="nested dissection: largest leaf")
     ap.add_argument("--layout", default="",
                     help="fix the level operators' layouts of the global-local arms: 'sigma,unroll,mask,rpl' per "
                          "level joined by ';' (an arm's 'layout' field of an earlier run), so that a profiled "
@@ -436,7 +434,8 @@ def main():
     seeds = [1000 + k for k in range(args.warmup + args.steps)]
     common = dict(layers=layers, rtol=rtol, policy=policy, smoother=args.smoother, problem=problem,
                   sigma=args.sigma, inherit=args.inherit, refine=args.refine,
-                  factor_f32=not args.f64_patch_factor)
+                  factor_f32=not args.f64_patch_factor, coarse_solver=args.coarse_solver,
+                  coarse_leaf=args.coarse_leaf)
     res = {}
     for prec in ("mixed", "fp64"):
         if prec in arms:

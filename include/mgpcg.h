@@ -173,6 +173,11 @@ typedef struct {
                                128, 256 or 384 = that class where every patch
                                fits it, -1 = always the three-launch path.
                                Needs patch_fused = 1 and patch_refine = 0     */
+  int32_t coarse_solver;    /* coarsest-level direct solve: 0 = nested
+                               dissection from 12288 unknowns, the dense
+                               explicit inverse below; 1 = dense inverse;
+                               2 = nested dissection                          */
+  int32_t coarse_nd_leaf;   /* largest leaf of the nested dissection (1024)    */
   int32_t sell_layout_levels; /* number of levels that sell_layout covers      */
   const int32_t *sell_layout; /* NULL, or host [4 * sell_layout_levels]: for
                                level l the values (sigma, unroll, mask, rpl)
@@ -236,6 +241,12 @@ typedef struct {
   int32_t patch_chunk;      /* tiles per row item of the level's packed
                                inverses (patches; the coarsest level: its
                                inverse)                                        */
+  int32_t coarse_nd_supernodes; /* coarsest level: supernodes of the nested
+                               dissection (0: dense inverse)                  */
+  double coarse_solve_bytes; /* coarsest level: FP64 matrix bytes one solve
+                               reads (dense: packed lower tiles; dissection:
+                               diagonal-block inverses and the tile rows of L
+                               below them, forward and backward)              */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -269,7 +280,7 @@ enum {
  * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
  * patch_fused 1, use_initial_guess 0, sell_colform 0, patch_factor_f32 1,
  * patch_refine 0, patch_inherit_levels 0, patch_chunk 0, patch_small_bound 0,
- * sell_layout_levels 0, sell_layout NULL. */
+ * coarse_solver 0, coarse_nd_leaf 1024, sell_layout_levels 0, sell_layout NULL. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

@@ -43,7 +43,7 @@ class MgOptions(C.Structure):
                 ("sell_rpl", C.c_int32), ("patch_fused", C.c_int32), ("use_initial_guess", C.c_int32),
                 ("sell_colform", C.c_int32), ("patch_factor_f32", C.c_int32), ("patch_refine", C.c_int32),
                 ("patch_inherit_levels", C.c_int32), ("patch_chunk", C.c_int32),
-                ("patch_small_bound", C.c_int32),
+                ("patch_small_bound", C.c_int32), ("coarse_solver", C.c_int32), ("coarse_nd_leaf", C.c_int32),
                 ("sell_layout_levels", C.c_int32),
                 ("sell_layout", C.POINTER(C.c_int32))]
 
@@ -68,7 +68,8 @@ class MgLevelInfo(C.Structure):
                 ("sell_slices_multiwindow", C.c_int64), ("sell_slices_32bit", C.c_int64),
                 ("sell_slices_16window", C.c_int64), ("patches_f32", C.c_int32),
                 ("patches_inherited", C.c_int32), ("patch_small_bound", C.c_int32),
-                ("patch_chunk", C.c_int32)]
+                ("patch_chunk", C.c_int32), ("coarse_nd_supernodes", C.c_int32),
+                ("coarse_solve_bytes", C.c_double)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -162,7 +163,8 @@ class Solver:
                  poisson_ratio: float = 0.33, sell_unroll: int = 0, sell_mask: int = -1, sell_rpl: int = 0,
                  patch_fused: bool = True, use_initial_guess: bool = False, sell_layout=None,
                  sell_colform: int = 0, patch_factor_f32: bool = True, patch_refine: bool = False,
-                 patch_inherit_levels: int = 0, patch_chunk: int = 0, patch_small_bound: int = 0):
+                 patch_inherit_levels: int = 0, patch_chunk: int = 0, patch_small_bound: int = 0,
+                 coarse_solver: int = 0, coarse_nd_leaf: int = 1024):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -197,6 +199,8 @@ class Solver:
         opt.patch_inherit_levels = patch_inherit_levels
         opt.patch_chunk = patch_chunk
         opt.patch_small_bound = patch_small_bound
+        opt.coarse_solver = coarse_solver
+        opt.coarse_nd_leaf = coarse_nd_leaf
         keep: list = []
         if sell_layout:  # [(sigma, unroll, mask, rpl) per level]
             lay = np.ascontiguousarray(np.asarray(sell_layout, dtype=np.int32).reshape(-1, 4))

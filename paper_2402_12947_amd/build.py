@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmgpcg.so")
 SOURCES = ["api.hip", "solve.hip", "setup_mesh.hip", "setup_assembly.hip", "setup_transfer.hip",
            "setup_galerkin.hip", "setup_patches.hip", "setup_dense.hip", "setup_patchfactor.hip",
-           "setup_eigen.hip", "solve_block.hip", "probe.hip"]
+           "setup_eigen.hip", "solve_block.hip", "probe.hip", "coarse_nd.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

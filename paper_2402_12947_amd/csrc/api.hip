@@ -135,6 +135,7 @@ static double time_on_stream(Ctx &c, F f) {
 static void tune_patches(Ctx &c, Level &L) {
   const bool mixed = c.opt.precision == MG_MIXED;
   if (L.coarsest) {
+    if (L.cnd.on) return;
     const int64_t n = L.nfree;
     const int fixed = c.opt.patch_chunk;
     if (fixed == 0 && n < 2048) return;
@@ -780,6 +781,8 @@ void mg_default_options(mg_options *o) {
   o->patch_inherit_levels = 0;
   o->patch_chunk = 0;
   o->patch_small_bound = 0;
+  o->coarse_solver = 0;
+  o->coarse_nd_leaf = 1024;
   o->sell_layout_levels = 0;
   o->sell_layout = nullptr;
   o->global_smoother = MG_SMOOTHER_CHEBYSHEV;
@@ -850,6 +853,9 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.patch_inherit_levels < 0) fail(MG_ERR_ARG, "patch_inherit_levels must be >= 0");
     if (o.patch_chunk != 0 && o.patch_chunk != 8 && o.patch_chunk != 16 && o.patch_chunk != 32)
       fail(MG_ERR_ARG, "patch_chunk must be 0, 8, 16 or 32");
+    if (o.coarse_solver < 0 || o.coarse_solver > 2) fail(MG_ERR_ARG, "coarse_solver must be 0, 1 or 2");
+    if (o.coarse_nd_leaf < 32 || o.coarse_nd_leaf > 16384)
+      fail(MG_ERR_ARG, "coarse_nd_leaf must lie in 32..16384");
     if (o.patch_small_bound != 0 && o.patch_small_bound != -1 && o.patch_small_bound != 128 &&
         o.patch_small_bound != 256 && o.patch_small_bound != 384)
       fail(MG_ERR_ARG, "patch_small_bound must be 0, -1, 128, 256 or 384");
@@ -1400,6 +1406,10 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
     o->patches_inherited = L.patch.n_inherited;
     o->patch_small_bound = L.patch.small_nb * PATCH_TILE;
     o->patch_chunk = L.coarsest ? L.cpk.chunk : L.patch.inv.chunk;
+    o->coarse_nd_supernodes = L.cnd.on ? L.cnd.nsup : 0;
+    if (L.coarsest)
+      o->coarse_solve_bytes = L.cnd.on ? (double)(L.cnd.dinv_bytes + L.cnd.b_bytes) * 2.0
+                                       : (double)L.cpk.packed * 8.0;
   }
   o->is_coarsest = L.coarsest ? 1 : 0;
   o->setup_ms = L.setup_ms;

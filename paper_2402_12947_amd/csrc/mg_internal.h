@@ -195,6 +195,28 @@ struct Patches {
   DBuf<int32_t> nbr_pos;
 };
 
+// The coarsest solve by nested dissection (coarse_nd.hip): supernodes
+// (leaves and separators, contiguous ranges of the dissection order) with the
+// inverses of their diagonal blocks of L and the nonzero 32-row tile rows of L
+// below them, all FP64.
+struct CoarseNd {
+  bool on = false;
+  int nsup = 0, height = 0, leaf = 0;
+  int64_t dinv_bytes = 0, b_bytes = 0;
+  DBuf<int32_t> pos;                      // [n] dissection order -> unknown
+  DBuf<int32_t> t_sup, t_loc;             // per global tile
+  DBuf<int32_t> s_a, s_n, s_t0;           // per supernode
+  DBuf<int64_t> s_doff;
+  DBuf<double> dinv;                      // diagonal-block inverses, lower tiles
+  DBuf<int32_t> q_sup, q_tgt;             // per stored tile row
+  DBuf<int64_t> q_off;
+  DBuf<double> bval;
+  DBuf<int32_t> s_qptr, s_q, g_qptr, g_q;
+  std::vector<int> lvl_tiles_first, lvl_items_first;  // by tree height
+  DBuf<int32_t> lvl_tiles, lvl_items;
+  DBuf<double> bp, y, t, x, contrib;      // solve work
+};
+
 struct Level {
   // mesh and DOF map
   int dim = 0, degree = 0, nloc = 0;
@@ -240,8 +262,9 @@ struct Level {
   // Chebyshev
   double lam = 0, lam_adj = 0, lo = 0, hi = 0;
   int lanczos_steps = 0, lanczos_steps_adj = 0;
-  // coarsest: dense inverse
+  // coarsest: dense inverse, or the nested-dissection factor
   bool coarsest = false;
+  CoarseNd cnd;
   DBuf<double> cinv;           // [nfree * nfree] (setup only)
   PackedInv cpk;               // the coarsest inverse, packed (one system)
   DBuf<int32_t> cptr;          // {0, nfree}
@@ -324,6 +347,9 @@ void build_patch_refine(Ctx &c, Level &L);
 void build_patch_neighbours(Ctx &c, Level &L, bool want32);
 void build_sgs(Ctx &c, Level &L, bool want32);
 void factor_coarsest(Ctx &c, Level &L);
+void factor_coarsest_nd(Ctx &c, Level &L, int leaf);
+template <class T>
+void coarse_apply_nd(hipStream_t s, const Level &L, const T *b, T *u, int vs);
 void estimate_eigenvalues(Ctx &c, Level &L);
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32, int rpl = 1);
 void ell_to_csr(Ctx &c, int64_t nrows, int64_t ncols, int width, const int32_t *col, const double *val,

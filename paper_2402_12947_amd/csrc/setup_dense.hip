@@ -96,6 +96,8 @@ __device__ void inverse_from_factor(const double *Lf, int n, double *X) {
 // patches above BATCH_MAX DOFs are factored one at a time by the blocked
 // multi-workgroup path of the coarsest level; above MAX_PATCH they are refused
 constexpr int BATCH_MAX = 2048;
+// smallest coarsest level solved by nested dissection when coarse_solver = 0
+constexpr int64_t COARSE_ND_MIN = 12288;
 constexpr int MAX_PATCH = 16384;
 
 __global__ void k_gather_patch_dense(const int64_t *rp, const int32_t *col, const double *val, const int32_t *B,
@@ -380,7 +382,8 @@ __global__ __launch_bounds__(256) void k_single_inverse(const int64_t *rp, const
 
 // In-place blocked Cholesky of the n x n SPD matrix M (row-major) and its
 // explicit inverse in X; *bad receives the first non-positive pivot row.
-static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, int *bad) {
+// M = L L^T in place (lower triangle of M; the strict upper part keeps A's)
+void dense_cholesky(hipStream_t s, double *M, int64_t n, int *bad) {
   int nb = (int)((n + TB - 1) / TB);
   for (int kb = 0; kb < nb; ++kb) {
     k_chol_diag<<<1, 256, 0, s>>>(M, n, kb, bad);
@@ -394,10 +397,14 @@ static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, in
       MG_LAUNCH_CHECK();
     }
   }
-  // inverses of the diagonal tiles of L, then W = L^-1 right-looking, X = W^T W
-  DBuf<double> Dinv, W;
+}
+
+// W = L^-1 (lower; L the lower triangle of M): inverses of the diagonal tiles,
+// then a right-looking block solve of L W = I
+void dense_lower_inverse(hipStream_t s, const double *M, int64_t n, double *W) {
+  int nb = (int)((n + TB - 1) / TB);
+  DBuf<double> Dinv;
   Dinv.alloc(n * n);
-  W.alloc(n * n);
   k_trtri_diag<<<nb, 64, 0, s>>>(M, Dinv, n);
   MG_LAUNCH_CHECK();
   k_identity<<<(unsigned)n, 256, 0, s>>>(W, n);
@@ -411,7 +418,16 @@ static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, in
       MG_LAUNCH_CHECK();
     }
   }
-  Dinv.release();
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+// X = A^-1 = W^T W with W = L^-1 (M is overwritten by the factor)
+static void dense_spd_inverse(hipStream_t s, double *M, int64_t n, double *X, int *bad) {
+  const int nb = (int)((n + TB - 1) / TB);
+  dense_cholesky(s, M, n, bad);
+  DBuf<double> W;
+  W.alloc(n * n);
+  dense_lower_inverse(s, M, n, W);
   int64_t tiles = (int64_t)nb * (nb + 1) / 2;
   k_lauum<<<(unsigned)tiles, 256, 0, s>>>(W, X, n, nb);
   MG_LAUNCH_CHECK();
@@ -435,6 +451,13 @@ void factor_coarsest(Ctx &c, Level &L) {
   int64_t n = L.nfree;
   if (n > 60000) fail(MG_ERR_LIMIT, "coarsest level has %lld unknowns (limit 60000 for the dense solver)",
                       (long long)n);
+  // nested dissection where the dense inverse's n^2 / 2 entries per solve
+  // outweigh the dissection's launches
+  const int mode = c.opt.coarse_solver;
+  if (mode == 2 || (mode == 0 && n >= COARSE_ND_MIN)) {
+    factor_coarsest_nd(c, L, c.opt.coarse_nd_leaf);
+    return;
+  }
   L.cinv.alloc(n * n);
   DBuf<int> bad;
   bad.alloc(1);

@@ -582,6 +582,10 @@ template void patch_correct_small<float>(hipStream_t, const Patches &, int, cons
 // coarsest level: u = A^-1 b with the packed FP64 inverse (FP64 arithmetic)
 template <class T>
 void coarse_apply(hipStream_t s, const Level &L, const T *b, T *u, int vs) {
+  if (L.cnd.on) {
+    coarse_apply_nd<T>(s, L, b, u, vs);
+    return;
+  }
   packed_apply<double, T, GATHER_SET>(s, L.cpk, L.cpk.v64.p, 0, L.cptr, nullptr, b, L.cpy.p, L.cpz.p, u, vs);
 }
 template void coarse_apply<double>(hipStream_t, const Level &, const double *, double *, int);

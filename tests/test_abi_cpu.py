@@ -101,3 +101,26 @@ def test_stream_probe_rejects_bad_arguments_on_host():
     assert lib().mg_stream_probe(0, 1 << 10, 1, ctypes.byref(g)) == MG_ERR_ARG
     assert lib().mg_stream_probe(0, 1 << 30, 0, ctypes.byref(g)) == MG_ERR_ARG
     assert lib().mg_stream_probe(0, 1 << 30, 1, None) == MG_ERR_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of mg_options and mg_level_info have the C layout
+    (sizes and the offsets of their last fields), compiled from the header."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2402_12947_amd.binding import MgLevelInfo, MgOptions, MgSolveStats
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mgpcg.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mg_options), sizeof(mg_level_info),'
+                   ' sizeof(mg_solve_stats), offsetof(mg_options, sell_layout),'
+                   ' offsetof(mg_level_info, coarse_solve_bytes), offsetof(mg_solve_stats, history));return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(MgOptions), ctypes.sizeof(MgLevelInfo), ctypes.sizeof(MgSolveStats),
+            MgOptions.sell_layout.offset, MgLevelInfo.coarse_solve_bytes.offset, MgSolveStats.history.offset]
+    assert got == want
