@@ -88,7 +88,10 @@ typedef struct {
                                or MG_PATCH_OVERLAP (coloured, sequential)     */
   double eig_tol;           /* Lanczos Ritz-residual tolerance (1e-8)          */
   int32_t eig_maxit;        /* Lanczos step limit (200)                        */
-  int32_t use_graph;        /* 1: replay the V-cycle from a captured hipGraph  */
+  int32_t use_graph;        /* 1: replay from captured hipGraphs: each CG
+                               iteration of the solvers (V-cycle and CG
+                               updates, one graph per block width) and the
+                               V-cycle of mg_vcycle / mg_vcycle_solve          */
   int32_t sell_sigma;       /* SELL row-sorting window: 0 = autotune, 1 = off,
                                else a multiple of 64                          */
   void *stream;             /* hipStream_t to run on; NULL = library-owned     */
@@ -372,15 +375,18 @@ mg_status mg_vcycle_solve(mg_ctx *c, const double *b, double *u, double rtol, in
 /* Many-instance solve (the serving pattern of independent problems): solves
  * the n_inst x nrhs systems A_i u_(i,r) = b_(i,r) of the contexts cs[i] together
  * with the same method and stopping rule as mg_pcg_solve.  b[i * nrhs + r] and
- * u[i * nrhs + r] are device FP64 vectors of instance i's n_free.  Every
- * instance runs on its own context stream from its own host thread, so the
- * instances' kernels overlap on the GPU, and solves its right-hand sides as
- * block solves (mg_pcg_solve_multi); contexts created with use_graph = 1
- * replay their V-cycles from captured hipGraphs.  The contexts must be
- * distinct.  st (may be NULL) receives n_inst * nrhs records; *wall_ms (may be
- * NULL) the wall time of the whole batch.  Returns the first error of the
- * lowest-numbered failing instance (its message in mg_last_error(cs[i])), else
- * MG_NOT_CONVERGED if any system did not converge, else MG_OK. */
+ * u[i * nrhs + r] are device FP64 vectors of instance i's n_free.  One host
+ * thread drives every instance: each solves its right-hand sides as the block
+ * runs of mg_pcg_solve_multi on its own context stream, and an instance whose
+ * last enqueued iteration has completed (polled, no common barrier) is given
+ * its next one at once, so the instances' kernels overlap on the GPU; with
+ * use_graph = 1 an iteration is one launch of the context's captured CG
+ * iteration graph.  The contexts must be distinct.  st (may be NULL) receives
+ * n_inst * nrhs records; *wall_ms (may be NULL) the wall time of the whole
+ * batch.  An instance that fails stops there while the others go on.
+ * Returns the first error of the lowest-numbered failing instance (its
+ * message in mg_last_error(cs[i])), else MG_NOT_CONVERGED if any system did
+ * not converge, else MG_OK. */
 mg_status mg_pcg_solve_batch(mg_ctx *const *cs, int32_t n_inst, int32_t nrhs, const double *const *b,
                              double *const *u, double rtol, int32_t maxit, mg_solve_stats *st,
                              double *wall_ms);

@@ -11,6 +11,7 @@
 #include <thread>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 
@@ -31,8 +32,8 @@ Ctx::~Ctx() {
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
   for (int k = 0; k < 5; ++k) {
-    if (kgraph_exec[k]) (void)hipGraphExecDestroy(kgraph_exec[k]);
-    if (kgraph[k]) (void)hipGraphDestroy(kgraph[k]);
+    if (cg_exec[k]) (void)hipGraphExecDestroy(cg_exec[k]);
+    if (cg_graph[k]) (void)hipGraphDestroy(cg_graph[k]);
   }
   for (auto &e : events) {
     (void)hipEventDestroy(e.first);
@@ -542,154 +543,289 @@ static void precondition_block_eager(Ctx &c, int K) {
   }
 }
 
-static void precondition_block(Ctx &c, int K) {
-  if (!c.opt.use_graph) {
-    precondition_block_eager(c, K);
-    return;
-  }
-  if (!c.kgraph_exec[K]) {
-    MG_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
-    try {
-      precondition_block_eager(c, K);
-    } catch (...) {
-      hipGraph_t g;
-      (void)hipStreamEndCapture(c.stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    MG_HIP(hipStreamEndCapture(c.stream, &c.kgraph[K]));
-    MG_HIP(hipGraphInstantiate(&c.kgraph_exec[K], c.kgraph[K], nullptr, nullptr, 0));
-  }
-  MG_HIP(hipGraphLaunch(c.kgraph_exec[K], c.stream));
-}
-
 static void dot_block_to(Ctx &c, int K, const double *x, const double *y, int64_t n, double *out) {
   const int nb = dot_blocks(n);
   dot_partials_block(c.stream, K, x, y, n, c.kpartial, nb);
   finish_sum_block(c.stream, K, c.kpartial, nb, out);
 }
 
-// CG on K columns in lockstep (K in {2, 4}; ncols <= K real columns, the rest
-// zero).  Each column is the single-vector CG of mg_pcg_solve with its own
-// scalars; a converged column is frozen (alpha = 0) while the others go on.
-// Returns whether every real column converged.
-static bool pcg_block(Ctx &c, int K, int ncols, const double *const *b, double *const *u, double rtol, int maxit,
-                      mg_solve_stats *st) {
+// ---------------------------------------------------------------------------
+// Preconditioned CG (Sec. 6.2) as a host state machine over device work.
+// Every iteration is the same device sequence: z = B r (one V-cycle),
+// rho' = r.z, beta = rho' / rho, p = z + beta p, q = A p with p.q,
+// alpha = rho' / p.q, x += alpha p, r -= alpha q with r.r, and the scalars
+// written to pinned host memory.  The first iteration is that sequence from
+// p = 0 and rho = 1, which gives p = z.  The host reads r.r once the
+// iteration has run and decides; with use_graph the sequence is captured
+// once per block width and replayed, so that an iteration costs one graph
+// launch and one wait.  A run is one vector (K = 1, the buffers of
+// mg_pcg_solve) or a block of K = 2 or 4 interleaved columns (padding
+// columns zero); a column of a block that has converged is frozen by its
+// device-side active flag while the others go on.
+// Device scalars (slot j K + q of column q): 0 rho = r.z, 1 p.q, 2 alpha,
+// 3 r.r, 4 rho', 5 beta, 6 breakdown flag, 7 b.b (later the true residual's
+// square), 8 active flag (blocks only).
+// ---------------------------------------------------------------------------
+struct CgBufs {
+  double *x, *r, *z, *p, *q, *b;
+};
+static CgBufs cg_bufs(Ctx &c, int K) {
+  if (K == 1) return {c.xpos, c.r, c.z, c.p, c.q, c.bpos};
+  return {c.kx, c.kr, c.kz, c.kp, c.kq, c.kb};
+}
+
+static void cg_iteration_eager(Ctx &c, int K) {
   Level &L0 = c.lv[0];
   const int64_t n = L0.nfree;
   hipStream_t s = c.stream;
-  ensure_block_work(c);
-  const double *bc[MG_BLOCK_MAX] = {};
-  double *uc[MG_BLOCK_MAX] = {};
-  for (int q = 0; q < ncols; ++q) {
-    bc[q] = b[q];
-    uc[q] = u[q];
-  }
-  hipEvent_t e0, e1;
-  MG_HIP(hipEventCreate(&e0));
-  MG_HIP(hipEventCreate(&e1));
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-  } guard{e0, e1};
-  MG_HIP(hipEventRecord(e0, s));
   double *scal = c.scal.p;
-  double *h = c.h_scal;
-  const bool warm = c.opt.use_initial_guess != 0;
-  fill<double>(s, scal, 8 * K, 0.0);
-  gather_block(s, K, bc, L0.perm, c.kb, n);
-  if (warm) {  // x_0 = u (padding columns zero), r_0 = b - A x_0
-    gather_block(s, K, uc, L0.perm, c.kx, n);
-    sell_spmv_block<double>(s, L0.S, K, c.kx, c.kr, SPMV_RESID, c.kb);
-    dot_block_to(c, K, c.kr, c.kr, n, scal + 3 * K);
+  const CgBufs v = cg_bufs(c, K);
+  const int nb = dot_blocks(n), sb = spmv_dot_blocks(L0.S);
+  if (K == 1) {
+    precondition_eager(c, v.r, v.z);
+    dot_to(c, v.r, v.z, n, scal + 4);
+    cg_beta(s, scal);
+    cg_update_p(s, v.p, v.z, scal, n);
+    spmv_dot(s, L0.S, v.p, v.q, c.partial);
+    finish_sum(s, c.partial, sb, scal + 1);
+    cg_alpha(s, scal);
+    cg_update_xr(s, v.x, v.r, v.p, v.q, scal, n, c.partial, nb);
+    finish_sum(s, c.partial, nb, scal + 3);
+    scal_to_host(s, scal, c.h_scal_dev, 8);
   } else {
-    fill<double>(s, c.kx.p, n * K, 0.0);
-    copy64(s, c.kb, c.kr, n * K);
+    precondition_block_eager(c, K);
+    dot_block_to(c, K, v.r, v.z, n, scal + 4 * K);
+    cg_beta_block(s, K, scal);
+    cg_update_p_block(s, K, v.p, v.z, scal, n);
+    spmv_dot_block(s, L0.S, K, v.p, v.q, c.kpartial);
+    finish_sum_block(s, K, c.kpartial, sb, scal + K);
+    cg_alpha_block(s, K, scal);
+    cg_update_xr_block(s, K, v.x, v.r, v.p, v.q, scal, n, c.kpartial, nb);
+    finish_sum_block(s, K, c.kpartial, nb, scal + 3 * K);
+    scal_to_host(s, scal, c.h_scal_dev, 9 * K);
   }
-  dot_block_to(c, K, c.kb, c.kb, n, scal + 7 * K);
-  MG_HIP(hipMemcpyAsync(h, scal, 8 * K * sizeof(double), hipMemcpyDeviceToHost, s));
-  MG_HIP(hipStreamSynchronize(s));
-  double bnorm[MG_BLOCK_MAX], rel[MG_BLOCK_MAX];
+}
+
+static void cg_iteration(Ctx &c, int K) {
+  if (!c.opt.use_graph || c.timing) {
+    cg_iteration_eager(c, K);
+    return;
+  }
+  if (!c.cg_exec[K]) {
+    MG_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    try {
+      cg_iteration_eager(c, K);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(c.stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    MG_HIP(hipStreamEndCapture(c.stream, &c.cg_graph[K]));
+    MG_HIP(hipGraphInstantiate(&c.cg_exec[K], c.cg_graph[K], nullptr, nullptr, 0));
+  }
+  MG_HIP(hipGraphLaunch(c.cg_exec[K], c.stream));
+}
+
+struct CgRun {
+  Ctx *c = nullptr;
+  int K = 1, ncols = 1;  // block width and real columns (ncols <= K)
+  const double *b[MG_BLOCK_MAX] = {};
+  double *u[MG_BLOCK_MAX] = {};
+  double rtol = 0;
+  int maxit = 0;
+  mg_solve_stats *st = nullptr;  // ncols records or NULL
+  enum Phase { START, ITERATE, END, DONE } phase = START;
+  bool warm = false;
+  double bnorm[MG_BLOCK_MAX] = {}, rel[MG_BLOCK_MAX] = {};
   int iters[MG_BLOCK_MAX] = {};
   bool conv[MG_BLOCK_MAX] = {};
   std::vector<double> hist[MG_BLOCK_MAX];
-  unsigned mask = 0;
-  for (int q = 0; q < K; ++q) {
-    bnorm[q] = std::sqrt(h[7 * K + q]);
-    rel[q] = bnorm[q] > 0 ? (warm ? std::sqrt(h[3 * K + q]) / bnorm[q] : 1.0) : 0.0;
-    hist[q].push_back(rel[q]);
-    conv[q] = bnorm[q] == 0.0 || rel[q] <= rtol;
-    if (!conv[q]) mask |= 1u << q;
-  }
+  unsigned mask = 0;  // columns still iterating
   int it = 0, broken = -1;
-  if (mask) {
-    precondition_block(c, K);
-    copy64(s, c.kz, c.kp, n * K);
-    dot_block_to(c, K, c.kr, c.kz, n, scal + 0);
-    const int nb = dot_blocks(n);
-    const int sb = spmv_dot_blocks(L0.S);
-    while (it < maxit) {
-      spmv_dot_block(s, L0.S, K, c.kp, c.kq, c.kpartial);
-      finish_sum_block(s, K, c.kpartial, sb, scal + K);
-      cg_alpha_block(s, K, mask, scal);
-      cg_update_xr_block(s, K, c.kx, c.kr, c.kp, c.kq, scal, n, c.kpartial, nb);
-      finish_sum_block(s, K, c.kpartial, nb, scal + 3 * K);
-      MG_HIP(hipMemcpyAsync(h, scal, 8 * K * sizeof(double), hipMemcpyDeviceToHost, s));
-      MG_HIP(hipStreamSynchronize(s));
-      ++it;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CgRun() = default;
+  CgRun(const CgRun &) = delete;
+  CgRun &operator=(const CgRun &) = delete;
+  ~CgRun() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+// enqueues the start: b (and x_0) in solve order, r_0, b.b (and r_0.r_0)
+static void cg_begin(CgRun &R) {
+  Ctx &c = *R.c;
+  const int K = R.K;
+  if (K > 1) ensure_block_work(c);
+  Level &L0 = c.lv[0];
+  const int64_t n = L0.nfree;
+  hipStream_t s = c.stream;
+  double *scal = c.scal.p;
+  const CgBufs v = cg_bufs(c, K);
+  R.warm = c.opt.use_initial_guess != 0;
+  MG_HIP(hipEventCreate(&R.e0));
+  MG_HIP(hipEventCreate(&R.e1));
+  MG_HIP(hipEventRecord(R.e0, s));
+  fill<double>(s, scal, 9 * K, 0.0);
+  if (K == 1) {
+    gather_perm<double, double>(s, R.b[0], L0.perm, v.b, n);
+    if (R.warm) gather_perm<double, double>(s, R.u[0], L0.perm, v.x, n);
+  } else {
+    gather_block(s, K, R.b, L0.perm, v.b, n);
+    if (R.warm) gather_block(s, K, R.u, L0.perm, v.x, n);
+  }
+  if (R.warm) {  // r_0 = b - A x_0
+    if (K == 1) {
+      sell_spmv<double>(s, L0.S, v.x, v.r, SPMV_RESID, v.b);
+      dot_to(c, v.r, v.r, n, scal + 3);
+    } else {
+      sell_spmv_block<double>(s, L0.S, K, v.x, v.r, SPMV_RESID, v.b);
+      dot_block_to(c, K, v.r, v.r, n, scal + 3 * K);
+    }
+  } else {
+    fill<double>(s, v.x, n * K, 0.0);
+    copy64(s, v.b, v.r, n * K);
+  }
+  if (K == 1) dot_to(c, v.b, v.b, n, scal + 7);
+  else dot_block_to(c, K, v.b, v.b, n, scal + 7 * K);
+  scal_to_host(s, scal, c.h_scal_dev, 8 * K);
+  R.phase = CgRun::START;
+}
+
+// enqueues the end: x back to the caller's order, the end event, the true
+// residual b - A x in FP64
+static void cg_end(CgRun &R) {
+  Ctx &c = *R.c;
+  const int K = R.K;
+  Level &L0 = c.lv[0];
+  const int64_t n = L0.nfree;
+  hipStream_t s = c.stream;
+  double *scal = c.scal.p;
+  const CgBufs v = cg_bufs(c, K);
+  if (K == 1) {
+    if (R.bnorm[0] == 0.0) fill<double>(s, v.x, n, 0.0);  // b = 0: u = 0 whatever the start
+    scatter_perm<double, double>(s, v.x, L0.perm, R.u[0], n);
+  } else {
+    scatter_block(s, K, v.x, L0.perm, R.u, n);
+    for (int q = 0; q < R.ncols; ++q)
+      if (R.bnorm[q] == 0.0 && R.warm) fill<double>(s, R.u[q], n, 0.0);
+  }
+  MG_HIP(hipEventRecord(R.e1, s));
+  if (K == 1) {
+    sell_spmv<double>(s, L0.S, v.x, v.q, SPMV_RESID, v.b);
+    dot_to(c, v.q, v.q, n, scal + 7);
+  } else {
+    sell_spmv_block<double>(s, L0.S, K, v.x, v.q, SPMV_RESID, v.b);
+    dot_block_to(c, K, v.q, v.q, n, scal + 7 * K);
+  }
+  scal_to_host(s, scal, c.h_scal_dev, 8 * K);
+  R.phase = CgRun::END;
+}
+
+// launches the next iteration, refreshing the device-side active flags of a
+// block when the host's set of iterating columns has changed
+static void cg_next(CgRun &R, bool mask_changed) {
+  if (R.K > 1 && mask_changed) cg_active_block(R.c->stream, R.K, R.mask, R.c->scal.p);
+  cg_iteration(*R.c, R.K);
+  R.phase = CgRun::ITERATE;
+}
+
+// the host side of a run once its enqueued work has completed (the scalars
+// are in pinned memory): reads them, decides, and enqueues what comes next.
+// Returns false when the run is over (its statistics written).
+static bool cg_advance(CgRun &R) {
+  Ctx &c = *R.c;
+  const int K = R.K;
+  const double *h = c.h_scal;
+  switch (R.phase) {
+    case CgRun::START: {
       for (int q = 0; q < K; ++q) {
-        if (!((mask >> q) & 1u)) continue;
+        R.bnorm[q] = std::sqrt(h[7 * K + q]);
+        R.rel[q] = R.bnorm[q] > 0 ? (R.warm ? std::sqrt(h[3 * K + q]) / R.bnorm[q] : 1.0) : 0.0;
+        R.hist[q].push_back(R.rel[q]);
+        R.conv[q] = R.bnorm[q] == 0.0 || R.rel[q] <= R.rtol;
+        if (!R.conv[q]) R.mask |= 1u << q;
+      }
+      if (!R.mask || R.maxit <= 0) {
+        cg_end(R);
+        return true;
+      }
+      // p = 0 and rho = 1: the first iteration's beta p vanishes, p = z
+      const CgBufs v = cg_bufs(c, K);
+      fill<double>(c.stream, v.p, c.lv[0].nfree * K, 0.0);
+      fill<double>(c.stream, c.scal.p, K, 1.0);
+      cg_next(R, true);
+      return true;
+    }
+    case CgRun::ITERATE: {
+      ++R.it;
+      const unsigned before = R.mask;
+      for (int q = 0; q < K; ++q) {
+        if (!((R.mask >> q) & 1u)) continue;
         const double rr = h[3 * K + q];
         if (h[6 * K + q] != 0.0 || !std::isfinite(rr)) {
-          broken = q;
+          R.broken = q;
           break;
         }
-        rel[q] = std::sqrt(rr) / bnorm[q];
-        hist[q].push_back(rel[q]);
-        iters[q] = it;
-        if (rel[q] <= rtol) {
-          conv[q] = true;
-          mask &= ~(1u << q);
+        R.rel[q] = std::sqrt(rr) / R.bnorm[q];
+        R.hist[q].push_back(R.rel[q]);
+        R.iters[q] = R.it;
+        if (R.rel[q] <= R.rtol) {
+          R.conv[q] = true;
+          R.mask &= ~(1u << q);
         }
       }
-      if (broken >= 0 || !mask) break;
-      precondition_block(c, K);
-      dot_block_to(c, K, c.kr, c.kz, n, scal + 4 * K);
-      cg_beta_block(s, K, mask, scal);
-      cg_update_p_block(s, K, c.kp, c.kz, scal, n);
+      if (R.broken >= 0 || !R.mask || R.it >= R.maxit) cg_end(R);
+      else cg_next(R, R.mask != before);
+      return true;
     }
-  }
-  scatter_block(s, K, c.kx, L0.perm, uc, n);
-  for (int q = 0; q < ncols; ++q)  // b = 0: u = 0 whatever the start
-    if (bnorm[q] == 0.0 && warm) fill<double>(s, uc[q], n, 0.0);
-  MG_HIP(hipEventRecord(e1, s));
-  MG_HIP(hipEventSynchronize(e1));
-  float tms = 0;
-  MG_HIP(hipEventElapsedTime(&tms, e0, e1));
-  // true residuals in FP64
-  sell_spmv_block<double>(s, L0.S, K, c.kx, c.kq, SPMV_RESID, c.kb);
-  dot_block_to(c, K, c.kq, c.kq, n, scal + 7 * K);
-  MG_HIP(hipMemcpyAsync(h, scal + 7 * K, K * sizeof(double), hipMemcpyDeviceToHost, s));
-  MG_HIP(hipStreamSynchronize(s));
-  if (st) {
-    for (int q = 0; q < ncols; ++q) {
-      mg_solve_stats &o = st[q];
-      std::memset(&o, 0, sizeof(o));
-      o.iterations = iters[q];
-      o.converged = conv[q] ? 1 : 0;
-      o.rel_residual = rel[q];
-      o.true_rel_residual = bnorm[q] > 0 ? std::sqrt(h[q]) / bnorm[q] : 0.0;
-      o.solve_ms = tms;
-      o.n_history = (int32_t)std::min<size_t>(hist[q].size(), MG_MAX_HISTORY);
-      for (int k = 0; k < o.n_history; ++k) o.history[k] = hist[q][k];
+    case CgRun::END: {
+      float tms = 0;
+      MG_HIP(hipEventElapsedTime(&tms, R.e0, R.e1));
+      if (R.st) {
+        for (int q = 0; q < R.ncols; ++q) {
+          mg_solve_stats &o = R.st[q];
+          std::memset(&o, 0, sizeof(o));
+          o.iterations = R.iters[q];
+          o.converged = R.conv[q] ? 1 : 0;
+          o.rel_residual = R.rel[q];
+          o.true_rel_residual = R.bnorm[q] > 0 ? std::sqrt(h[7 * K + q]) / R.bnorm[q] : 0.0;
+          o.solve_ms = tms;
+          o.n_history = (int32_t)std::min<size_t>(R.hist[q].size(), MG_MAX_HISTORY);
+          for (int k = 0; k < o.n_history; ++k) o.history[k] = R.hist[q][k];
+        }
+      }
+      R.phase = CgRun::DONE;
+      if (R.broken >= 0) {
+        if (K == 1) fail(MG_ERR_BREAKDOWN, "CG breakdown at iteration %d (p.Ap <= 0 or a non-finite value)", R.it);
+        fail(MG_ERR_BREAKDOWN, "CG breakdown in column %d at iteration %d (p.Ap <= 0 or a non-finite value)",
+             R.broken, R.it);
+      }
+      return false;
     }
+    default:
+      return false;
   }
-  if (broken >= 0)
-    fail(MG_ERR_BREAKDOWN, "CG breakdown in column %d at iteration %d (p.Ap <= 0 or a non-finite value)", broken, it);
-  bool all = true;
-  for (int q = 0; q < ncols; ++q) all &= conv[q];
-  return all;
 }
+
+// The right-hand sides of one context cut into runs: groups of 4 columns; a
+// remainder of 3 is padded with a zero column, 2 runs as a block of two and
+// 1 as a single vector.
+struct CgPlan {
+  int first, K, ncols;
+};
+static std::vector<CgPlan> cg_plan(int nrhs) {
+  std::vector<CgPlan> out;
+  for (int i = 0; i < nrhs;) {
+    const int left = nrhs - i;
+    const int K = left == 1 ? 1 : left == 2 ? 2 : 4, ncols = std::min(left, K);
+    out.push_back({i, K, ncols});
+    i += ncols;
+  }
+  return out;
+}
+
 
 }  // namespace mg
 
@@ -750,6 +886,103 @@ static void copy_out(hipStream_t s, const T *d, size_t n, void *out) {
   if (!d) fail(MG_ERR_ARG, "array not available on this level");
   MG_HIP(hipMemcpyAsync(out, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
+}
+
+// The vectors of one context's nrhs systems: none NULL, no solution aliasing
+// another vector.
+static void check_vectors(int nrhs, const double *const *b, double *const *u) {
+  for (int i = 0; i < nrhs; ++i) {
+    if (!b[i] || !u[i]) fail(MG_ERR_ARG, "NULL vector of right-hand side %d", i);
+    for (int j = 0; j < nrhs; ++j)
+      if (u[i] == b[j] || (j < i && u[i] == u[j])) fail(MG_ERR_ARG, "solution %d aliases another vector", i);
+  }
+}
+
+// Solves the nrhs systems of each of n_inst distinct contexts (b, u and st
+// indexed i * nrhs + r) from one host thread.  Each context works through
+// its runs (cg_plan) one after another; a context whose enqueued work has
+// completed is advanced at once (polled with hipStreamQuery when there are
+// several), so that the contexts' iterations overlap on the GPU with no
+// common barrier.  status[i]: MG_OK, MG_NOT_CONVERGED, or context i's first
+// error (its message in the context).
+static void cg_drive(mg_ctx *const *cs, int n_inst, int nrhs, const double *const *b, double *const *u,
+                     double rtol, int maxit, mg_solve_stats *st, std::vector<mg_status> &status) {
+  const std::vector<CgPlan> plan = cg_plan(nrhs);
+  struct Inst {
+    size_t next = 0;  // next run of the plan
+    std::unique_ptr<CgRun> run;
+    bool busy = false;
+  };
+  std::vector<Inst> in(n_inst);
+  status.assign(n_inst, MG_OK);
+  auto start_next = [&](int i) {
+    Inst &I = in[i];
+    I.run.reset();
+    I.busy = false;
+    if (I.next >= plan.size()) return;
+    const CgPlan &g = plan[I.next++];
+    I.run = std::make_unique<CgRun>();
+    CgRun &R = *I.run;
+    R.c = &cs[i]->impl;
+    R.K = g.K;
+    R.ncols = g.ncols;
+    R.rtol = rtol;
+    R.maxit = maxit;
+    const int64_t k = (int64_t)i * nrhs + g.first;
+    for (int q = 0; q < g.ncols; ++q) {
+      R.b[q] = b[k + q];
+      R.u[q] = u[k + q];
+    }
+    R.st = st ? st + k : nullptr;
+    I.busy = true;
+    cg_begin(R);
+  };
+  // runs f for context i; an error ends the context's work
+  auto guarded = [&](int i, const auto &f) {
+    try {
+      f();
+      return;
+    } catch (const Error &e) {
+      status[i] = e.code;
+      cs[i]->impl.err = e.msg;
+    } catch (const std::exception &e) {
+      status[i] = MG_ERR_HIP;
+      cs[i]->impl.err = e.what();
+    }
+    in[i].busy = false;
+    in[i].run.reset();
+  };
+  for (int i = 0; i < n_inst; ++i)
+    guarded(i, [&] {
+      check_vectors(nrhs, b + (int64_t)i * nrhs, u + (int64_t)i * nrhs);
+      start_next(i);
+    });
+  for (;;) {
+    bool busy = false, progressed = false;
+    for (int i = 0; i < n_inst; ++i) {
+      Inst &I = in[i];
+      if (!I.busy) continue;
+      busy = true;
+      hipStream_t s = I.run->c->stream;
+      hipError_t q = hipSuccess;
+      if (n_inst == 1) q = hipStreamSynchronize(s);
+      else if ((q = hipStreamQuery(s)) == hipErrorNotReady) continue;
+      progressed = true;
+      guarded(i, [&] {
+        if (q != hipSuccess) fail(MG_ERR_HIP, "waiting for the stream: %s", hipGetErrorString(q));
+        CgRun &R = *I.run;
+        if (cg_advance(R)) return;
+        for (int c = 0; c < R.ncols; ++c)
+          if (!R.conv[c]) status[i] = MG_NOT_CONVERGED;
+        start_next(i);
+      });
+    }
+    if (!busy) break;
+    if (!progressed) std::this_thread::yield();
+  }
+  // a context that failed may still have work in flight
+  for (int i = 0; i < n_inst; ++i)
+    if (status[i] < 0) (void)hipStreamSynchronize(cs[i]->impl.stream);
 }
 
 
@@ -985,8 +1218,9 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     c.xpos.alloc(n0);
     int64_t pb = std::max<int64_t>(1024, spmv_dot_blocks(c.lv[0].S));
     c.partial.alloc(pb);
-    c.scal.alloc(8 * MG_BLOCK_MAX);
-    MG_HIP(hipHostMalloc((void **)&c.h_scal, 8 * MG_BLOCK_MAX * sizeof(double), hipHostMallocDefault));
+    c.scal.alloc(16 * MG_BLOCK_MAX);
+    MG_HIP(hipHostMalloc((void **)&c.h_scal, 16 * MG_BLOCK_MAX * sizeof(double), hipHostMallocDefault));
+    MG_HIP(hipHostGetDevicePointer((void **)&c.h_scal_dev, c.h_scal, 0));
     // column form of each slice: cbase[2 s] >= 0 two windows, -1 32-bit,
     // below -1 eight or sixteen windows
     for (const Level &L : c.lv) {
@@ -1102,101 +1336,12 @@ mg_status mg_pcg_solve(mg_ctx *h, const double *b, double *u, double rtol, int32
   Ctx *cp = h ? &h->impl : nullptr;
   MG_API_BEGIN
   if (!h || !b || !u) fail(MG_ERR_ARG, "NULL argument");
-  Ctx &c = h->impl;
   if (b == u) fail(MG_ERR_ARG, "b must not alias u");
   if (maxit < 0 || !(rtol >= 0)) fail(MG_ERR_ARG, "bad rtol or maxit");
-  Level &L0 = c.lv[0];
-  const int64_t n = L0.nfree;
-  hipStream_t s = c.stream;
   if (st) std::memset(st, 0, sizeof(*st));
-  hipEvent_t e0, e1;
-  MG_HIP(hipEventCreate(&e0));
-  MG_HIP(hipEventCreate(&e1));
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-  } guard{e0, e1};
-  MG_HIP(hipEventRecord(e0, s));
-  double *scal = c.scal.p;
-  double *x = c.xpos.p;
-  const bool warm = c.opt.use_initial_guess != 0;
-  fill<double>(s, scal, 8, 0.0);
-  gather_perm<double, double>(s, b, L0.perm, c.bpos, n);
-  if (warm) {  // x_0 = u, r_0 = b - A x_0
-    gather_perm<double, double>(s, u, L0.perm, x, n);
-    sell_spmv<double>(s, L0.S, x, c.r, SPMV_RESID, c.bpos);
-  } else {
-    fill<double>(s, x, n, 0.0);
-    copy64(s, c.bpos, c.r, n);
-  }
-  dot_to(c, c.bpos, c.bpos, n, scal + 7);
-  double bb = read_scalar(c, scal + 7);
-  double bnorm = std::sqrt(bb);
-  double rel = bnorm > 0 ? 1.0 : 0.0;
-  if (warm && bnorm > 0) {
-    dot_to(c, c.r, c.r, n, scal + 3);
-    rel = std::sqrt(read_scalar(c, scal + 3)) / bnorm;
-  }
-  if (bnorm == 0.0) fill<double>(s, x, n, 0.0);  // b = 0: u = 0 whatever the start
-  std::vector<double> hist{rel};
-  int it = 0;
-  bool converged = bnorm == 0.0 || rel <= rtol, breakdown = false;
-  if (!converged) {
-    precondition(c);
-    copy64(s, c.z, c.p, n);
-    dot_to(c, c.r, c.z, n, scal + 0);
-    const int nb = dot_blocks(n);
-    while (it < maxit) {
-      // q = A p with p.q
-      int sb = spmv_dot_blocks(L0.S);
-      spmv_dot(s, L0.S, c.p, c.q, c.partial);
-      finish_sum(s, c.partial, sb, scal + 1);
-      cg_alpha(s, scal);
-      cg_update_xr(s, x, c.r, c.p, c.q, scal, n, c.partial, nb);
-      finish_sum(s, c.partial, nb, scal + 3);
-      MG_HIP(hipMemcpyAsync(c.h_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-      MG_HIP(hipStreamSynchronize(s));
-      ++it;
-      double rr = c.h_scal[3];
-      if (c.h_scal[6] != 0.0 || !std::isfinite(rr)) {
-        breakdown = true;
-        break;
-      }
-      rel = std::sqrt(rr) / bnorm;
-      hist.push_back(rel);
-      if (rel <= rtol) {
-        converged = true;
-        break;
-      }
-      precondition(c);
-      dot_to(c, c.r, c.z, n, scal + 4);
-      cg_beta(s, scal);
-      cg_update_p(s, c.p, c.z, scal, n);
-    }
-  }
-  scatter_perm<double, double>(s, x, L0.perm, u, n);
-  MG_HIP(hipEventRecord(e1, s));
-  MG_HIP(hipEventSynchronize(e1));
-  float tms = 0;
-  MG_HIP(hipEventElapsedTime(&tms, e0, e1));
-  // true residual in FP64
-  double true_rel = 0;
-  if (bnorm > 0) {
-    sell_spmv<double>(s, L0.S, x, c.ax, SPMV_RESID, c.bpos);
-    dot_to(c, c.ax, c.ax, n, scal + 7);
-    true_rel = std::sqrt(read_scalar(c, scal + 7)) / bnorm;
-  }
-  if (st) {
-    st->iterations = it;
-    st->converged = converged ? 1 : 0;
-    st->rel_residual = rel;
-    st->true_rel_residual = true_rel;
-    st->solve_ms = tms;
-    st->n_history = (int32_t)std::min<size_t>(hist.size(), MG_MAX_HISTORY);
-    for (int k = 0; k < st->n_history; ++k) st->history[k] = hist[k];
-  }
-  if (breakdown) fail(MG_ERR_BREAKDOWN, "CG breakdown at iteration %d (p.Ap <= 0 or a non-finite value)", it);
-  return converged ? MG_OK : MG_NOT_CONVERGED;
+  std::vector<mg_status> status;
+  cg_drive(&h, 1, 1, &b, &u, rtol, maxit, st, status);
+  return status[0];
   MG_API_END(cp)
 }
 
@@ -1205,30 +1350,12 @@ mg_status mg_pcg_solve_multi(mg_ctx *h, int32_t nrhs, const double *const *b, do
   Ctx *cp = h ? &h->impl : nullptr;
   MG_API_BEGIN
   if (!h || nrhs < 0 || (nrhs > 0 && (!b || !u))) fail(MG_ERR_ARG, "NULL argument or negative count");
-  Ctx &c = h->impl;
   if (maxit < 0 || !(rtol >= 0)) fail(MG_ERR_ARG, "bad rtol or maxit");
-  for (int i = 0; i < nrhs; ++i) {
-    if (!b[i] || !u[i]) fail(MG_ERR_ARG, "NULL vector of right-hand side %d", i);
-    for (int j = 0; j < nrhs; ++j)
-      if (u[i] == b[j] || (j < i && u[i] == u[j])) fail(MG_ERR_ARG, "solution %d aliases another vector", i);
-  }
-  // groups of 4 columns; a remainder of 3 is padded with a zero column, 2
-  // runs as a block of two and 1 as a single-vector solve
-  bool not_conv = false;
-  for (int i = 0; i < nrhs;) {
-    const int left = nrhs - i;
-    if (left == 1) {
-      mg_status code = mg_pcg_solve(h, b[i], u[i], rtol, maxit, st ? st + i : nullptr);
-      if (code < 0) return code;
-      not_conv |= code == MG_NOT_CONVERGED;
-      i += 1;
-      continue;
-    }
-    const int K = left == 2 ? 2 : 4, ncols = std::min(left, K);
-    not_conv |= !pcg_block(c, K, ncols, b + i, u + i, rtol, maxit, st ? st + i : nullptr);
-    i += ncols;
-  }
-  return not_conv ? MG_NOT_CONVERGED : MG_OK;
+  if (st && nrhs > 0) std::memset(st, 0, sizeof(*st) * nrhs);
+  if (nrhs == 0) return MG_OK;
+  std::vector<mg_status> status;
+  cg_drive(&h, 1, nrhs, b, u, rtol, maxit, st, status);
+  return status[0];
   MG_API_END(cp)
 }
 
@@ -1312,8 +1439,12 @@ mg_status mg_vcycle_solve(mg_ctx *h, const double *b, double *u, double rtol, in
 
 mg_status mg_pcg_solve_batch(mg_ctx *const *cs, int32_t n_inst, int32_t nrhs, const double *const *b,
                              double *const *u, double rtol, int32_t maxit, mg_solve_stats *st, double *wall_ms) {
-  if (!cs || !b || !u || n_inst < 0 || nrhs < 0) {
+  if (!cs || n_inst < 0 || nrhs < 0 || (n_inst > 0 && nrhs > 0 && (!b || !u))) {
     g_error = "mg_pcg_solve_batch: NULL argument or negative count";
+    return MG_ERR_ARG;
+  }
+  if (maxit < 0 || !(rtol >= 0)) {
+    g_error = "mg_pcg_solve_batch: bad rtol or maxit";
     return MG_ERR_ARG;
   }
   for (int i = 0; i < n_inst; ++i) {
@@ -1327,18 +1458,10 @@ mg_status mg_pcg_solve_batch(mg_ctx *const *cs, int32_t n_inst, int32_t nrhs, co
         return MG_ERR_ARG;
       }
   }
-  std::vector<mg_status> status(n_inst, MG_OK);
+  if (st && n_inst > 0 && nrhs > 0) std::memset(st, 0, sizeof(*st) * (size_t)n_inst * nrhs);
   auto t0 = std::chrono::steady_clock::now();
-  // one host thread per instance (each context has its own stream); the
-  // right-hand sides of an instance run as block solves
-  auto work = [&](int i) {
-    const int64_t k = (int64_t)i * nrhs;
-    status[i] = mg_pcg_solve_multi(cs[i], nrhs, b + k, u + k, rtol, maxit, st ? st + k : nullptr);
-  };
-  std::vector<std::thread> threads;
-  threads.reserve(n_inst);
-  for (int i = 0; i < n_inst; ++i) threads.emplace_back(work, i);
-  for (auto &t : threads) t.join();
+  std::vector<mg_status> status(n_inst, MG_OK);
+  if (n_inst > 0 && nrhs > 0) cg_drive(cs, n_inst, nrhs, b, u, rtol, maxit, st, status);
   if (wall_ms) *wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   mg_status worst = MG_OK;
   for (int i = 0; i < n_inst; ++i) {

@@ -300,8 +300,9 @@ struct Ctx {
   // PCG work (FP64, level 0, solve order)
   DBuf<double> r, z, p, q, ax, bpos, xpos;
   DBuf<double> partial;        // dot-product block partials
-  DBuf<double> scal;           // device scalars of CG
+  DBuf<double> scal;           // device scalars of CG (16 per column)
   double *h_scal = nullptr;    // pinned host mirror
+  double *h_scal_dev = nullptr;  // its device address
   // mass matrix (free rows x all DOFs) for mg_rhs_from_nodal, built lazily
   Csr M;
   Sell Ms;
@@ -312,15 +313,15 @@ struct Ctx {
   size_t events_used = 0;
   std::vector<int64_t> timed_launches;  // per level
   std::vector<double> timed_ms;
-  // captured V-cycle graph
+  // captured V-cycle graph (mg_vcycle, mg_vcycle_solve)
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   // block CG work (FP64, level 0, solve order, MG_BLOCK_MAX interleaved
-  // columns; allocated on the first block solve) and the block V-cycle
-  // graphs (index: block width)
+  // columns; allocated on the first block solve) and the captured CG
+  // iterations (index: block width, 1 = the single-vector solve)
   DBuf<double> kr, kz, kp, kq, kx, kb, kpartial;
-  hipGraphExec_t kgraph_exec[5] = {};
-  hipGraph_t kgraph[5] = {};
+  hipGraphExec_t cg_exec[5] = {};
+  hipGraph_t cg_graph[5] = {};
   ~Ctx();
 };
 
@@ -448,10 +449,11 @@ void spmv_dot_block(hipStream_t s, const Sell &S, int K, const double *p, double
 void dot_partials_block(hipStream_t s, int K, const double *x, const double *y, int64_t n, double *part,
                         int nblocks);
 void finish_sum_block(hipStream_t s, int K, const double *part, int nblocks, double *out);
-void cg_alpha_block(hipStream_t s, int K, unsigned mask, double *scal);
+void cg_alpha_block(hipStream_t s, int K, double *scal);
 void cg_update_xr_block(hipStream_t s, int K, double *x, double *r, const double *p, const double *q,
                         const double *scal, int64_t n, double *part, int nblocks);
-void cg_beta_block(hipStream_t s, int K, unsigned mask, double *scal);
+void cg_beta_block(hipStream_t s, int K, double *scal);
+void cg_active_block(hipStream_t s, int K, unsigned mask, double *scal);
 void cg_update_p_block(hipStream_t s, int K, double *p, const double *z, const double *scal, int64_t n);
 // cols: host array of K device pointers (canonical order; NULL = zero column)
 void gather_block(hipStream_t s, int K, const double *const *cols, const int32_t *perm, double *y, int64_t n);
@@ -463,5 +465,6 @@ void cg_update_xr(hipStream_t s, double *x, double *r, const double *p, const do
                   const double *scal, int64_t n, double *part, int nblocks);
 void cg_beta(hipStream_t s, double *scal);
 void cg_update_p(hipStream_t s, double *p, const double *z, const double *scal, int64_t n);
+void scal_to_host(hipStream_t s, const double *scal, double *host_dev, int count);
 
 }  // namespace mg

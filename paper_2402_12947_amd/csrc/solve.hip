@@ -753,6 +753,19 @@ void cg_update_p(hipStream_t s, double *p, const double *z, const double *scal, 
   MG_LAUNCH_CHECK();
 }
 
+// the CG scalars into pinned host memory (host_dev: its device address), made
+// visible to the host before the kernel ends, so that a wait on the stream
+// is enough to read them; a kernel rather than a copy so that it can sit in
+// a captured graph
+__global__ void k_scal_to_host(const double *__restrict__ scal, double *host_dev, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) host_dev[i] = scal[i];
+  __threadfence_system();
+}
+void scal_to_host(hipStream_t s, const double *scal, double *host_dev, int count) {
+  k_scal_to_host<<<1, 64, 0, s>>>(scal, host_dev, count);
+  MG_LAUNCH_CHECK();
+}
+
 // q = A p (FP64 SELL) with partial sums of p.q
 template <int U, bool M>
 __global__ __launch_bounds__(256) void k_spmv_dot(

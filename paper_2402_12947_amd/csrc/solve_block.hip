@@ -382,10 +382,12 @@ void finish_sum_block(hipStream_t s, int K, const double *part, int nblocks, dou
   MG_LAUNCH_CHECK();
 }
 
-__global__ void k_cg_alpha_k(double *scal, int K, unsigned mask) {
+// scal[8 K + q] != 0: column q is still active; a frozen column gets
+// alpha = beta = 0 (its x and r stay, p = z)
+__global__ void k_cg_alpha_k(double *scal, int K) {
   const int q = threadIdx.x;
   if (q >= K) return;
-  if (!((mask >> q) & 1u)) {
+  if (scal[8 * K + q] == 0.0) {
     scal[2 * K + q] = 0.0;
     return;
   }
@@ -394,8 +396,8 @@ __global__ void k_cg_alpha_k(double *scal, int K, unsigned mask) {
   scal[2 * K + q] = bad ? 0.0 : scal[q] / pq;
   if (bad) scal[6 * K + q] = 1.0;
 }
-void cg_alpha_block(hipStream_t s, int K, unsigned mask, double *scal) {
-  k_cg_alpha_k<<<1, 64, 0, s>>>(scal, K, mask);
+void cg_alpha_block(hipStream_t s, int K, double *scal) {
+  k_cg_alpha_k<<<1, 64, 0, s>>>(scal, K);
   MG_LAUNCH_CHECK();
 }
 
@@ -433,10 +435,10 @@ void cg_update_xr_block(hipStream_t s, int K, double *x, double *r, const double
   MG_LAUNCH_CHECK();
 }
 
-__global__ void k_cg_beta_k(double *scal, int K, unsigned mask) {
+__global__ void k_cg_beta_k(double *scal, int K) {
   const int q = threadIdx.x;
   if (q >= K) return;
-  if (!((mask >> q) & 1u)) {
+  if (scal[8 * K + q] == 0.0) {
     scal[5 * K + q] = 0.0;
     return;
   }
@@ -446,8 +448,17 @@ __global__ void k_cg_beta_k(double *scal, int K, unsigned mask) {
   scal[q] = rn;
   if (bad) scal[6 * K + q] = 1.0;
 }
-void cg_beta_block(hipStream_t s, int K, unsigned mask, double *scal) {
-  k_cg_beta_k<<<1, 64, 0, s>>>(scal, K, mask);
+void cg_beta_block(hipStream_t s, int K, double *scal) {
+  k_cg_beta_k<<<1, 64, 0, s>>>(scal, K);
+  MG_LAUNCH_CHECK();
+}
+
+__global__ void k_cg_active_k(double *scal, int K, unsigned mask) {
+  const int q = threadIdx.x;
+  if (q < K) scal[8 * K + q] = ((mask >> q) & 1u) ? 1.0 : 0.0;
+}
+void cg_active_block(hipStream_t s, int K, unsigned mask, double *scal) {
+  k_cg_active_k<<<1, 64, 0, s>>>(scal, K, mask);
   MG_LAUNCH_CHECK();
 }
 
