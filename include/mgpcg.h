@@ -190,6 +190,10 @@ typedef struct {
                                to the autotuner); copied by mg_setup.  Lets a
                                measurement repeat the layouts of an earlier
                                run, whose choices mg_level_info reports      */
+  int32_t patch_rows_rpl;   /* lanes per row of the patch-row residual (the
+                               rows of A at the patch DOFs): 0 = chosen per
+                               level by timing, else 1, 2, 4 or 8 (1 with
+                               patch_refine)                                   */
 } mg_options;
 
 typedef struct {
@@ -250,6 +254,7 @@ typedef struct {
                                reads (dense: packed lower tiles; dissection:
                                diagonal-block inverses and the tile rows of L
                                below them, forward and backward)              */
+  int32_t patch_rows_rpl;   /* lanes per row of the patch-row residual         */
 } mg_level_info;
 
 /* Arrays that mg_get_array copies to a caller-owned HOST buffer. */
@@ -283,7 +288,8 @@ enum {
  * young 6.9e10, poisson_ratio 0.33, sell_unroll 0, sell_mask -1, sell_rpl 0,
  * patch_fused 1, use_initial_guess 0, sell_colform 0, patch_factor_f32 1,
  * patch_refine 0, patch_inherit_levels 0, patch_chunk 0, patch_small_bound 0,
- * coarse_solver 0, coarse_nd_leaf 1024, sell_layout_levels 0, sell_layout NULL. */
+ * coarse_solver 0, coarse_nd_leaf 1024, sell_layout_levels 0, sell_layout NULL,
+ * patch_rows_rpl 0. */
 void mg_default_options(mg_options *opt);
 
 /* Builds the hierarchy (Sec. 2; Sec. 4.4; Sec. 5): per level the DOF map,

@@ -45,7 +45,7 @@ class MgOptions(C.Structure):
                 ("patch_inherit_levels", C.c_int32), ("patch_chunk", C.c_int32),
                 ("patch_small_bound", C.c_int32), ("coarse_solver", C.c_int32), ("coarse_nd_leaf", C.c_int32),
                 ("sell_layout_levels", C.c_int32),
-                ("sell_layout", C.POINTER(C.c_int32))]
+                ("sell_layout", C.POINTER(C.c_int32)), ("patch_rows_rpl", C.c_int32)]
 
 
 class MgSolveStats(C.Structure):
@@ -69,7 +69,7 @@ class MgLevelInfo(C.Structure):
                 ("sell_slices_16window", C.c_int64), ("patches_f32", C.c_int32),
                 ("patches_inherited", C.c_int32), ("patch_small_bound", C.c_int32),
                 ("patch_chunk", C.c_int32), ("coarse_nd_supernodes", C.c_int32),
-                ("coarse_solve_bytes", C.c_double)]
+                ("coarse_solve_bytes", C.c_double), ("patch_rows_rpl", C.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -164,7 +164,7 @@ class Solver:
                  patch_fused: bool = True, use_initial_guess: bool = False, sell_layout=None,
                  sell_colform: int = 0, patch_factor_f32: bool = True, patch_refine: bool = False,
                  patch_inherit_levels: int = 0, patch_chunk: int = 0, patch_small_bound: int = 0,
-                 coarse_solver: int = 0, coarse_nd_leaf: int = 1024):
+                 coarse_solver: int = 0, coarse_nd_leaf: int = 1024, patch_rows_rpl: int = 0):
         L = lib()
         opt = MgOptions()
         L.mg_default_options(C.byref(opt))
@@ -201,6 +201,7 @@ class Solver:
         opt.patch_small_bound = patch_small_bound
         opt.coarse_solver = coarse_solver
         opt.coarse_nd_leaf = coarse_nd_leaf
+        opt.patch_rows_rpl = patch_rows_rpl
         keep: list = []
         if sell_layout:  # [(sigma, unroll, mask, rpl) per level]
             lay = np.ascontiguousarray(np.asarray(sell_layout, dtype=np.int32).reshape(-1, 4))

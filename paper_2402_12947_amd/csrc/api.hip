@@ -122,6 +122,54 @@ static double time_on_stream(Ctx &c, F f) {
   return best / 5.0;
 }
 
+// Lanes per patch row (1, 2, 4 or 8) of a level's patch-row residual: the
+// option's value, else the fastest of the four on the residual launches of
+// all colours (the first of the order 1, 2, 4, 8 within 2 % of the fastest).
+// One lane per row is kept where the patch solves are refined (their
+// refinement values share the rows' layout), where every colour can run the
+// fused one-launch correction (whose residual reads whole slices of one lane
+// per row), and on levels with fewer than 2^20 stored patch-row entries.
+// The lanes per row set the order in which a row's products are summed.
+static void tune_patch_rows(Ctx &c, Level &L) {
+  Patches &P = L.patch;
+  const bool mixed = c.opt.precision == MG_MIXED;
+  const int fixed = c.opt.patch_rows_rpl;
+  if (fixed) {
+    relayout_patch_rows(c, L, mixed, fixed);
+    return;
+  }
+  bool all_fused = c.opt.patch_fused && P.maxn <= 12 * PATCH_TILE;
+  for (int col = 0; col < P.ncolour; ++col) all_fused &= P.colour_fused[col] != 0;
+  if (c.opt.patch_refine || all_fused || P.rows.stored < (1 << 20)) {
+    relayout_patch_rows(c, L, mixed, 1);
+    return;
+  }
+  auto run = [&] {
+    for (int col = 0; col < P.ncolour; ++col) {
+      if (mixed) patch_residual<float>(c.stream, P, col, L.w32[0], L.w32[1], LV<float>::res(L));
+      else patch_residual<double>(c.stream, P, col, L.w64[0], L.w64[1], LV<double>::res(L));
+    }
+  };
+  if (mixed) {
+    fill<float>(c.stream, L.w32[0], L.nfree, 0.5f);
+    fill<float>(c.stream, L.w32[1], L.nfree, 0.5f);
+  } else {
+    fill<double>(c.stream, L.w64[0], L.nfree, 0.5);
+    fill<double>(c.stream, L.w64[1], L.nfree, 0.5);
+  }
+  double best = -1;
+  int pick = 1;
+  for (int rpl : {1, 2, 4, 8}) {
+    relayout_patch_rows(c, L, mixed, rpl);
+    const double t = time_on_stream(c, run);
+    if (best < 0 || t < 0.98 * best) {
+      if (best < 0 || t < best) best = t;
+      pick = rpl;
+    }
+  }
+  relayout_patch_rows(c, L, mixed, pick);
+}
+
 // Patch-path autotuner of a level (setup): the packed-row chunk of the patch
 // inverses (8, 16 or 32 tiles per row item) and the one-workgroup size class
 // of the local correction (patches of up to 128, 256 or 384 DOFs, or the
@@ -168,9 +216,10 @@ static void tune_patches(Ctx &c, Level &L) {
   Patches &P = L.patch;
   P.small_nb = 0;
   if (P.n == 0 || !c.opt.local_correction) return;
+  tune_patch_rows(c, L);
   // size classes that take every patch of the level
   std::vector<int> nbs;
-  if (c.opt.patch_fused && !c.opt.patch_refine && P.rows.rpl == 1) {
+  if (c.opt.patch_fused && !c.opt.patch_refine) {
     if (c.opt.patch_small_bound > 0) {
       if (c.opt.patch_small_bound >= P.maxn) nbs.push_back(c.opt.patch_small_bound / PATCH_TILE);
     } else if (c.opt.patch_small_bound == 0) {
@@ -259,7 +308,7 @@ static void local_correction(Ctx &c, Level &L, const T *b, T *u, bool descending
       patch_apply_refined<T>(c.stream, L.patch, col, LV<T>::res(L), LV<T>::py(L), LV<T>::pz(L), u, L.pst.p);
       continue;
     }
-    if (L.patch.small_nb && L.patch.colour_fused[col]) {
+    if (L.patch.small_nb && L.patch.colour_fused[col] && L.patch.rows.rpl == 1) {
       patch_correct_small<T>(c.stream, L.patch, col, b, (const T *)nullptr, u);
       continue;
     }
@@ -1092,6 +1141,10 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.patch_small_bound != 0 && o.patch_small_bound != -1 && o.patch_small_bound != 128 &&
         o.patch_small_bound != 256 && o.patch_small_bound != 384)
       fail(MG_ERR_ARG, "patch_small_bound must be 0, -1, 128, 256 or 384");
+    if (o.patch_rows_rpl != 0 && o.patch_rows_rpl != 1 && o.patch_rows_rpl != 2 && o.patch_rows_rpl != 4 &&
+        o.patch_rows_rpl != 8)
+      fail(MG_ERR_ARG, "patch_rows_rpl must be 0, 1, 2, 4 or 8");
+    if (o.patch_refine && o.patch_rows_rpl > 1) fail(MG_ERR_ARG, "patch_refine needs patch_rows_rpl 0 or 1");
     if (o.sell_layout_levels < 0 || (o.sell_layout_levels > 0 && !o.sell_layout))
       fail(MG_ERR_ARG, "sell_layout must hold 4 values for each of sell_layout_levels levels");
     for (int l = 0; l < o.sell_layout_levels; ++l) {
@@ -1529,6 +1582,7 @@ mg_status mg_get_level_info(const mg_ctx *h, int32_t level, mg_level_info *o) {
     o->patches_inherited = L.patch.n_inherited;
     o->patch_small_bound = L.patch.small_nb * PATCH_TILE;
     o->patch_chunk = L.coarsest ? L.cpk.chunk : L.patch.inv.chunk;
+    o->patch_rows_rpl = L.patch.total > 0 ? L.patch.rows.rpl : 0;
     o->coarse_nd_supernodes = L.cnd.on ? L.cnd.nsup : 0;
     if (L.coarsest)
       o->coarse_solve_bytes = L.cnd.on ? (double)(L.cnd.dinv_bytes + L.cnd.b_bytes) * 2.0

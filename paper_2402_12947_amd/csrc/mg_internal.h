@@ -344,6 +344,7 @@ void inherit_patches(Ctx &c, const Level &F, Level &C, std::vector<std::vector<i
 void factor_patches(Ctx &c, Level &L);
 void factor_patches_batched(Ctx &c, Level &L, int batch_max, std::vector<int32_t> &rest, int *bad);
 void build_patch_rows(Ctx &c, Level &L, bool want32);
+void relayout_patch_rows(Ctx &c, Level &L, bool want32, int rpl);
 void build_patch_refine(Ctx &c, Level &L);
 void build_patch_neighbours(Ctx &c, Level &L, bool want32);
 void build_sgs(Ctx &c, Level &L, bool want32);

@@ -763,6 +763,18 @@ void build_patch_rows(Ctx &c, Level &L, bool want32) {
   }
 }
 
+// The patch rows' SELL with rpl lanes per row (a candidate of the patch-path
+// autotuner): the same rows in the same kernel order, one slice per 64 / rpl
+// rows.
+void relayout_patch_rows(Ctx &c, Level &L, bool want32, int rpl) {
+  Patches &P = L.patch;
+  if (P.total == 0 || P.rows.rpl == rpl) return;
+  Csr B;
+  permute_csr(c, L.A, P.dofs_canon, P.total, L.iperm, L.nfree, B);
+  build_sell(c, B, P.rows, 1, want32, rpl);
+  P.rows.perm.release();
+}
+
 // The refinement values of the patch rows: loc = the values of P.rows with
 // every column outside the row's own patch zeroed, so that the product with
 // loc is A^[d] applied to a vector that holds a patch solve at its patch's

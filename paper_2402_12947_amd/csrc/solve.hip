@@ -221,18 +221,21 @@ template void sgs_colour_sweep<float>(hipStream_t, const Sell &, const int32_t *
 // local correction
 // ---------------------------------------------------------------------------
 // r = b - A u on the rows of one colour's patches: the patch rows of A are a
-// SELL matrix of their own (kernel order, one lane per row, so a colour's row
-// range is a position range), streamed like the level operator.
+// SELL matrix of their own (kernel order, rpl lanes per row, chosen per level
+// by timing), streamed like the level operator; a colour's rows [k0, k1) are
+// the rows of the slices k0 / (64 / rpl) .. (k1 - 1) / (64 / rpl).
 template <class T>
 __global__ __launch_bounds__(256) void k_patch_residual(int64_t k0, int64_t k1, SellCols cols,
                                                         const T *__restrict__ val,
                                                         const int32_t *__restrict__ dofs, const T *__restrict__ b,
                                                         const T *__restrict__ u, T *__restrict__ res) {
-  int64_t k = (k0 & ~(int64_t)63) + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int64_t sl = k >> 6;
-  if (k >= ((k1 + 63) & ~(int64_t)63)) return;
-  T acc = sell_row(cols, val, u, sl, (int)(k & 63));
-  if (k >= k0 && k < k1) res[k] = b[dofs[k]] - acc;
+  const int rps = 64 / cols.rpl;
+  const int64_t pos = k0 / rps * 64 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t sl = pos >> 6;
+  if (sl > (k1 - 1) / rps) return;
+  const T acc = sell_row(cols, val, u, sl, (int)(pos & 63));
+  const SellRow rw = sell_row_of(cols, pos);
+  if (rw.lead && rw.row >= k0 && rw.row < k1) res[rw.row] = b[dofs[rw.row]] - acc;
 }
 
 template <class T>
@@ -240,7 +243,8 @@ void patch_residual(hipStream_t s, const Patches &pt, int colour, const T *b, co
   int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
   int64_t k0 = pt.h_kptr[p0], k1 = pt.h_kptr[p1];
   if (k1 <= k0) return;
-  int64_t span = ((k1 + 63) & ~(int64_t)63) - (k0 & ~(int64_t)63);
+  const int64_t rps = 64 / pt.rows.rpl;
+  const int64_t span = ((k1 - 1) / rps - k0 / rps + 1) * 64;
   k_patch_residual<T><<<(unsigned)((span + 255) / 256), 256, 0, s>>>(k0, k1, cols_of(pt.rows),
                                                                       sell_vals<T>(pt.rows), pt.dofs, b, u, res);
   MG_LAUNCH_CHECK();
@@ -558,8 +562,8 @@ template <class T>
 void patch_correct_small(hipStream_t s, const Patches &pt, int colour, const T *b, const T *res, T *u) {
   const int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
   if (p1 <= p0) return;
-  if (pt.small_nb * PATCH_TILE < pt.maxn || pt.rows.rpl != 1)
-    fail(MG_ERR_ARG, "patch_correct_small: patches too large");
+  if (pt.small_nb * PATCH_TILE < pt.maxn) fail(MG_ERR_ARG, "patch_correct_small: patches too large");
+  if (!res && pt.rows.rpl != 1) fail(MG_ERR_ARG, "patch_correct_small: the fused residual needs one lane per row");
   const T *pk = std::is_same<T, double>::value ? (const T *)pt.inv.v64.p : (const T *)pt.inv.v32.p;
   const unsigned g = (unsigned)(p1 - p0);
   if (pt.small_nb == 4)

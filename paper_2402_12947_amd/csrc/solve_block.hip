@@ -265,11 +265,14 @@ __global__ __launch_bounds__(256) void k_patch_residual_k(int64_t k0, int64_t k1
                                                           const int32_t *__restrict__ dofs,
                                                           const T *__restrict__ b, const T *__restrict__ u,
                                                           T *__restrict__ res) {
-  const int64_t k = (k0 & ~(int64_t)63) + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= ((k1 + 63) & ~(int64_t)63)) return;
+  const int rps = 64 / cols.rpl;
+  const int64_t pos = k0 / rps * 64 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if ((pos >> 6) > (k1 - 1) / rps) return;
   T acc[K];
-  sell_row_k<T, K>(cols, val, u, k >> 6, (int)(k & 63), acc);
-  if (k < k0 || k >= k1) return;
+  sell_row_k<T, K>(cols, val, u, pos >> 6, (int)(pos & 63), acc);
+  const SellRow rw = sell_row_of(cols, pos);
+  const int64_t k = rw.row;
+  if (!rw.lead || k < k0 || k >= k1) return;
   Row<T, K> o = ld<T, K>(b, dofs[k]);
 #pragma unroll
   for (int q = 0; q < K; ++q) o.v[q] -= acc[q];
@@ -281,7 +284,8 @@ void patch_residual_block(hipStream_t s, const Patches &pt, int colour, int K, c
   const int p0 = pt.colour_first[colour], p1 = pt.colour_first[colour + 1];
   const int64_t k0 = pt.h_kptr[p0], k1 = pt.h_kptr[p1];
   if (k1 <= k0) return;
-  const int64_t span = ((k1 + 63) & ~(int64_t)63) - (k0 & ~(int64_t)63);
+  const int64_t rps = 64 / pt.rows.rpl;
+  const int64_t span = ((k1 - 1) / rps - k0 / rps + 1) * 64;
   const unsigned g = (unsigned)((span + 255) / 256);
   const T *v = sell_vals<T>(pt.rows);
   if (K == 2) k_patch_residual_k<T, 2><<<g, 256, 0, s>>>(k0, k1, cols_of(pt.rows), v, pt.dofs, b, u, res);

@@ -68,6 +68,8 @@ def test_setup_rejects_bad_input_on_host():
     assert setup_status([mesh], sell_mask=2)[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_rpl=3)[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_colform=4)[0] == MG_ERR_ARG
+    assert setup_status([mesh], patch_rows_rpl=3)[0] == MG_ERR_ARG
+    assert setup_status([mesh], patch_rows_rpl=4, patch_refine=True)[0] == MG_ERR_ARG
     # per-level layouts follow the same rules as the global layout options
     assert setup_status([mesh], sell_layout=[[100, 0, -1, 0]])[0] == MG_ERR_ARG
     assert setup_status([mesh], sell_layout=[[0, 16, -1, 0]])[0] == MG_ERR_ARG
@@ -116,11 +118,11 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mgpcg.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mg_options), sizeof(mg_level_info),'
-                   ' sizeof(mg_solve_stats), offsetof(mg_options, sell_layout),'
-                   ' offsetof(mg_level_info, coarse_solve_bytes), offsetof(mg_solve_stats, history));return 0;}\n')
+                   ' sizeof(mg_solve_stats), offsetof(mg_options, patch_rows_rpl),'
+                   ' offsetof(mg_level_info, patch_rows_rpl), offsetof(mg_solve_stats, history));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(MgOptions), ctypes.sizeof(MgLevelInfo), ctypes.sizeof(MgSolveStats),
-            MgOptions.sell_layout.offset, MgLevelInfo.coarse_solve_bytes.offset, MgSolveStats.history.offset]
+            MgOptions.patch_rows_rpl.offset, MgLevelInfo.patch_rows_rpl.offset, MgSolveStats.history.offset]
     assert got == want

@@ -4,10 +4,11 @@ Local correction: the one-workgroup kernel in its size classes (patches of up
 to 128, 256 or 384 DOFs per workgroup; one launch per colour, two for a
 colour whose patches couple) or the three-launch path (patch-row residual,
 packed-inverse row items, gather); the packed row items hold 8, 16 or 32 tiles
-(`patch_chunk`), which also applies to the coarsest level's inverse.  Every
-forced combination: one V-cycle within 1e-10 of the oracle; the size classes
-bitwise equal to each other and to the three-launch path while a tile row
-fits one chunk.  The automatic choice is reported in the level info.
+(`patch_chunk`), which also applies to the coarsest level's inverse; the
+patch-row residual runs with 1, 2, 4 or 8 lanes per row (`patch_rows_rpl`).
+Every forced combination: one V-cycle within 1e-10 of the oracle; the size
+classes bitwise equal to each other and to the three-launch path while a tile
+row fits one chunk.  The automatic choice is reported in the level info.
 """
 import functools
 
@@ -97,4 +98,33 @@ def test_coarsest_chunk(chunk):
     u = to_dev(u0)
     s.vcycle(to_dev(b), u)
     assert rel_err(from_dev(u), want) < 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_patch_row_lanes(name):
+    """The patch-row residual with 1, 2, 4 or 8 lanes per row, on the
+    three-launch path and (where the patches fit) with the one-workgroup
+    kernel taking the residual from it; block solves with 8 lanes equal the
+    single-vector solves."""
+    maxn = _cycle(name, patch_small_bound=-1)[1]["max_patch"]
+    for rpl in (1, 2, 4, 8):
+        _, info = _cycle(name, patch_small_bound=-1, patch_rows_rpl=rpl)
+        assert info["patch_rows_rpl"] == rpl
+        if maxn <= 384:
+            _, info = _cycle(name, patch_small_bound=384, patch_rows_rpl=rpl)
+            assert info["patch_rows_rpl"] == rpl and info["patch_small_bound"] == 384
+    from paper_2402_12947_amd import Solver
+    wl, scale, degree, layers, policy = CASES[name]
+    meshes, ora, b, u0, want = _case(name)
+    s = Solver(meshes, degree=degree, layers=layers, policy=policy, patch_rows_rpl=8)
+    n = s.n_free(0)
+    bs = [to_dev(meshgen.random_rhs(n, 80 + r)) for r in range(2)]
+    us = [to_dev(np.zeros(n)) for _ in bs]
+    res = s.pcg_multi(bs, us, 1e-10, 300)
+    for r in range(2):
+        u = to_dev(np.zeros(n))
+        st = s.pcg(bs[r], u, 1e-10, 300)
+        assert abs(res["stats"][r]["iterations"] - st["iterations"]) <= 1
+        assert rel_err(from_dev(us[r]), from_dev(u)) < 1e-10
     s.close()
