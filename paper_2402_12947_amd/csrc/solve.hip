@@ -9,7 +9,9 @@
 //   skipping each row's padding (Sell::mask, also chosen by timing).  Blocks
 //   keep the hardware's round-robin spread over the 8 XCDs: renumbering them
 //   into one contiguous slice range per XCD was measured 1.6x slower on this
-//   kernel, into interleaved chunks of 1 to 64 blocks per XCD no faster.
+//   kernel, into interleaved chunks of 1 to 1024 blocks per XCD no faster
+//   (within the run-to-run spread, FP32 and FP64, levels 0 to 2 of the 3D P2
+//   cube), and chunks that leave each XCD only a few runs slower again.
 // * The Chebyshev-Jacobi step of the global smoother S_g (paper Sec. 3.2,
 //   Sec. 5; classical Chebyshev acceleration on D^-1 A) is one fused pass:
 //   r = D^-1 (b - A x), d = c_d d + c_r r, x' = x + d.
