@@ -25,7 +25,10 @@ run without timing events; a separate, untimed solve per arm then times every
 full Chebyshev step per level and the coarsest solve with HIP events on the
 library's stream (the roofline entry and the per-level table).  The CPU
 baseline is the oracle on a bounded sample (the same recipe at 1/8 of the
-size per side, single-threaded).
+size per side, single-threaded).  The default run then also times the
+many-instance solve (32 cubes of 50k-3M DOFs, 4 right-hand sides each, all
+solved together by mg_pcg_solve_batch) and reports it under many_instance
+(--no-batch skips it; --workload cube_batch_32x4 gives it its own line).
 
 Prints one JSON line.
 """
@@ -282,8 +285,9 @@ def run_study(scale=4):
 
 def run_batch(name, steps, warmup):
     """Many-instance solve: every instance's hierarchy in mixed precision with
-    graph-captured V-cycles, all instances solved together by
-    mg_pcg_solve_batch, against the same systems solved one by one in FP64."""
+    graph-captured CG iterations, all instances solved together by
+    mg_pcg_solve_batch (one host thread), against the same systems solved one
+    by one in FP64."""
     import torch
 
     import meshgen
@@ -348,7 +352,7 @@ def run_batch(name, steps, warmup):
     value = total * steps / el_fast
     base = total / el_slow
     return {
-        "metric": "aggregate DOFs solved/sec to rtol 1e-8 (batched mixed MG-PCG, graph-captured V-cycles)",
+        "metric": "aggregate DOFs solved/sec to rtol 1e-8 (batched mixed MG-PCG, graph-captured CG iterations)",
         "value": value, "unit": "DOF/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": 1e3 * el_fast / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-in-f64", "data": "synthetic (seeded meshes and right-hand sides)",
@@ -408,6 +412,9 @@ def main():
     ap.add_argument("--study", action="store_true",
                     help="instead of the benchmark line: the stationary-solver / preconditioner study of "
                          "plain vs global-local smoothing on the reference mesh and Cases A and B")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="default workload only: skip the many-instance solve (cube_batch_32x4, two batches) "
+                         "reported under many_instance")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -548,6 +555,20 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU baseline: the oracle, single-threaded, on the 1/8-size sample")
         line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8, policy, problem)
+    if args.workload == "cube_129_p2" and not args.no_batch:
+        # the many-instance pattern in the same run: 32 cubes of uneven size,
+        # 4 right-hand sides each, all solved together
+        log("many-instance solve (cube_batch_32x4)")
+        bt = run_batch("cube_batch_32x4", 2, 1)
+        line["many_instance"] = {
+            "workload": "cube_batch_32x4", "metric": bt["metric"], "value": bt["value"], "unit": "DOF/s",
+            "ms_per_batch": bt["ms_per_step"], "batches_timed": 2,
+            "instances": bt["config"]["instances"], "rhs_per_instance": bt["config"]["rhs_per_instance"],
+            "dofs_total": bt["config"]["dofs_total"], "iterations_min_max": bt["config"]["iterations_min_max"],
+            "worst_true_rel_residual": bt["config"]["worst_true_rel_residual"],
+            "setup_s": bt["config"]["setup_s"], "unblocked_dofs_per_s": bt["unblocked_dofs_per_s"],
+            "one_by_one_fp64_dofs_per_s": bt["one_by_one_fp64"]["dofs_per_s"],
+            "speedup_vs_one_by_one_fp64": bt["speedup_vs_one_by_one_fp64"]}
     print(json.dumps(line), flush=True)
 
 
