@@ -1,5 +1,5 @@
-"""GPU parity at full size: the 1025x1025 P2 square (4.19M DOFs, five levels),
-the 2D P2 workload.
+"""GPU parity at full size: the 1025x1025 square with P2 (4.19M DOFs) and P3
+elements (9.43M DOFs), five levels each, the 2D workloads.
 
 The oracle cannot run every stage at this size in seconds, so the checks are:
 complete comparisons where the oracle is fast (DOF map, flags, patches,
@@ -27,20 +27,21 @@ from tests.parity_util import from_dev, rel_err, sparse_close, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def hier():
+@pytest.fixture(scope="module", params=[2, 3], ids=["p2", "p3"])
+def hier(request):
     """The GPU hierarchy and an oracle hierarchy with its own assembly, Galerkin
     products, patch factorisations and coarsest Cholesky, taking the GPU's
     prolongations (compared on sampled rows below) and Chebyshev intervals."""
     from paper_2402_12947_amd import Solver
+    degree = request.param
     meshes = meshgen.hierarchy("square_1025", seed=0)
-    print("[fullsize] building GPU hierarchy", flush=True)
-    gpu = Solver(meshes, degree=2, tau=0.1, layers=1)
+    print(f"[fullsize P{degree}] building GPU hierarchy", flush=True)
+    gpu = Solver(meshes, degree=degree, tau=0.1, layers=1)
     nl = gpu.n_levels
     Ps = [gpu.prolongation(l) for l in range(nl - 1)]
     iv = [(gpu.level_info(l)["cheb_lo"], gpu.level_info(l)["cheb_hi"]) for l in range(nl - 1)]
-    print("[fullsize] oracle hierarchy", flush=True)
-    ora = oracle.Hierarchy(meshes, tau=0.1, layers=1, opts=oracle.Options(degree=2), prolongations=Ps,
+    print(f"[fullsize P{degree}] oracle hierarchy", flush=True)
+    ora = oracle.Hierarchy(meshes, tau=0.1, layers=1, opts=oracle.Options(degree=degree), prolongations=Ps,
                            intervals=iv)
     yield meshes, gpu, ora
     gpu.close()
@@ -74,14 +75,15 @@ def test_dofmap_flags_patches(full):
 def test_operator_and_transfer(full):
     meshes, gpu, dm, A = full
     assert sparse_close(gpu.matrix(0), A, 1e-12)
-    dmc = DofMap(meshes[1], 2)
+    degree = gpu.degree
+    dmc = DofMap(meshes[1], degree)
     rng = np.random.default_rng(1)
     rows = np.sort(rng.choice(dm.n_free, 20000, replace=False))
     pts = dm.nodes[dm.free[rows]]
     cell = locate(pts, dmc.coords, dmc.cells)
     assert np.array_equal(gpu.get_array(0, "locate")[rows], cell)
     lam = barycentric(dmc.coords, dmc.cells, cell, pts)
-    basis, _ = oracle.local_basis(2, 2)
+    basis, _ = oracle.local_basis(2, degree)
     vals = np.stack([oracle.fem.poly_eval(p, lam) for p in basis], axis=1)
     cols = dmc.free_index[dmc.cell_dofs[cell]]
     vals[cols < 0] = 0.0
@@ -126,7 +128,7 @@ def test_solution_true_residual(full):
     b = meshgen.random_rhs(n, 6)
     u = to_dev(np.zeros(n))
     st = gpu.pcg(to_dev(b), u, 1e-8, 100)
-    assert st["converged"] and st["iterations"] <= 12
+    assert st["converged"] and st["iterations"] <= 14
     x = from_dev(u)
     assert np.linalg.norm(b - A @ x) <= 1.05e-8 * np.linalg.norm(b)
 
@@ -139,9 +141,11 @@ def test_vcycle_and_pcg_iterations(hier):
     The coarse operators agree with the oracle's Galerkin products to
     rounding (1e-11 relative, checked first; the GPU does not store entries
     that vanish identically, whose rounding residue the oracle keeps), and the
-    coarsest solve (16,383 unknowns, condition number about 1.4e4) amplifies
-    that rounding to about 1e-10 in a whole cycle; with the same operators the
-    two cycles agree to about 1e-12."""
+    coarsest solve amplifies that rounding by up to its condition number in a
+    whole cycle: about 1e-10 with P2 (16,383 coarsest unknowns, condition
+    number about 1.4e4), 1.7e-9 measured with P3 (36,863 unknowns), hence the
+    bounds 1e-9 and 5e-9 of that comparison.  With the same operators the two
+    cycles agree to about 1e-12 (bound 1e-10)."""
     meshes, gpu, ora = hier
     ops = [gpu.matrix(l) for l in range(1, gpu.n_levels)]
     for l, A in enumerate(ops, start=1):
@@ -151,12 +155,16 @@ def test_vcycle_and_pcg_iterations(hier):
     u = to_dev(u0)
     gpu.vcycle(to_dev(b), u)
     x_cycle = from_dev(u)
-    assert rel_err(x_cycle, ora.vcycle(b, u0.copy())) < 1e-9
-    print("[fullsize] oracle PCG", flush=True)
+    d_own = rel_err(x_cycle, ora.vcycle(b, u0.copy()))
+    print(f"[fullsize P{gpu.degree}] cycle vs the oracle's own coarse operators: {d_own:.2e}", flush=True)
+    assert d_own < (1e-9 if gpu.degree == 2 else 5e-9)
+    print(f"[fullsize P{gpu.degree}] oracle PCG", flush=True)
     x_o, it_o, conv_o, _ = ora.pcg(b, 1e-8, 100)
     u = to_dev(np.zeros(n))
     st = gpu.pcg(to_dev(b), u, 1e-8, 100)
     assert conv_o and st["converged"] and abs(st["iterations"] - it_o) <= 1, (st["iterations"], it_o)
     assert rel_err(from_dev(u), x_o) < 1e-8
     ora.replace_coarse_operators(ops)
-    assert rel_err(x_cycle, ora.vcycle(b, u0.copy())) < 1e-10
+    d_same = rel_err(x_cycle, ora.vcycle(b, u0.copy()))
+    print(f"[fullsize P{gpu.degree}] cycle with the GPU's coarse operators: {d_same:.2e}", flush=True)
+    assert d_same < 1e-10
