@@ -20,8 +20,11 @@ right-hand sides:
   plain_fp64  plain Chebyshev smoother (no S_c, unadjusted lambda_max), FP64
   ref         global-local FP64 on the high-quality reference mesh (the same
               recipe without degraded cells): the iteration count to match
-value = DOFs x timed solves / wall time of the mixed arm.  The timed solves
-run without timing events; a separate, untimed solve per arm then times every
+value = DOFs x timed solves / wall time of the mixed arm.  Each CG iteration
+of the timed solves is one replay of its captured hipGraph (--eager: host
+launches), and the run starts with 10 s of untimed streaming so that the GPU's
+clocks and power state settle.  The timed solves run without timing events;
+a separate, untimed solve per arm then times every
 full Chebyshev step per level and the coarsest solve with HIP events on the
 library's stream (the roofline entry and the per-level table).  The CPU
 baseline is the oracle on a bounded sample (the same recipe at 1/8 of the
@@ -391,7 +394,12 @@ def main():
                     help="comma list of mixed, fp64, paper (mixed with the paper's per-level patches only), "
                          "plain, ref")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay the V-cycle from a hipGraph in the timed solves")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every kernel of the timed solves from the host (default: each CG iteration of "
+                         "the global-local arms replayed from its captured hipGraph)")
+    ap.add_argument("--gpu-warmup-s", type=float, default=10.0,
+                    help="seconds of untimed streaming on the GPU before the first setup (clocks and power "
+                         "state settle; 0 = none)")
     ap.add_argument("--sigma", type=int, default=0, help="SELL sorting window (0 = library's choice)")
     ap.add_argument("--inherit", type=int, default=1,
                     help="coarse levels that also take the patches inherited through the interpolation from the "
@@ -425,6 +433,12 @@ def main():
     import torch
     import meshgen
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.gpu_warmup_s > 0:
+        from paper_2402_12947_amd.binding import stream_probe
+        log(f"GPU warm-up: {args.gpu_warmup_s:.0f} s of streaming")
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < args.gpu_warmup_s:
+            stream_probe("mix7:1", 2 << 30, 20)
     if args.study:
         run_study()
         return
@@ -447,7 +461,7 @@ def main():
     for prec in ("mixed", "fp64"):
         if prec in arms:
             res[prec] = run_arm(meshes, degree, seeds=seeds, warmup=args.warmup, precision=prec, local=True,
-                                use_graph=args.graph, label=f"global-local {prec}",
+                                use_graph=not args.eager, label=f"global-local {prec}",
                                 layout=parse_layout(args.layout), **common)
     main_arm = res[args.precision]
     n = main_arm["n"]
@@ -468,7 +482,7 @@ def main():
     if "paper" in arms and args.inherit > 0:
         pp = dict(common, inherit=0)
         q = run_arm(meshes, degree, seeds=seeds, warmup=args.warmup, precision="mixed", local=True, timing=False,
-                    use_graph=args.graph, label="global-local mixed, paper's patches", **pp)
+                    use_graph=not args.eager, label="global-local mixed, paper's patches", **pp)
         extra["global_local_mixed_paper_patches"] = _arm_summary(q)
         res_paper = q
     else:
@@ -533,7 +547,7 @@ def main():
                    "setup_s": round(main_arm["setup_s"], 3),
                    "true_rel_residual": main_arm["true_rel_residual"],
                    "patches_level0": main_arm["levels"][0]["n_patches"],
-                   "coarsest_dofs": main_arm["levels"][-1]["n_free"], "graph": bool(args.graph),
+                   "coarsest_dofs": main_arm["levels"][-1]["n_free"], "graph": not args.eager,
                    "levels_n_nnz_padding_sigma_idx16_unroll_mask_rpl": [
                        [lv["n_free"], lv["nnz"], round(lv["sell_stored"] / max(1, lv["nnz"]), 4), lv["sell_sigma"],
                         round(lv["sell_nnz16"] / max(1, lv["sell_stored"]), 4), lv["sell_unroll"], lv["sell_mask"],
