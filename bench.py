@@ -401,10 +401,11 @@ def main():
                     help="seconds of untimed streaming on the GPU before the first setup (clocks and power "
                          "state settle; 0 = none)")
     ap.add_argument("--sigma", type=int, default=0, help="SELL sorting window (0 = library's choice)")
-    ap.add_argument("--inherit", type=int, default=1,
+    ap.add_argument("--inherit", type=int, default=-1,
                     help="coarse levels that also take the patches inherited through the interpolation from the "
                          "finest level's degraded cells (patch_inherit_levels; 0 = the paper's construction, "
-                         "which then also runs as an extra mixed arm when this is above 0)")
+                         "which then also runs as an extra mixed arm when this is above 0); default 1, and 0 on "
+                         "the patch stress workload, whose inherited components would cover most of level 1")
     ap.add_argument("--refine", action="store_true", help="one FP64 refinement step of every patch solve")
     ap.add_argument("--f64-patch-factor", action="store_true",
                     help="mixed arm: factor the patch systems in FP64 (default: FP32 matrix cores)")
@@ -447,6 +448,8 @@ def main():
         return
     recipe, degree, scale, layers, rtol, policy = WORKLOADS[args.workload][:6]
     problem = WORKLOADS[args.workload][6] if len(WORKLOADS[args.workload]) > 6 else "poisson"
+    if args.inherit < 0:
+        args.inherit = 0 if args.workload == "cube_129_stress_p2" else 1
     log(f"generating the {args.workload} hierarchy")
     meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
     arms = set(args.arms.split(","))

@@ -401,6 +401,7 @@ void patch_apply_refined(hipStream_t s, const Patches &pt, int colour, T *res, T
 // update of u) in one launch (colour_fused colours only); else the product
 // and the update, from the residual res of patch_residual.
 constexpr int SMALL_PATCH = 384;  // largest patch of the one-workgroup path (12 tile rows)
+constexpr int MAX_PATCH = 16384;  // largest local-correction patch (its dense inverse: 2 GiB in FP64)
 template <class T>
 void patch_correct_small(hipStream_t s, const Patches &pt, int colour, const T *b, const T *res, T *u);
 template <class T>

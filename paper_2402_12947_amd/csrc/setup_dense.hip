@@ -95,10 +95,10 @@ __device__ void inverse_from_factor(const double *Lf, int n, double *X) {
 
 // patches above BATCH_MAX DOFs are factored one at a time by the blocked
 // multi-workgroup path of the coarsest level; above MAX_PATCH they are refused
+// (when the patches are set)
 constexpr int BATCH_MAX = 2048;
 // smallest coarsest level solved by nested dissection when coarse_solver = 0
 constexpr int64_t COARSE_ND_MIN = 12288;
-constexpr int MAX_PATCH = 16384;
 
 __global__ void k_gather_patch_dense(const int64_t *rp, const int32_t *col, const double *val, const int32_t *B,
                                      int n, double *M) {
@@ -137,9 +137,6 @@ void factor_patches(Ctx &c, Level &L) {
   Patches &P = L.patch;
   if (P.n == 0) return;
   hipStream_t s = c.stream;
-  if (P.maxn > MAX_PATCH)
-    fail(MG_ERR_LIMIT, "a local-correction patch has %d DOFs (limit %d): the low-quality regions merge into "
-                       "one large subdomain", P.maxn, MAX_PATCH);
   int64_t total = (int64_t)P.inv64.n;
   DBuf<int> bad;
   bad.alloc(1);

@@ -224,6 +224,11 @@ void set_patches(Ctx &c, Level &L, const std::vector<std::vector<int32_t>> &dofs
     P.maxn = std::max(P.maxn, (int)dofs[p].size());
   }
   P.total = P.h_ptr[P.n];
+  if (P.maxn > MAX_PATCH)
+    fail(MG_ERR_LIMIT, "a local-correction patch has %d DOFs (limit %d): the low-quality regions merge into "
+                       "one large subdomain%s", P.maxn, MAX_PATCH,
+         P.n_inherited > 0 ? " (with the patches inherited from the finer level; fewer patch_inherit_levels "
+                             "avoid it)" : "");
   // kernel order: by colour, then canonical id
   std::vector<int> order(P.n);
   std::iota(order.begin(), order.end(), 0);

@@ -14,8 +14,9 @@
       known byte count.
 
   python profile_summary.py mfma <counter_collection.csv> <out.md> "<command>" "<title>"
-      FP64 matrix-core work per dispatch (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512
-      flops) over the dispatch duration, against the FP64 matrix peak.
+      FP32 and FP64 matrix-core work per dispatch (SQ_INSTS_VALU_MFMA_MOPS_F32 /
+      _F64 x 512 flops) over the dispatch duration, against the matrix peak of
+      the dispatch's precision.
 """
 import csv
 import hashlib
@@ -129,28 +130,36 @@ def counters(fetch_csv, write_csv, out_json, out_md, kernel, alg_bytes, fetch_cm
     print(json.dumps(d))
 
 
-PEAK_F64_TFLOPS = 78.6
+PEAK_TFLOPS = {"F64": 78.6, "F32": 157.3}   # MI355X dense matrix-core peaks
 
 
 def mfma(path, out, cmd, title):
+    """Matrix-core work per dispatch from SQ_INSTS_VALU_MFMA_MOPS_F32 / _F64
+    (units of 512 flops) over the dispatch duration, against the peak of the
+    dispatch's own precision (the one with the larger count)."""
     per = defaultdict(dict)
     for r in csv.DictReader(open(path)):
         key = (int(r["Dispatch_Id"]), short(r["Kernel_Name"]), int(r["Grid_Size"]))
         per[key][r["Counter_Name"]] = float(r["Counter_Value"])
         per[key]["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
     L = [f"# {title}", "", "Command (from the repository root, one MI355X):", "", "```", cmd, "```", "",
-         "| dispatch | kernel | workgroups | FP64 MFMA flops | ms | TFLOP/s | of FP64 matrix peak |",
-         "|---|---|---|---|---|---|---|"]
-    tf = tt = 0.0
+         "| dispatch | kernel | workgroups | precision | MFMA flops | ms | TFLOP/s | of matrix peak |",
+         "|---|---|---|---|---|---|---|---|"]
+    tot = defaultdict(lambda: [0.0, 0])
     for (did, name, grid), v in sorted(per.items()):
-        fl = v.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512
+        fl = {p: v.get(f"SQ_INSTS_VALU_MFMA_MOPS_{p}", 0.0) * 512 for p in PEAK_TFLOPS}
+        p = max(fl, key=fl.get)
         ns = v["ns"]
-        tf += fl
-        tt += ns
-        L.append(f"| {did} | `{name}` | {grid // 256} | {fl:.3e} | {ns / 1e6:.1f} | {fl / ns / 1e3:.2f} | "
-                 f"{fl / ns / 1e3 / PEAK_F64_TFLOPS:.3f} |")
-    L += ["", f"Total: {tf:.3e} flops in {tt / 1e6:.1f} ms = {tf / tt / 1e3:.2f} TFLOP/s "
-              f"({tf / tt / 1e3 / PEAK_F64_TFLOPS:.3f} of the {PEAK_F64_TFLOPS} TFLOP/s FP64 matrix peak).", ""]
+        tot[p][0] += fl[p]
+        tot[p][1] += ns
+        L.append(f"| {did} | `{name}` | {grid // 256} | {p} | {fl[p]:.3e} | {ns / 1e6:.1f} | "
+                 f"{fl[p] / ns / 1e3:.2f} | {fl[p] / ns / 1e3 / PEAK_TFLOPS[p]:.3f} |")
+    L.append("")
+    for p, (f, t) in sorted(tot.items()):
+        if t:
+            L.append(f"{p} total: {f:.3e} flops in {t / 1e6:.1f} ms = {f / t / 1e3:.2f} TFLOP/s "
+                     f"({f / t / 1e3 / PEAK_TFLOPS[p]:.3f} of the {PEAK_TFLOPS[p]} TFLOP/s {p} matrix peak).")
+    L.append("")
     open(out, "w").write("\n".join(L) + "\n")
 
 

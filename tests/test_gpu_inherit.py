@@ -90,3 +90,14 @@ def test_level1_bound_back_at_the_reference():
     assert abs(gpu.level_info(1)["cheb_hi"] - lam_ref) < 0.01 * lam_ref
     ref.close()
     plain.close()
+
+
+def test_inheritance_too_large_is_refused():
+    """On the patch stress mesh (about 40 % of the fine DOFs in patches) the
+    inherited components cover most of level 1: set-up stops with MG_ERR_LIMIT
+    and names the inheritance, before any dense allocation."""
+    from paper_2402_12947_amd import MG_ERR_LIMIT, setup_status
+    meshes = meshgen.hierarchy("cube_129_stress", seed=0, scale=2)
+    code, msg = setup_status(meshes, degree=2, layers=0, policy="overlap", patch_inherit_levels=1)
+    print(f"[inherit stress] {code} {msg}", flush=True)
+    assert code == MG_ERR_LIMIT and "patch_inherit_levels" in msg
