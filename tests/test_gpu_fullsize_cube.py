@@ -138,11 +138,14 @@ def test_full_size_forms():
     slice at 32 bits (whose decode is compared with the oracle in
     test_gpu_colforms), for one smoother application, one V-cycle and a
     whole solve.  Both hierarchies fix the same layouts (sorting window,
-    gathers in flight, padding skip, lanes per row) so that only the column
-    forms differ."""
+    gathers in flight, padding skip, lanes per row, and the local
+    correction's chunk, size class and lanes per patch row, which the
+    autotuner would otherwise choose by timing, each setting an order of
+    summation) so that only the column forms differ."""
     from paper_2402_12947_amd import Solver
     meshes = meshgen.hierarchy("cube_129", seed=0)
-    fixed = dict(degree=2, tau=0.1, layers=1, sell_sigma=128, sell_unroll=8, sell_mask=1, sell_rpl=1)
+    fixed = dict(degree=2, tau=0.1, layers=1, sell_sigma=128, sell_unroll=8, sell_mask=1, sell_rpl=1,
+                 patch_chunk=16, patch_small_bound=-1, patch_rows_rpl=1)
     print("[full-size cube] natural column forms", flush=True)
     nat = Solver(meshes, **fixed)
     for l in (0, 1):
