@@ -118,7 +118,8 @@ typedef struct {
                                The result is the same bitwise either way      */
   int32_t sell_rpl;         /* lanes per row of the level operators' sparse
                                products: 0 = chosen per level by timing,
-                               1, 2, 4 or 8                                    */
+                               1, 2, 4, 8, 16 or 32 (the transfer operators
+                               take at most 8)                                 */
   int32_t patch_fused;      /* 1: a colour whose patches fit the level's
                                one-workgroup class (patch_small_bound) and do
                                not couple to each other runs its local
@@ -233,7 +234,7 @@ typedef struct {
                                its slice; 0: they read every stored entry
                                (same result bitwise; chosen by timing)         */
   int32_t sell_rpl;         /* lanes per row of the level's operator products
-                               (1, 2, 4 or 8; chosen by timing)               */
+                               (1, 2, 4, 8, 16 or 32; chosen by timing)       */
   int32_t patch_fused_colours; /* patch colours whose local correction runs
                                as one launch                                   */
   int64_t sell_slices;      /* slices of the level operator's SELL layout      */

@@ -1125,8 +1125,9 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     if (o.sell_unroll != 0 && o.sell_unroll != 4 && o.sell_unroll != 8)
       fail(MG_ERR_ARG, "sell_unroll must be 0, 4 or 8");
     if (o.sell_mask < -1 || o.sell_mask > 1) fail(MG_ERR_ARG, "sell_mask must be -1, 0 or 1");
-    if (o.sell_rpl != 0 && o.sell_rpl != 1 && o.sell_rpl != 2 && o.sell_rpl != 4 && o.sell_rpl != 8)
-      fail(MG_ERR_ARG, "sell_rpl must be 0, 1, 2, 4 or 8");
+    if (o.sell_rpl != 0 && o.sell_rpl != 1 && o.sell_rpl != 2 && o.sell_rpl != 4 && o.sell_rpl != 8 &&
+        o.sell_rpl != 16 && o.sell_rpl != 32)
+      fail(MG_ERR_ARG, "sell_rpl must be 0, 1, 2, 4, 8, 16 or 32");
     if (o.patch_fused != 0 && o.patch_fused != 1) fail(MG_ERR_ARG, "patch_fused must be 0 or 1");
     if (o.use_initial_guess != 0 && o.use_initial_guess != 1) fail(MG_ERR_ARG, "use_initial_guess must be 0 or 1");
     if (o.sell_colform < 0 || o.sell_colform > 3) fail(MG_ERR_ARG, "sell_colform must be 0, 1, 2 or 3");
@@ -1150,7 +1151,7 @@ mg_status mg_setup(const mg_mesh *levels, int32_t n_levels, double quality_thres
     for (int l = 0; l < o.sell_layout_levels; ++l) {
       const int32_t *q = o.sell_layout + 4 * l;
       if (q[0] < 0 || (q[0] > 1 && q[0] % SELL_C) || (q[1] != 0 && q[1] != 4 && q[1] != 8) || q[2] < -1 ||
-          q[2] > 1 || (q[3] != 0 && q[3] != 1 && q[3] != 2 && q[3] != 4 && q[3] != 8))
+          q[2] > 1 || (q[3] != 0 && q[3] != 1 && q[3] != 2 && q[3] != 4 && q[3] != 8 && q[3] != 16 && q[3] != 32))
         fail(MG_ERR_ARG, "sell_layout of level %d: (sigma, unroll, mask, rpl) must each be a value the "
                          "options sell_sigma, sell_unroll, sell_mask, sell_rpl accept", l);
     }

@@ -595,7 +595,8 @@ __global__ __launch_bounds__(256) void k_compress_cols(int64_t nslices, const in
 void build_sell(Ctx &c, const Csr &A, Sell &S, int sigma, bool want32, int rpl) {
   hipStream_t s = c.stream;
   if (sigma != 1) fail(MG_ERR_ARG, "build_sell keeps the row order (sigma must be 1)");
-  if (rpl != 1 && rpl != 2 && rpl != 4 && rpl != 8) fail(MG_ERR_ARG, "lanes per row must be 1, 2, 4 or 8");
+  if (rpl != 1 && rpl != 2 && rpl != 4 && rpl != 8 && rpl != 16 && rpl != 32)
+    fail(MG_ERR_ARG, "lanes per row must be 1, 2, 4, 8, 16 or 32");
   S.nrows = A.nrows;
   S.ncols = A.ncols;
   S.sigma = 1;
@@ -1114,7 +1115,7 @@ void solve_order(Ctx &c, Level &L, int sigma, bool want32) {
     rpls.push_back(c.opt.sell_rpl);
   } else if (tune) {
     rpls.push_back(1);
-    for (int r : {2, 4, 8})
+    for (int r : {2, 4, 8, 16, 32})
       if (avg >= 8.0 * r) rpls.push_back(r);
   } else {
     rpls.push_back(rule_rpl(L.A.nrows, L.A.nnz));
@@ -1217,7 +1218,7 @@ void build_transfer_sell(Ctx &c, Level &F, const Level &C, bool want32) {
   const bool timing = F.nfree >= 65536;
   if (timing) tune_unroll(c, F.P, C.nfree, F.nfree, want32);
   if (!timing || c.opt.sell_rpl) {
-    build_sell(c, Rp, F.R, 1, want32, c.opt.sell_rpl ? c.opt.sell_rpl : rule_rpl(Rp.nrows, Rp.nnz));
+    build_sell(c, Rp, F.R, 1, want32, c.opt.sell_rpl ? std::min(c.opt.sell_rpl, 8) : rule_rpl(Rp.nrows, Rp.nnz));
     if (timing) tune_unroll(c, F.R, F.nfree, C.nfree, want32);
     return;
   }

@@ -5,8 +5,9 @@ Every SELL row product sums entry j of a lane's share of its row into
 accumulator j mod U and adds the accumulators pairwise, whether it skips the
 padding of the shorter rows of a slice (sell_mask = 1) or reads every stored
 entry (sell_mask = 0), so that choice of the autotuner cannot change a result.
-With several lanes per row (sell_rpl) the row is split over the lanes, which
-changes the rounding of the row products only.  Checked on whole solves
+With several lanes per row (sell_rpl: 2 to 32; 16 and 32 for the long rows of
+the Galerkin levels, the transfers keeping at most 8) the row is split over
+the lanes, which changes the rounding of the row products only.  Checked on whole solves
 (every level operator, transfer, patch-row and split first-step product of
 the cycle) with the variant fixed by the options.
 """
@@ -63,7 +64,7 @@ def test_masked_and_full_products_agree_bitwise(name, precision):
     x_ref = x_o if precision == "fp64" else ora.pcg(rhs, 1e-12, 300)[0]
     tol = 1e-8 if precision == "fp64" else 1e-6
     b = to_dev(rhs)
-    for unroll, rpl in ((4, 1), (8, 1), (4, 2), (8, 4), (4, 8)):
+    for unroll, rpl in ((4, 1), (8, 1), (4, 2), (8, 4), (4, 8), (8, 16), (4, 32)):
         u0, it0, info = _solve(meshes, degree, layers, precision, unroll, 0, b, rtol, rpl)
         u1, it1, _ = _solve(meshes, degree, layers, precision, unroll, 1, b, rtol, rpl)
         # the layouts pad, so the masked variant really skips entries
