@@ -347,7 +347,8 @@ mg_status mg_vcycle_noalloc(mg_ctx *c, const double *b, double *u);
  * recursively updated residual; a warm start that already meets the tolerance
  * returns u unchanged after 0 iterations, and b = 0 returns u = 0.  st may be
  * NULL.  Returns MG_NOT_CONVERGED if maxit iterations were not enough (u holds
- * the last iterate), or MG_ERR_BREAKDOWN. */
+ * the last iterate), or MG_ERR_BREAKDOWN (p.Ap <= 0, or a non-finite value,
+ * one in b included). */
 mg_status mg_pcg_solve(mg_ctx *c, const double *b, double *u, double rtol, int32_t maxit,
                        mg_solve_stats *st);
 

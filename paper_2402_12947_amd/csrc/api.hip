@@ -790,13 +790,19 @@ static bool cg_advance(CgRun &R) {
   switch (R.phase) {
     case CgRun::START: {
       for (int q = 0; q < K; ++q) {
+        // a non-finite b (or warm-start residual) is a breakdown before the
+        // first iteration, not a zero right-hand side
+        if (!std::isfinite(h[7 * K + q]) || (R.warm && !std::isfinite(h[3 * K + q]))) {
+          R.broken = q;
+          break;
+        }
         R.bnorm[q] = std::sqrt(h[7 * K + q]);
         R.rel[q] = R.bnorm[q] > 0 ? (R.warm ? std::sqrt(h[3 * K + q]) / R.bnorm[q] : 1.0) : 0.0;
         R.hist[q].push_back(R.rel[q]);
         R.conv[q] = R.bnorm[q] == 0.0 || R.rel[q] <= R.rtol;
         if (!R.conv[q]) R.mask |= 1u << q;
       }
-      if (!R.mask || R.maxit <= 0) {
+      if (R.broken >= 0 || !R.mask || R.maxit <= 0) {
         cg_end(R);
         return true;
       }
@@ -1444,6 +1450,7 @@ mg_status mg_vcycle_solve(mg_ctx *h, const double *b, double *u, double rtol, in
   }
   dot_to(c, c.bpos, c.bpos, n, scal + 7);
   const double bnorm = std::sqrt(read_scalar(c, scal + 7));
+  if (!std::isfinite(bnorm)) fail(MG_ERR_BREAKDOWN, "the right-hand side holds a non-finite value");
   double rel = bnorm > 0 ? 1.0 : 0.0;
   if (bnorm == 0.0) {
     fill<double>(s, x, n, 0.0);  // b = 0: u = 0 whatever the start
