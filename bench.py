@@ -17,6 +17,8 @@ right-hand sides:
               from the finest level's degraded cells (--inherit 1)
   fp64        the same in FP64 throughout
   paper       mixed with the paper's per-level patches only (--inherit 0)
+  refined     (patch stress workload only) mixed with one FP64 refinement
+              step of every patch solve
   plain_fp64  plain Chebyshev smoother (no S_c, unadjusted lambda_max), FP64
   ref         global-local FP64 on the high-quality reference mesh (the same
               recipe without degraded cells): the iteration count to match
@@ -490,6 +492,13 @@ def main():
         res_paper = q
     else:
         res_paper = None
+    if args.workload == "cube_129_stress_p2" and not args.refine and "mixed" in arms:
+        # the patch stress configuration names FP64 refinement of the FP32
+        # patch solves: the mixed arm once more with it
+        rr = run_arm(meshes, degree, seeds=seeds, warmup=args.warmup, precision="mixed", local=True, timing=False,
+                     use_graph=not args.eager, label="global-local mixed, refined patch solves",
+                     **dict(common, refine=True))
+        extra["global_local_mixed_refined_patch_solves"] = _arm_summary(rr)
     if "plain" in arms:
         p = run_arm(meshes, degree, seeds=seeds[:args.warmup + max(1, args.steps // 2)], warmup=args.warmup,
                     precision="fp64", local=False, timing=False, label="plain fp64", **common)

@@ -1,9 +1,9 @@
 """Edge cases of the CG driver (single vector, blocks, many instances), with
 host launches and with the captured CG iteration: a right-hand side holding a
-NaN ends in MG_ERR_BREAKDOWN (the scalars' breakdown flag, seen by the host
-after the iteration) and leaves the context usable; in a batch the broken
-instance fails alone; maxit = 0 returns the start after 0 iterations with
-MG_NOT_CONVERGED; b = 0 returns u = 0 after 0 iterations."""
+NaN ends in MG_ERR_BREAKDOWN (so does the stationary solver) and leaves the
+context usable; in a batch the broken instance fails alone; maxit = 0
+returns the start after 0 iterations with MG_NOT_CONVERGED; b = 0 returns
+u = 0 after 0 iterations."""
 import functools
 
 import numpy as np
@@ -39,6 +39,9 @@ def test_nan_rhs_breaks_down_and_context_recovers(graph):
     with pytest.raises(MgError) as e:
         s.pcg_multi([to_dev(meshgen.random_rhs(n, 2)), to_dev(_nan_rhs(n, 3))],
                     [to_dev(np.zeros(n)), to_dev(np.zeros(n))], 1e-10, 100)
+    assert e.value.code == MG_ERR_BREAKDOWN
+    with pytest.raises(MgError) as e:
+        s.mg_solve(to_dev(_nan_rhs(n, 11)), to_dev(np.zeros(n)), 1e-8, 20)
     assert e.value.code == MG_ERR_BREAKDOWN
     # a valid solve afterwards: the same as on a fresh context
     b = to_dev(meshgen.random_rhs(n, 4))
