@@ -411,9 +411,10 @@ mg_status mg_get_array(const mg_ctx *c, int32_t level, int32_t what, void *out);
 
 /* Device-event timing of the solve phase: when enabled (and until disabled),
  * every launch of the full Chebyshev step kernel on each level, and every
- * coarsest solve (the product with the coarsest level's stored inverse), is
- * bracketed by HIP events on the context's stream, and the V-cycle runs
- * eagerly even when use_graph = 1.  mg_level_kernel_time returns, for one
+ * coarsest solve (the product with the coarsest level's stored inverse or
+ * the nested-dissection solve), is bracketed by HIP events on the context's
+ * stream, and the V-cycles and CG iterations run eagerly even when
+ * use_graph = 1.  mg_level_kernel_time returns, for one
  * level, the number of such launches since enabling and their summed
  * duration in milliseconds (level < coarsest: Chebyshev steps; level =
  * coarsest: coarsest solves); mg_kernel_time is its level-0 form.  Both
