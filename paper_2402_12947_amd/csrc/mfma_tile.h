@@ -19,8 +19,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // row-major matrix M: element (x, y) of the operand is M[r0 + x][c0 + y], or
 // M[r0 + y][c0 + x] when swap is set (zero outside the matrix).  For the A
 // operand lane l holds (x, y) = (16 blk + l % 16, 4 s + l / 16), for the B
-// operand (4 s + l / 16, 16 blk + l % 16); o[blk * 8 + s].
-template <bool ROLE_A, class T>
+// operand (4 s + l / 16, 16 blk + l % 16); o[blk * 8 + s].  I: the type of
+// the element offsets (int32_t where n^2 < 2^31: half the address registers).
+template <bool ROLE_A, class I = int64_t, class T>
 __device__ inline void fetch_ops(const T *M, int n, int r0, int c0, bool swap, T o[16], int lane) {
   const int p = lane & 15, q = lane >> 4;
 #pragma unroll
@@ -30,7 +31,7 @@ __device__ inline void fetch_ops(const T *M, int n, int r0, int c0, bool swap, T
       const int x = ROLE_A ? 16 * blk + p : 4 * s + q;
       const int y = ROLE_A ? 4 * s + q : 16 * blk + p;
       const int r = swap ? r0 + y : r0 + x, c = swap ? c0 + x : c0 + y;
-      o[blk * 8 + s] = (r < n && c < n) ? M[(int64_t)r * n + c] : (T)0;
+      o[blk * 8 + s] = (r < n && c < n) ? M[(I)r * n + c] : (T)0;
     }
 }
 

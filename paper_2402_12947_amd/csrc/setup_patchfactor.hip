@@ -63,13 +63,15 @@ __device__ inline void tri_rc(int t, int &i, int &j) {
 // row-major, FP64).  FP32 only: sc + ptr[patch] receives the equilibration
 // scales (n_d), weak[patch] = 1 marks a patch whose scaled pivots fell below
 // PIVOT_MIN_F32 (its inverse is not written).
+// Element offsets inside a patch are int32 (n_d <= MAX_PATCH, n_d^2 < 2^31),
+// which halves the address registers; the FP32 instantiation is held to 128
+// registers so that four wavefronts per SIMD (four patches per CU) hide the
+// latency of the operand loads.
 template <class T>
-__global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, const int32_t *col,
-                                                           const double *val, const int32_t *list,
-                                                           const int32_t *ptr, const int32_t *dofs,
-                                                           const int64_t *soff, T *scratch,
-                                                           const int64_t *ioff, double *inv, int *bad,
-                                                           double *sc, int *weak) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value ? 4 : 1)))
+void k_patch_factor_mfma(const int64_t *rp, const int32_t *col, const double *val, const int32_t *list,
+                         const int32_t *ptr, const int32_t *dofs, const int64_t *soff, T *scratch,
+                         const int64_t *ioff, double *inv, int *bad, double *sc, int *weak) {
   using acc_t = typename MfmaAcc<T>::type;
   constexpr bool F32 = std::is_same<T, float>::value;
   __shared__ PatchSmem<T> sm;
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
     for (int t = wave; t < rest; t += 4) {
       const int ib = kb + 1 + t;
       T a[16], b[16];
-      fetch_ops<true>(M, n, ib * PT, o, false, a, lane);
+      fetch_ops<true, int32_t>(M, n, ib * PT, o, false, a, lane);
 #pragma unroll
       for (int blk = 0; blk < 2; ++blk)
 #pragma unroll
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
       zero_acc(acc);
       mma_ops(acc, a, b);
       for_acc(acc, lane, [&](int i, int j, T v) {
-        if (ib * PT + i < n && o + j < n) M[(int64_t)(ib * PT + i) * n + o + j] = v;
+        if (ib * PT + i < n && o + j < n) M[(ib * PT + i) * n + o + j] = v;
       });
     }
     __syncthreads();
@@ -185,14 +187,14 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
       tri_rc(t, i, j);
       const int ib = kb + 1 + i, jb = kb + 1 + j;
       T a[16], b[16];
-      fetch_ops<true>(M, n, ib * PT, o, false, a, lane);
-      fetch_ops<false>(M, n, jb * PT, o, true, b, lane);
+      fetch_ops<true, int32_t>(M, n, ib * PT, o, false, a, lane);
+      fetch_ops<false, int32_t>(M, n, jb * PT, o, true, b, lane);
       acc_t acc[2][2];
       zero_acc(acc);
       mma_ops(acc, a, b);
       for_acc(acc, lane, [&](int r, int c, T v) {
         int gr = ib * PT + r, gc = jb * PT + c;
-        if (gr < n && gc < n) M[(int64_t)gr * n + gc] -= v;
+        if (gr < n && gc < n) M[gr * n + gc] -= v;
       });
     }
     __syncthreads();
@@ -203,14 +205,14 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
   for (int kb = 0; kb < nb; ++kb) {
     for (int jb = wave; jb < kb; jb += 4) {
       T a[16], b[16];
-      fetch_ops<true>(W, n, kb * PT, kb * PT, false, a, lane);
-      fetch_ops<false>(W, n, kb * PT, jb * PT, false, b, lane);
+      fetch_ops<true, int32_t>(W, n, kb * PT, kb * PT, false, a, lane);
+      fetch_ops<false, int32_t>(W, n, kb * PT, jb * PT, false, b, lane);
       acc_t acc[2][2];
       zero_acc(acc);
       mma_ops(acc, a, b);
       for_acc(acc, lane, [&](int r, int c, T v) {
         int gr = kb * PT + r, gc = jb * PT + c;
-        if (gr < n && gc < n) W[(int64_t)gr * n + gc] = v;
+        if (gr < n && gc < n) W[gr * n + gc] = v;
       });
     }
     __syncthreads();
@@ -218,14 +220,14 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
     for (int t = wave; t < nt; t += 4) {
       const int ib = kb + 1 + t / (kb + 1), jb = t % (kb + 1);
       T a[16], b[16];
-      fetch_ops<true>(M, n, ib * PT, kb * PT, false, a, lane);
-      fetch_ops<false>(W, n, kb * PT, jb * PT, false, b, lane);
+      fetch_ops<true, int32_t>(M, n, ib * PT, kb * PT, false, a, lane);
+      fetch_ops<false, int32_t>(W, n, kb * PT, jb * PT, false, b, lane);
       acc_t acc[2][2];
       zero_acc(acc);
       mma_ops(acc, a, b);
       for_acc(acc, lane, [&](int r, int c, T v) {
         int gr = ib * PT + r, gc = jb * PT + c;
-        if (gr < n && gc < n) W[(int64_t)gr * n + gc] -= v;
+        if (gr < n && gc < n) W[gr * n + gc] -= v;
       });
     }
     __syncthreads();
@@ -240,16 +242,16 @@ __global__ __launch_bounds__(256) void k_patch_factor_mfma(const int64_t *rp, co
     zero_acc(acc);
     for (int k = ib; k < nb; ++k) {
       T a[16], b[16];
-      fetch_ops<true>(W, n, k * PT, ib * PT, true, a, lane);
-      fetch_ops<false>(W, n, k * PT, jb * PT, false, b, lane);
+      fetch_ops<true, int32_t>(W, n, k * PT, ib * PT, true, a, lane);
+      fetch_ops<false, int32_t>(W, n, k * PT, jb * PT, false, b, lane);
       mma_ops(acc, a, b);
     }
     for_acc(acc, lane, [&](int r, int c, T v) {
       int gr = ib * PT + r, gc = jb * PT + c;
       if (gr < n && gc < n && (ib != jb || r >= c)) {  // diagonal tiles: lower half, mirrored
         const double x = F32 ? S[gr] * (double)v * S[gc] : (double)v;
-        X[(int64_t)gr * n + gc] = x;
-        X[(int64_t)gc * n + gr] = x;
+        X[gr * n + gc] = x;
+        X[gc * n + gr] = x;
       }
     });
   }
