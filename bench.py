@@ -203,7 +203,7 @@ def _rhs(n, seed):
     return meshgen.random_rhs(n, seed)
 
 
-def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", problem="poisson", budget_s=12.0):
+def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", problem="poisson", budget_s=12.0, inherit=0):
     import meshgen
     import oracle
     try:
@@ -214,7 +214,7 @@ def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", problem="p
     meshes = meshgen.hierarchy(recipe, seed=0, scale=scale)
     H = oracle.Hierarchy(meshes, tau=0.1, layers=layers,
                          opts=oracle.Options(degree=degree, patch_policy=oracle.OVERLAP if policy == "overlap"
-                                             else oracle.MERGE, problem=problem))
+                                             else oracle.MERGE, problem=problem, inherit_levels=inherit))
     n = H.levels[0].A.shape[0]
     solved, t0 = 0, time.perf_counter()
     its = []
@@ -229,8 +229,8 @@ def cpu_baseline(recipe, degree, layers, rtol, scale, policy="merge", problem="p
         ctx.unregister() if hasattr(ctx, "unregister") else None
     return {"value": n * solved / el, "unit": "DOF/s", "cores": 1, "kind": "oracle",
             "sample": f"{recipe} recipe at 1/{scale} size per side (P{degree}, {n} DOFs, "
-                      f"{len(meshes)} levels), {solved} full MG-PCG solves to rtol {rtol:g}, setup untimed, "
-                      f"iterations {its[0]}",
+                      f"{len(meshes)} levels, inherited patches on {inherit} level(s)), {solved} full MG-PCG "
+                      f"solves to rtol {rtol:g}, setup untimed, iterations {its[0]}",
             "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(),
             "host_affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
@@ -580,7 +580,8 @@ def main():
                                           "write": dst.numel() * 8}
     if not args.no_cpu_baseline:
         log("CPU baseline: the oracle, single-threaded, on the 1/8-size sample")
-        line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8, policy, problem)
+        line["cpu_baseline"] = cpu_baseline(recipe, degree, layers, rtol, scale * 8, policy, problem,
+                                            inherit=args.inherit)
     if args.workload == "cube_129_p2" and not args.no_batch:
         # the many-instance pattern in the same run: 32 cubes of uneven size,
         # 4 right-hand sides each, all solved together
