@@ -78,6 +78,25 @@ __device__ inline void for_acc(v4f acc[2][2], int lane, F f) {
       for (int e = 0; e < 4; ++e) f(16 * a + 4 * (lane >> 4) + e, 16 * b + (lane & 15), acc[a][b][e]);
 }
 
+// acc = the 32 x 32 tile M[r0 + i][c0 + j] of the n x n row-major matrix M
+// (zero outside it), in the accumulator layout of for_acc, so that a product
+// can accumulate onto it (C - A B as C + (-A) B: one round trip to memory
+// for the tile instead of a read after the products)
+__device__ inline int acc_row(const v4d *, int a, int lane, int e) { return 16 * a + (lane >> 4) + 4 * e; }
+__device__ inline int acc_row(const v4f *, int a, int lane, int e) { return 16 * a + 4 * (lane >> 4) + e; }
+template <class I = int64_t, class V, class T>
+__device__ inline void load_acc(V acc[2][2], const T *M, int n, int r0, int c0, int lane) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + acc_row(&acc[0][0], a, lane, e), c = c0 + 16 * b + (lane & 15);
+        acc[a][b][e] = (r < n && c < n) ? M[(I)r * n + c] : (T)0;
+      }
+}
+
 template <class T>
 struct MfmaAcc;
 template <>

@@ -12,7 +12,8 @@
 // Every tile product is a 32 x 32 x 32 product on the matrix cores, each
 // wavefront owning one output tile (2 x 2 blocks of 16 x 16), its operands
 // loaded straight from memory into the MFMA register layout (all 32 loads of
-// a tile in flight at once).  Tiles of one step are dealt to the four
+// a tile in flight at once); an update C - A B loads C into the accumulators
+// with the operands and accumulates (-A) B onto it, one round trip to memory.  Tiles of one step are dealt to the four
 // wavefronts, which run independently; steps are separated by workgroup
 // barriers.  Only the diagonal tile and its inverse live in LDS.  Patches are
 // launched largest first so the long ones start early (longest-processing-
@@ -64,11 +65,11 @@ __device__ inline void tri_rc(int t, int &i, int &j) {
 // scales (n_d), weak[patch] = 1 marks a patch whose scaled pivots fell below
 // PIVOT_MIN_F32 (its inverse is not written).
 // Element offsets inside a patch are int32 (n_d <= MAX_PATCH, n_d^2 < 2^31),
-// which halves the address registers; the FP32 instantiation is held to 128
-// registers so that four wavefronts per SIMD (four patches per CU) hide the
-// latency of the operand loads.
+// which halves the address registers; the FP32 instantiation is held to 168
+// registers, three wavefronts per SIMD (three patches per CU), the most that
+// fit without spilling once the updated tile is loaded with the operands.
 template <class T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value ? 4 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<T, float>::value ? 3 : 1)))
 void k_patch_factor_mfma(const int64_t *rp, const int32_t *col, const double *val, const int32_t *list,
                          const int32_t *ptr, const int32_t *dofs, const int64_t *soff, T *scratch,
                          const int64_t *ioff, double *inv, int *bad, double *sc, int *weak) {
@@ -180,21 +181,25 @@ void k_patch_factor_mfma(const int64_t *rp, const int32_t *col, const double *va
       });
     }
     __syncthreads();
-    // trailing lower triangle: M[ib, jb] -= M[ib, kb] M[jb, kb]^T
+    // trailing lower triangle: M[ib, jb] -= M[ib, kb] M[jb, kb]^T, the tile
+    // loaded into the accumulators with the operands and the product added
+    // with -M[ib, kb]
     const int ntr = rest * (rest + 1) / 2;
     for (int t = wave; t < ntr; t += 4) {
       int i = 0, j = 0;
       tri_rc(t, i, j);
       const int ib = kb + 1 + i, jb = kb + 1 + j;
       T a[16], b[16];
+      acc_t acc[2][2];
       fetch_ops<true, int32_t>(M, n, ib * PT, o, false, a, lane);
       fetch_ops<false, int32_t>(M, n, jb * PT, o, true, b, lane);
-      acc_t acc[2][2];
-      zero_acc(acc);
+      load_acc<int32_t>(acc, M, n, ib * PT, jb * PT, lane);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = -a[q];
       mma_ops(acc, a, b);
       for_acc(acc, lane, [&](int r, int c, T v) {
         int gr = ib * PT + r, gc = jb * PT + c;
-        if (gr < n && gc < n) M[gr * n + gc] -= v;
+        if (gr < n && gc < n) M[gr * n + gc] = v;
       });
     }
     __syncthreads();
@@ -220,14 +225,16 @@ void k_patch_factor_mfma(const int64_t *rp, const int32_t *col, const double *va
     for (int t = wave; t < nt; t += 4) {
       const int ib = kb + 1 + t / (kb + 1), jb = t % (kb + 1);
       T a[16], b[16];
+      acc_t acc[2][2];
       fetch_ops<true, int32_t>(M, n, ib * PT, kb * PT, false, a, lane);
       fetch_ops<false, int32_t>(W, n, kb * PT, jb * PT, false, b, lane);
-      acc_t acc[2][2];
-      zero_acc(acc);
+      load_acc<int32_t>(acc, W, n, ib * PT, jb * PT, lane);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = -a[q];
       mma_ops(acc, a, b);
       for_acc(acc, lane, [&](int r, int c, T v) {
         int gr = ib * PT + r, gc = jb * PT + c;
-        if (gr < n && gc < n) W[gr * n + gc] -= v;
+        if (gr < n && gc < n) W[gr * n + gc] = v;
       });
     }
     __syncthreads();
